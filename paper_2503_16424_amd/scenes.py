@@ -1,0 +1,274 @@
+"""Seeded synthetic curve scenes shared by the tests, the benchmark and the oracle runs.
+
+This module only draws random inputs and lays them out in the flat
+structure-of-arrays form that both the CPU oracle and the HIP library accept.
+It holds none of the rendering method's arithmetic: no Bernstein evaluation, no
+scales, no blending.  Everything is drawn with numpy's PCG64 generator
+(``numpy.random.default_rng(seed)``) in a fixed, documented order so that a
+scene is reproducible from its seed alone.
+
+Curve model (Sec. 3.2 of the paper, "Primitives of Bezier Splatting"):
+
+* an *open* curve (kind 0) is a stroke of ``S`` cubic segments sharing
+  endpoints, i.e. ``3S+1`` control points, with a stroke width and one or
+  ``S`` opacities (per-segment opacity, appendix on flexible attributes);
+* a *closed* curve (kind 1) is the paired structure of Sec. 3.3: two boundary
+  curves of ``S`` cubic segments that share their first and last control
+  point.  It is stored as the ``3S+1`` points of boundary A followed by the
+  ``3S-1`` interior points of boundary B (``6S`` points in total) and carries
+  ``R`` interpolated interior rows with a per-curve table ``tau`` of ``R+2``
+  interpolation weights (``tau[0]=0``, ``tau[R+1]=1``).
+
+All coordinates are in pixels, pixel ``(x, y)`` has its centre at
+``(x+0.5, y+0.5)``; colours and opacities are the activated values in [0, 1].
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+OPEN = 0
+CLOSED = 1
+
+
+@dataclass
+class Scene:
+    width: int
+    height: int
+    bg: np.ndarray              # float32[3]
+    kind: np.ndarray            # int32[n]
+    nseg: np.ndarray            # int32[n]   S
+    k_samples: np.ndarray       # int32[n]   K >= 2
+    r_interior: np.ndarray      # int32[n]   R (0 for open curves)
+    ctrl: np.ndarray            # float32[n_ctrl, 2]
+    ctrl_off: np.ndarray        # int32[n+1]
+    tau: np.ndarray             # float32[n_tau]
+    tau_off: np.ndarray         # int32[n+1] (R+2 entries per curve)
+    stroke_w: np.ndarray        # float32[n] (stroke width of open curves, px)
+    color: np.ndarray           # float32[n, 3]
+    opacity: np.ndarray         # float32[n_opa]
+    opa_off: np.ndarray         # int32[n+1] (1 or S entries per curve)
+    rank: np.ndarray            # int32[n] draw order, 0 = front
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_curves(self) -> int:
+        return int(self.kind.shape[0])
+
+    def rows(self) -> np.ndarray:
+        """Rows of sample points per curve: 1 for open, R+2 for closed."""
+        return np.where(self.kind == CLOSED, self.r_interior + 2, 1).astype(np.int64)
+
+    def n_gauss_per_curve(self) -> np.ndarray:
+        return self.rows() * self.k_samples.astype(np.int64)
+
+    @property
+    def n_gauss(self) -> int:
+        return int(self.n_gauss_per_curve().sum())
+
+    def arrays(self) -> dict:
+        return {k: getattr(self, k) for k in (
+            "bg", "kind", "nseg", "k_samples", "r_interior", "ctrl", "ctrl_off", "tau",
+            "tau_off", "stroke_w", "color", "opacity", "opa_off", "rank")}
+
+    def copy(self) -> "Scene":
+        a = {k: np.array(v, copy=True) for k, v in self.arrays().items()}
+        return Scene(width=self.width, height=self.height, name=self.name,
+                     meta=dict(self.meta), **a)
+
+
+def cdf_tau(R: int) -> np.ndarray:
+    """Interpolation weights of the R interior rows of a closed curve.
+
+    The paper draws them from an unnamed normalised CDF that must place rows
+    more densely near the two boundaries (Sec. 3.3).  The reading used here is
+    the standard normal CDF on [-2, 2], renormalised to [0, 1], evaluated at
+    R+2 equally spaced abscissae; this is an *input* table, swappable by the
+    caller.
+    """
+    z = -2.0 + 4.0 * np.arange(R + 2) / (R + 1)
+    phi = lambda v: 0.5 * (1.0 + math.erf(v / math.sqrt(2.0)))
+    lo, hi = phi(-2.0), phi(2.0)
+    t = np.array([(phi(v) - lo) / (hi - lo) for v in z], dtype=np.float64)
+    t[0], t[-1] = 0.0, 1.0
+    return t.astype(np.float32)
+
+
+def _assemble(width, height, kinds, nsegs, ks, rs, ctrl_list, widths, colors,
+              opa_list, rank, bg=(1.0, 1.0, 1.0), tau_list=None, name="", meta=None) -> Scene:
+    n = len(kinds)
+    ctrl_off = np.zeros(n + 1, np.int32)
+    opa_off = np.zeros(n + 1, np.int32)
+    tau_off = np.zeros(n + 1, np.int32)
+    taus = []
+    for i in range(n):
+        ctrl_off[i + 1] = ctrl_off[i] + len(ctrl_list[i])
+        opa_off[i + 1] = opa_off[i] + len(opa_list[i])
+        tb = tau_list[i] if tau_list is not None else cdf_tau(int(rs[i]))
+        taus.append(np.asarray(tb, np.float32))
+        tau_off[i + 1] = tau_off[i] + len(tb)
+    ctrl = (np.concatenate([np.asarray(c, np.float32).reshape(-1, 2) for c in ctrl_list])
+            if n else np.zeros((0, 2), np.float32))
+    opacity = (np.concatenate([np.asarray(o, np.float32).reshape(-1) for o in opa_list])
+               if n else np.zeros(0, np.float32))
+    tau = np.concatenate(taus) if n else np.zeros(0, np.float32)
+    return Scene(
+        width=int(width), height=int(height), bg=np.asarray(bg, np.float32),
+        kind=np.asarray(kinds, np.int32), nseg=np.asarray(nsegs, np.int32),
+        k_samples=np.asarray(ks, np.int32), r_interior=np.asarray(rs, np.int32),
+        ctrl=np.ascontiguousarray(ctrl, np.float32), ctrl_off=ctrl_off,
+        tau=np.ascontiguousarray(tau, np.float32), tau_off=tau_off,
+        stroke_w=np.asarray(widths, np.float32).reshape(n),
+        color=np.asarray(colors, np.float32).reshape(n, 3),
+        opacity=np.ascontiguousarray(opacity, np.float32), opa_off=opa_off,
+        rank=np.asarray(rank, np.int32), name=name, meta=meta or {})
+
+
+def uniform_open(seed: int, W: int, H: int, n: int, K: int, S: int = 1,
+                 per_segment_opacity: bool = False, name: str = "") -> Scene:
+    """Open strokes with every control point uniform over the canvas.
+
+    Draw order of the generator: control points, widths, colours, opacities.
+    Widths U[1,4] px, colours U[0,1]^3, opacities U[0.3,1]; identity draw order.
+    """
+    rng = np.random.default_rng(seed)
+    npts = 3 * S + 1
+    ctrl = rng.uniform(0.0, 1.0, (n, npts, 2)) * np.array([W, H], np.float64)
+    widths = rng.uniform(1.0, 4.0, n)
+    colors = rng.uniform(0.0, 1.0, (n, 3))
+    n_opa = S if per_segment_opacity else 1
+    opas = rng.uniform(0.3, 1.0, (n, n_opa))
+    return _assemble(W, H, [OPEN] * n, [S] * n, [K] * n, [0] * n, list(ctrl), widths,
+                     colors, list(opas), np.arange(n), name=name)
+
+
+def mixed(seed: int, W: int, H: int, n_closed: int, n_open: int, K: int = 24, R: int = 20,
+          S_open: int = 3, S_closed: int = 1, extent=(4.0, 400.0), per_segment_opacity=True,
+          permute=True, name: str = "") -> Scene:
+    """Closed lenses and open strokes scattered over the canvas.
+
+    Per curve: centre U[0,W)xU[0,H), linear extent L log-uniform in ``extent``.
+    Closed (drawn first, all closed curves): chord endpoints centre +- (L/2)(cos f, sin f)
+    with f ~ U[0,pi); the inner control points of boundary A sit on the chord at
+    equal spacing offset by +h_A along the chord normal, those of boundary B by
+    -h_B, with h ~ U[0.15,0.5]*L each, giving convex lenses.  Open: every
+    control point is centre + L*U[-1/2,1/2]^2.  Then widths U[1,4] (open),
+    colours U[0,1]^3, opacities U[0.3,1] (one per curve, or one per segment for
+    open curves when ``per_segment_opacity``), and finally a random draw-order
+    permutation when ``permute``.
+    """
+    rng = np.random.default_rng(seed)
+    n = n_closed + n_open
+    lo, hi = math.log(extent[0]), math.log(extent[1])
+    centre = rng.uniform(0.0, 1.0, (n, 2)) * np.array([W, H], np.float64)
+    L = np.exp(rng.uniform(lo, hi, n))
+    ctrl_list, kinds, nsegs, rs = [], [], [], []
+    # closed lenses
+    phi = rng.uniform(0.0, math.pi, n_closed)
+    hA = rng.uniform(0.15, 0.5, n_closed) * L[:n_closed]
+    hB = rng.uniform(0.15, 0.5, n_closed) * L[:n_closed]
+    for i in range(n_closed):
+        e = np.array([math.cos(phi[i]), math.sin(phi[i])])
+        nrm = np.array([-e[1], e[0]])
+        p0 = centre[i] - 0.5 * L[i] * e
+        p3 = centre[i] + 0.5 * L[i] * e
+        m = 3 * S_closed
+        along = [p0 + (j / m) * (p3 - p0) for j in range(m + 1)]
+        A = [along[0]] + [along[j] + hA[i] * nrm for j in range(1, m)] + [along[m]]
+        B = [along[j] - hB[i] * nrm for j in range(1, m)]
+        ctrl_list.append(np.array(A + B))
+        kinds.append(CLOSED)
+        nsegs.append(S_closed)
+        rs.append(R)
+    # open strokes
+    m = 3 * S_open + 1
+    off = rng.uniform(-0.5, 0.5, (n_open, m, 2))
+    for j in range(n_open):
+        i = n_closed + j
+        ctrl_list.append(centre[i] + L[i] * off[j])
+        kinds.append(OPEN)
+        nsegs.append(S_open)
+        rs.append(0)
+    widths = rng.uniform(1.0, 4.0, n)
+    widths[:n_closed] = 0.0
+    colors = rng.uniform(0.0, 1.0, (n, 3))
+    opa_list = []
+    for i in range(n):
+        k = nsegs[i] if (kinds[i] == OPEN and per_segment_opacity) else 1
+        opa_list.append(rng.uniform(0.3, 1.0, k))
+    rank = rng.permutation(n) if permute else np.arange(n)
+    return _assemble(W, H, kinds, nsegs, [K] * n, rs, ctrl_list, widths, colors,
+                     opa_list, rank, name=name)
+
+
+def target_noise(seed: int, W: int, H: int) -> np.ndarray:
+    """Uniform-noise target image, planar [3][H][W] float32."""
+    return np.random.default_rng(seed).uniform(0.0, 1.0, (3, H, W)).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads.  Sizes follow the paper's experiments (2K frames, thousands
+# of curves, K Gaussians per row, R = 20 interior rows for closed curves).
+# ---------------------------------------------------------------------------
+
+def tiny_128(seed: int = 0) -> Scene:
+    """128x128 canvas, 256 open single-segment curves x 16 samples (4,096 Gaussians).
+
+    Draw order: control points U[0,128)^2, widths, colours, opacities; the
+    uniform-noise target is drawn afterwards from the same generator by
+    :func:`tiny_128_target`.
+    """
+    return uniform_open(seed, 128, 128, 256, 16, S=1, name="open-128x128-256c-K16")
+
+
+def tiny_128_target(seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    n, npts = 256, 4
+    rng.uniform(0.0, 1.0, (n, npts, 2))
+    rng.uniform(1.0, 4.0, n)
+    rng.uniform(0.0, 1.0, (n, 3))
+    rng.uniform(0.3, 1.0, (n, 1))
+    return rng.uniform(0.0, 1.0, (3, 128, 128)).astype(np.float32)
+
+
+def open_512(seed: int = 0) -> Scene:
+    """512x512 canvas, 2,048 open single-segment curves x 32 samples (65,536 Gaussians)."""
+    return uniform_open(seed, 512, 512, 2048, 32, S=1, name="open-512x512-2048c-K32")
+
+
+def hidden_512(seed: int = 1) -> Scene:
+    """The 4,096-curve hidden scene whose render is the 512x512 optimisation target."""
+    return uniform_open(seed, 512, 512, 4096, 32, S=1, name="hidden-512x512-4096c-K32")
+
+
+def paper_2048(seed: int = 0) -> Scene:
+    """2048x2048, 20,000 curves: 12,000 closed (R=20, K=24) + 8,000 open (S=3, K=24).
+
+    6,528,000 Gaussians; extents log-uniform over 4..400 px; seeded draw order.
+    """
+    return mixed(seed, 2048, 2048, 12000, 8000, K=24, R=20, S_open=3, S_closed=1,
+                 extent=(4.0, 400.0), name="mixed-2048x2048-20k-R20-K24")
+
+
+def paper_analog(seed: int = 0, closed: bool = False) -> Scene:
+    """2040x1344 frame with 2,048 curves (the size of the paper's speed comparison)."""
+    if closed:
+        return mixed(seed, 2040, 1344, 2048, 0, K=24, R=20, name="closed-2040x1344-2048c")
+    return mixed(seed, 2040, 1344, 0, 2048, K=24, S_open=3, name="open-2040x1344-2048c")
+
+
+def small_mixed(seed: int, W: int = 48, H: int = 40, n_closed: int = 3, n_open: int = 4,
+                K: int = 8, R: int = 3, extent=(6.0, 30.0)) -> Scene:
+    """Small mixed scenes for finite-difference and parity tests."""
+    return mixed(seed, W, H, n_closed, n_open, K=K, R=R, S_open=3, S_closed=1,
+                 extent=extent, name=f"small-mixed-{W}x{H}-s{seed}")
+
+
+WORKLOADS = {
+    "tiny_128": tiny_128,
+    "open_512": open_512,
+    "paper_2048": paper_2048,
+}

@@ -1,0 +1,80 @@
+"""Test helpers that are independent of both the oracle and the HIP library."""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+from paper_2503_16424_amd import scenes
+
+
+def de_casteljau(P, t):
+    """Point on a Bezier curve by repeated linear interpolation (de Casteljau)."""
+    pts = [np.asarray(p, dtype=np.float64) for p in P]
+    while len(pts) > 1:
+        pts = [(1.0 - t) * a + t * b for a, b in zip(pts[:-1], pts[1:])]
+    return pts[0]
+
+
+def composite_point(P, S, k, K):
+    """Point at global parameter u = k/(K-1) on an S-segment composite cubic.
+
+    The segment is chosen with exact rational arithmetic; a parameter that
+    lands exactly on a joint belongs to the later segment (both give the same
+    point by continuity)."""
+    u = Fraction(k, K - 1)
+    s = min(int(u * S), S - 1)
+    t = float(u * S - s)
+    return de_casteljau(P[3 * s:3 * s + 4], t), s
+
+
+def closed_boundaries(ctrl, S):
+    """Boundary A (3S+1 points) and B (A's endpoints around the 3S-1 stored
+    interior points) of a closed curve's control points."""
+    m = 3 * S
+    A = np.asarray(ctrl[:m + 1], np.float64)
+    B = np.concatenate([A[:1], np.asarray(ctrl[m + 1:], np.float64), A[m:]])
+    return A, B
+
+
+def gauss_set(mu, conic, opac, color):
+    return dict(mu=np.asarray(mu, np.float64).reshape(-1, 2),
+                conic=np.asarray(conic, np.float64).reshape(-1, 3),
+                opac=np.asarray(opac, np.float64).reshape(-1),
+                color=np.asarray(color, np.float64).reshape(-1, 3))
+
+
+def scene_from_curves(W, H, curves, bg=(1.0, 1.0, 1.0), rank=None):
+    """curves: list of dicts(kind, S, K, R, ctrl, width, color, opacity[, tau])."""
+    n = len(curves)
+    taus = [c.get("tau", scenes.cdf_tau(c.get("R", 0))) for c in curves]
+    sc = scenes._assemble(W, H, [c["kind"] for c in curves], [c["S"] for c in curves],
+                          [c["K"] for c in curves], [c.get("R", 0) for c in curves],
+                          [np.asarray(c["ctrl"], np.float64) for c in curves],
+                          [c.get("width", 0.0) for c in curves], [c["color"] for c in curves],
+                          [np.atleast_1d(c["opacity"]) for c in curves],
+                          np.arange(n) if rank is None else rank, bg=bg, tau_list=taus)
+    sc = to_f64(sc)
+    # keep the exact float64 inputs (the assembler stores float32)
+    sc.ctrl = np.concatenate([np.asarray(c["ctrl"], np.float64).reshape(-1, 2) for c in curves])
+    sc.tau = np.concatenate([np.asarray(t, np.float64) for t in taus])
+    sc.stroke_w = np.array([c.get("width", 0.0) for c in curves], np.float64)
+    sc.color = np.array([c["color"] for c in curves], np.float64).reshape(n, 3)
+    sc.opacity = np.concatenate([np.atleast_1d(np.asarray(c["opacity"], np.float64))
+                                 for c in curves])
+    return sc
+
+
+def to_f64(sc):
+    """Float64 copies of the float inputs (so finite differences can perturb them)."""
+    sc = sc.copy()
+    for k in ("ctrl", "tau", "stroke_w", "color", "opacity", "bg"):
+        setattr(sc, k, np.asarray(getattr(sc, k), np.float64))
+    return sc
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)

@@ -1,0 +1,205 @@
+"""Throughput of the differentiable rasterizer on one MI355X.
+
+One step = bz_sample + bz_bin + bz_render_fwd + L2 gradient + bz_render_bwd
+(both stages) over a fixed synthetic scene already resident in HBM.  Default
+workload: 2048x2048 canvas, 20,000 curves (12,000 closed with R = 20 interior
+rows and 8,000 open 3-segment strokes, 24 samples per row), 6,528,000
+Gaussians, seeded draw order, uniform-noise target.
+
+Prints one JSON line (see the README for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd steps/s at 2048², 20k curves; steps-to-PSNR learned vs plain init"
+
+# Algorithmic work per contributing (pixel, Gaussian) pair, in FP32 flops with
+# an FMA counted as 2, derived from the blending recurrence:
+#   forward : offset d (4), p = 1/2 d^T Q d (7), exp (1), support test (1),
+#             alpha = min(alpha_max, o'(G - g_min)) (3), w = alpha T (1),
+#             C += w c (6), T *= 1 - alpha (2)                            = 25
+#   backward: offset (4), p (7), exp (1), test (1), alpha + clamp (4),
+#             T before = T / (1 - alpha) (3), w (1), colour grads (3),
+#             alpha grad T sum (c - A) g (9), A update (9), opacity grad (3),
+#             p grad (3), d and d d^T moments (5)                          = 53
+FLOPS_FWD_PAIR = 25
+FLOPS_BWD_PAIR = 53
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, plain
+# (non-packed) FP32 VALU: the build disables packed FP32 instructions.
+PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+BYTES_REC = 48
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper_2048", choices=["paper_2048", "open_512",
+                                                                 "tiny_128"])
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=128,
+                    help="rows of the frame the CPU oracle renders for its baseline")
+    return ap.parse_args()
+
+
+def cpu_baseline(sc, target, rows):
+    """Time the FP64 oracle on a band of rows of the same workload and scale
+    to one full step (sampling and the per-curve chain are timed whole)."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    H, W = sc.height, sc.width
+    y0 = H // 2 - rows // 2
+    y1 = y0 + rows
+    t0 = time.perf_counter()
+    g = oracle.sample(sc)
+    t1 = time.perf_counter()
+    fw = oracle.render(g, W, H, sc.bg, rows=(y0, y1))
+    d = np.zeros((3, H, W))
+    d[:, y0:y1] = 2.0 * (fw["image"][:, y0:y1] - target[:, y0:y1]) / (3.0 * H * W)
+    t2 = time.perf_counter()
+    bw = oracle.render(g, W, H, sc.bg, rows=(y0, y1), d_image=d)
+    t3 = time.perf_counter()
+    oracle.chain(sc, bw["d_gauss"])
+    t4 = time.perf_counter()
+    band = t3 - t2                  # the backward call re-runs the band's forward itself
+    step = (t1 - t0) + band * (H / rows) + (t4 - t3)
+    return dict(value=1.0 / step, unit="steps/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"FP64 oracle: full sampling ({t1 - t0:.2f} s) and per-curve chain "
+                        f"({t4 - t3:.2f} s); forward+backward of rows {y0}..{y1 - 1} "
+                        f"({rows} of {H}, {t3 - t2:.2f} s) scaled by {H / rows:.0f}; "
+                        f"host {platform.processor() or platform.machine()}"),
+                seconds=t4 - t0)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_2503_16424_amd import bz, scenes
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tw, th = (int(v) for v in a.tile.split("x"))
+    if a.workload == "paper_2048":
+        sc, target = scenes.paper_2048(0), scenes.target_noise(1, 2048, 2048)
+    elif a.workload == "open_512":
+        sc, target = scenes.open_512(0), scenes.target_noise(1, 512, 512)
+    else:
+        sc, target = scenes.tiny_128(0), scenes.tiny_128_target(0)
+    print(f"# workload {sc.name}: {sc.n_curves} curves, {sc.n_gauss} Gaussians", file=sys.stderr,
+          flush=True)
+    r = bz.Rasterizer(sc, bz.RenderOptions(tile_w=tw, tile_h=th), device="cuda:0")
+    tgt = torch.as_tensor(target, device=dev)
+    r.render()                                    # sizes the pair buffer (synchronises)
+    need = r.pairs_required()
+    if need * 1.1 > r.cap_pairs:
+        r._alloc_pairs(int(need * 1.1) + 1024)
+    for _ in range(a.warmup):
+        r.step(tgt)
+    torch.cuda.synchronize()
+    print(f"# warmup done, {need} pairs", file=sys.stderr, flush=True)
+
+    stages = ["sample", "bin", "fwd", "l2", "bwd"]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+          for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        e = ev[i]
+        e[0].record()
+        r.sample()
+        e[1].record()
+        r.bin()
+        e[2].record()
+        r.forward()
+        e[3].record()
+        r.l2_grad(tgt)
+        e[4].record()
+        r.backward()
+        e[5].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = sum(ev[i][0].elapsed_time(ev[i][-1]) for i in range(a.steps)) / a.steps
+    stage_ms = {s: sum(ev[i][j].elapsed_time(ev[i][j + 1]) for i in range(a.steps)) / a.steps
+                for j, s in enumerate(stages)}
+    ms_per_step = wall * 1000.0 / a.steps
+    flags = r.flags()
+    if flags & bz.STATUS_OVERFLOW:
+        raise RuntimeError("pair buffer overflowed during the timed steps")
+    n_alg = int(r.n_contrib.to(torch.int64).sum().item())
+    loss = float(r.loss.item()) / (3 * sc.width * sc.height)
+    print(f"# {a.steps} steps: {ms_per_step:.3f} ms/step wall, {gpu_ms:.3f} ms/step events; "
+          f"stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}; "
+          f"contributing pairs {n_alg}; mse {loss:.5f}", file=sys.stderr, flush=True)
+
+    # Roofline of the dominant stage's kernel.
+    dom = max(("fwd", "bwd", "bin", "sample"), key=lambda s: stage_ms[s])
+    if dom == "fwd":
+        ach = n_alg * FLOPS_FWD_PAIR / (stage_ms["fwd"] * 1e-3) / 1e12
+        roof = dict(kernel="k_fwd (bz_render_fwd)", bound="alu", achieved=ach,
+                    peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
+    elif dom == "bwd":
+        ach = n_alg * FLOPS_BWD_PAIR / (stage_ms["bwd"] * 1e-3) / 1e12
+        roof = dict(kernel="bz_render_bwd (k_bwd_tiles + k_bwd_curves)", bound="alu",
+                    achieved=ach, peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
+    elif dom == "bin":
+        byts = sc.n_gauss * 28 + need * 4 + r.n_tiles * 8
+        ach = byts / (stage_ms["bin"] * 1e-3) / 1e9
+        roof = dict(kernel="bz_bin", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s")
+    else:
+        byts = sc.n_gauss * BYTES_REC
+        ach = byts / (stage_ms["sample"] * 1e-3) / 1e9
+        roof = dict(kernel="k_sample", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_per_step,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "canvas": [sc.width, sc.height],
+                   "curves": sc.n_curves, "gaussians": sc.n_gauss, "seed": 0,
+                   "tile": [tw, th], "parallelism": "single GPU"},
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "pairs": {"tile_pairs": need, "contributing": n_alg},
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc, target.astype(np.float64), a.cpu_rows)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,224 @@
+/*
+ * bz.h -- C ABI of libbz, the MI355X (gfx950) rasterizer of Bezier Splatting
+ * ("Bezier Splatting for Fast and Differentiable Vector Graphics Rendering",
+ * arXiv 2503.16424).
+ *
+ * Problem statement (Sec. 3.5, "Training objective"): curves are laid on a
+ * canvas, rendered by a differentiable rasterizer into an image, and optimised
+ * through gradients of any image loss.  The library provides that rasterizer:
+ *
+ *   bz_sample      curves -> 2D Gaussians                    (Sec. 3.3)
+ *   bz_bin         Gaussians -> per-tile lists in draw order (Sec. 3.4, tile pipeline)
+ *   bz_render_fwd  per-tile front-to-back alpha blending     (Sec. 3.4, blending sum)
+ *   bz_render_bwd  reverse-order gradients to Gaussians, then to curve
+ *                  control points, widths, colours, opacities
+ *
+ * Conventions shared by every call:
+ *  - Pointers inside the structs and the image/gradient pointers are DEVICE
+ *    pointers owned by the caller; functions marked "host" take host pointers.
+ *    The library never allocates or frees memory and keeps no global state.
+ *  - Every device call is asynchronous and ordered on the caller's stream; no
+ *    call synchronises.  The return code reports argument errors (BZ_ERR_ARG,
+ *    BZ_ERR_UNSUPPORTED) detected on the host before anything is launched, and
+ *    launch errors (BZ_ERR_HIP).  Data-dependent failures (tile-list overflow,
+ *    non-finite Gaussians) are reported through the device status words of
+ *    bz_bins, never silently.
+ *  - Coordinates are pixels; pixel (x, y) has its centre at (x + 1/2, y + 1/2).
+ *    Images are planar float32 [3][height][width].
+ *  - Colours and opacities are activated values in [0, 1]; gradients are with
+ *    respect to exactly the values passed in.
+ *  - Calls on distinct buffers may run concurrently on different streams.
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BZ_OK = 0,
+    BZ_ERR_ARG = -1,          /* invalid argument (null pointer, bad size, bad option) */
+    BZ_ERR_CAPACITY = -2,     /* a host-known size exceeds a caller buffer */
+    BZ_ERR_HIP = -3,          /* kernel launch failed */
+    BZ_ERR_UNSUPPORTED = -4   /* valid but outside what this build handles */
+} bz_status;
+
+/* Kind of a curve (Sec. 3.2). */
+#define BZ_OPEN 0     /* stroke: S cubic segments, 3S+1 control points, a width */
+#define BZ_CLOSED 1   /* paired boundaries A, B sharing endpoints: 6S points, filled */
+
+/* Rendering options (host struct, passed by pointer, read during the call). */
+typedef struct {
+    int32_t width, height;   /* canvas in pixels, 1..32768 each */
+    float bg[3];             /* background colour composited with T_final */
+    float rho;               /* density constant of Eq. sigma (> 0); 2.0 */
+    float sigma0_sq;         /* isotropic screen dilation added to both squared
+                                scales, px^2 (>= 0); 0.3 */
+    float g_min;             /* kernel truncation: Gt = (G - g_min)_+/(1 - g_min),
+                                0 < g_min < 1; 1/255 */
+    float alpha_max;         /* alpha clamp, (0, 1]; 0.99 */
+    float t_min;             /* a pixel stops after the contributor that brings its
+                                transmittance below t_min, [0, 1); 1e-6 */
+    int32_t tile_w, tile_h;  /* binning tile: multiples of 8, product 64..1024.
+                                Results do not depend on the tile shape. */
+} bz_opts;
+
+/* Curve set, structure of arrays on the device.
+ *
+ *   kind[i], nseg[i] = S (1..4), k_samples[i] = K (2..1024), r_interior[i] = R
+ *   (0..254, closed only; ignored for open curves).
+ *   ctrl[ctrl_off[i] .. ctrl_off[i+1]) : float2 control points.  Open: 3S+1
+ *       points.  Closed: boundary A's 3S+1 points, then boundary B's 3S-1
+ *       interior points (B shares A's first and last point).
+ *   tau[tau_off[i] ..]: R+2 row interpolation weights of a closed curve,
+ *       tau[0] = 0 and tau[R+1] = 1 (Sec. 3.3, rows sampled from a normalised CDF).
+ *   stroke_w[i]  : stroke width of an open curve (sigma_y before dilation).
+ *   color[i][3]  : RGB.
+ *   opacity[opa_off[i] .. opa_off[i+1]) : 1 value, or S values (one per segment).
+ *   order[p]     : the curve drawn at position p (p = 0 in front); a permutation.
+ *   gauss_off[p] : first Gaussian of the curve drawn at position p; the curve has
+ *       K (open) or K*(R+2) (closed) Gaussians; gauss_off[n_curves] = n_gauss.
+ *   order and gauss_off are produced on the host by bz_layout_host.
+ *   max_gauss_per_curve: the largest per-curve Gaussian count (from bz_layout_host).
+ */
+typedef struct {
+    int32_t n_curves;
+    int64_t n_gauss;
+    int32_t max_gauss_per_curve;
+    int32_t max_k;
+    const int32_t *kind, *nseg, *k_samples, *r_interior;
+    const float *ctrl;
+    const int32_t *ctrl_off;
+    const float *tau;
+    const int32_t *tau_off;
+    const float *stroke_w;
+    const float *color;
+    const float *opacity;
+    const int32_t *opa_off;
+    const int32_t *order;
+    const int64_t *gauss_off;
+} bz_curves;
+
+/* Gaussians, one 48-byte record (12 floats) per Gaussian in draw order:
+ *   [0..1]  mean, high float part (x, y)
+ *   [2..3]  mean, low part: mean = hi + lo to ~2^-48 relative (the mean is
+ *           computed in double precision)
+ *   [4..6]  Q = Sigma^-1 as (Qxx, Qxy, Qyy); p = 1/2 d^T Q d, d = pixel - mean
+ *   [7]     opacity o
+ *   [8..10] colour
+ *   [11]    curve id (int32 bit pattern)
+ * rec must be 16-byte aligned and hold cap records; n is the number of valid
+ * records (set by bz_sample). */
+typedef struct {
+    int64_t cap;
+    int64_t n;
+    float *rec;
+} bz_gaussians;
+
+/* Tile lists.  ids[ranges[2t] .. ranges[2t+1]) are the Gaussians whose support
+ * may reach a pixel of tile t (row-major tiles), in increasing draw order.
+ * status (device, 4 x int64): [0] pairs required by the last bz_bin,
+ * [1] flags: bit 0 = ids capacity exceeded (the lists are then invalid and the
+ * render calls fill the image with NaN), bit 1 = non-finite Gaussian skipped.
+ * workspace: device scratch of bz_workspace_size bytes, 256-byte aligned. */
+typedef struct {
+    int64_t cap_pairs;       /* capacity of ids, < 2^32 */
+    uint32_t *ids;
+    uint32_t *ranges;        /* [n_tiles][2] */
+    void *workspace;
+    int64_t workspace_bytes;
+    int64_t *status;
+} bz_bins;
+
+/* Per-pixel forward state kept for the reverse pass ([height][width] each).
+ * n_last: number of list entries up to and including the pixel's last
+ * contributor.  n_contrib (optional, may be NULL): contributors per pixel. */
+typedef struct {
+    float *t_final;
+    uint32_t *n_last;
+    uint32_t *n_contrib;
+} bz_pixstate;
+
+/* Gradients.  Per curve, same layouts as the inputs: d_ctrl [n_ctrl][2],
+ * d_width [n_curves], d_color [n_curves][3], d_opacity [n_opa].  d_gauss is
+ * required scratch and output: per-Gaussian gradients as 9 planes of n_gauss
+ * floats: (mean x, mean y, Qxx, Qxy, Qyy, o, r, g, b).  bz_render_bwd overwrites
+ * all of them (the caller need not zero them). */
+typedef struct {
+    float *d_ctrl, *d_width, *d_color, *d_opacity;
+    float *d_gauss;
+} bz_grads;
+
+/* Host: validate a curve set's sizes and build order[] (inverse of rank,
+ * rank 0 = front) and gauss_off[] (n_curves + 1 entries).  All pointers are
+ * HOST pointers; ctrl_off, tau_off and opa_off have n_curves + 1 entries and
+ * are checked against kind/S/R (3S+1 or 6S points, at least R+2 weights, 1 or
+ * S opacities).  max_gauss and max_k (optional) receive the largest per-curve
+ * Gaussian count and K.  Draw order: depth is assigned per curve (Sec. 3.3),
+ * and inside a curve Gaussians follow row-major (r, k) order.
+ * Returns BZ_ERR_ARG on any inconsistency, BZ_ERR_UNSUPPORTED for S > 4,
+ * K > 1024, R > 254 or a curve whose Gaussians exceed the per-curve limit. */
+bz_status bz_layout_host(int32_t n_curves, const int32_t *kind, const int32_t *nseg,
+                         const int32_t *k_samples, const int32_t *r_interior,
+                         const int32_t *ctrl_off, const int32_t *tau_off,
+                         const int32_t *opa_off, const int32_t *rank, int32_t *order,
+                         int64_t *gauss_off, int32_t *max_gauss, int32_t *max_k);
+
+/* Host: bytes of workspace bz_bin needs for n_gauss Gaussians and cap_pairs pairs. */
+bz_status bz_workspace_size(const bz_opts *opts, int64_t n_gauss, int64_t cap_pairs,
+                            int64_t *bytes);
+
+/* Host: number of tiles of the canvas for the options' tile shape. */
+bz_status bz_num_tiles(const bz_opts *opts, int64_t *n_tiles);
+
+/* Sec. 3.3: sample K Gaussians per row along every curve (one row for open
+ * curves, R+2 rows for closed ones), scales from neighbour distances (Eq.
+ * sigma), orientation from the neighbour chord (Eq. rotation), covariance
+ * (Eq. RSSR) dilated by sigma0_sq, opacity per segment, colour per curve.
+ * Writes g->rec[0 .. c->n_gauss) and sets g->n = c->n_gauss (host field);
+ * requires g->cap >= c->n_gauss. */
+bz_status bz_sample(const bz_curves *c, const bz_opts *opts, bz_gaussians *g,
+                    hipStream_t stream);
+
+/* Sec. 3.4 tile pipeline: bound each Gaussian's truncated support
+ * (1/2 d^T Q d <= -ln g_min), list it in every tile the bound touches, sort
+ * the (tile, Gaussian) pairs by tile keeping draw order, and write per-tile
+ * ranges.  Uses b->workspace; reports through b->status. */
+bz_status bz_bin(const bz_gaussians *g, const bz_opts *opts, bz_bins *b, hipStream_t stream);
+
+/* Sec. 3.4 blending: per pixel, front to back over its tile's list,
+ * alpha = min(alpha_max, o (G - g_min)_+/(1 - g_min)) with
+ * G = exp(-1/2 d^T Q d) (Eq. rasterization2), C += alpha T c, T *= 1 - alpha,
+ * stop after T < t_min, then C += T bg.  image: [3][H][W]; state: per-pixel
+ * t_final, n_last (and optionally n_contrib) for bz_render_bwd. */
+bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *opts,
+                        float *image, bz_pixstate *state, hipStream_t stream);
+
+/* Reverse pass.  Stage 1, per pixel, walks the contributors of the forward
+ * pass last to first, recovering T before each one by division by (1 - alpha)
+ * and carrying the colour composited behind it, and accumulates per-Gaussian
+ * gradients into grads->d_gauss.  Stage 2, per curve, chains them through the
+ * sampling of Sec. 3.3 to control points, widths, colours and opacities.
+ * d_image: dL/dimage, [3][H][W].  c, g, b, opts and state must be those of the
+ * forward pass. */
+bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins *b,
+                        const bz_opts *opts, const float *d_image, const bz_pixstate *state,
+                        bz_grads *grads, hipStream_t stream);
+
+/* Mean squared error loss of Sec. 3.5 (the L2 term): d_image = scale*(image - target)
+ * elementwise over n floats, and loss[0] = sum (image - target)^2 accumulated
+ * (loss is zeroed by the call; may be NULL). */
+bz_status bz_l2_grad(const float *image, const float *target, int64_t n, float scale,
+                     float *d_image, float *loss, hipStream_t stream);
+
+/* Short description of a status code (static string). */
+const char *bz_status_str(bz_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BZ_H */

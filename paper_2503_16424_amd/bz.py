@@ -1,0 +1,337 @@
+"""Thin Python binding of libbz (include/bz.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream, every step of the rasterizer runs in libbz's HIP kernels.  The
+binding raises if libbz.so is missing or if no GPU is present; there is no
+CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbz.so")
+
+BZ_OK, BZ_ERR_ARG, BZ_ERR_CAPACITY, BZ_ERR_HIP, BZ_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_OVERFLOW = 1
+STATUS_NONFINITE = 2
+
+
+class Opts(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bg", C.c_float * 3),
+                ("rho", C.c_float), ("sigma0_sq", C.c_float), ("g_min", C.c_float),
+                ("alpha_max", C.c_float), ("t_min", C.c_float), ("tile_w", C.c_int32),
+                ("tile_h", C.c_int32)]
+
+
+class Curves(C.Structure):
+    _fields_ = [("n_curves", C.c_int32), ("n_gauss", C.c_int64),
+                ("max_gauss_per_curve", C.c_int32), ("max_k", C.c_int32),
+                ("kind", C.c_void_p), ("nseg", C.c_void_p), ("k_samples", C.c_void_p),
+                ("r_interior", C.c_void_p), ("ctrl", C.c_void_p), ("ctrl_off", C.c_void_p),
+                ("tau", C.c_void_p), ("tau_off", C.c_void_p), ("stroke_w", C.c_void_p),
+                ("color", C.c_void_p), ("opacity", C.c_void_p), ("opa_off", C.c_void_p),
+                ("order", C.c_void_p), ("gauss_off", C.c_void_p)]
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("n", C.c_int64), ("rec", C.c_void_p)]
+
+
+class Bins(C.Structure):
+    _fields_ = [("cap_pairs", C.c_int64), ("ids", C.c_void_p), ("ranges", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
+                ("status", C.c_void_p)]
+
+
+class PixState(C.Structure):
+    _fields_ = [("t_final", C.c_void_p), ("n_last", C.c_void_p), ("n_contrib", C.c_void_p)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("d_ctrl", C.c_void_p), ("d_width", C.c_void_p), ("d_color", C.c_void_p),
+                ("d_opacity", C.c_void_p), ("d_gauss", C.c_void_p)]
+
+
+EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_sample", "bz_bin",
+           "bz_render_fwd", "bz_render_bwd", "bz_l2_grad", "bz_status_str")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libbz.so not found at {path}; build it with "
+                           "`python -m paper_2503_16424_amd.build`")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    lib.bz_status_str.restype = C.c_char_p
+    lib.bz_status_str.argtypes = [C.c_int]
+    lib.bz_layout_host.restype = C.c_int
+    lib.bz_layout_host.argtypes = [C.c_int32] + [C.c_void_p] * 10 + [P(C.c_int32), P(C.c_int32)]
+    lib.bz_workspace_size.restype = C.c_int
+    lib.bz_workspace_size.argtypes = [P(Opts), C.c_int64, C.c_int64, P(C.c_int64)]
+    lib.bz_num_tiles.restype = C.c_int
+    lib.bz_num_tiles.argtypes = [P(Opts), P(C.c_int64)]
+    lib.bz_sample.restype = C.c_int
+    lib.bz_sample.argtypes = [P(Curves), P(Opts), P(Gaussians), C.c_void_p]
+    lib.bz_bin.restype = C.c_int
+    lib.bz_bin.argtypes = [P(Gaussians), P(Opts), P(Bins), C.c_void_p]
+    lib.bz_render_fwd.restype = C.c_int
+    lib.bz_render_fwd.argtypes = [P(Gaussians), P(Bins), P(Opts), C.c_void_p, P(PixState),
+                                  C.c_void_p]
+    lib.bz_render_bwd.restype = C.c_int
+    lib.bz_render_bwd.argtypes = [P(Curves), P(Gaussians), P(Bins), P(Opts), C.c_void_p,
+                                  P(PixState), P(Grads), C.c_void_p]
+    lib.bz_l2_grad.restype = C.c_int
+    lib.bz_l2_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p,
+                               C.c_void_p, C.c_void_p]
+    _lib = lib
+    return lib
+
+
+class BzError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        msg = load_library().bz_status_str(code).decode()
+        super().__init__(f"{fn} failed: {msg} ({code})")
+        self.code = code
+
+
+def _check(fn, code):
+    if code != BZ_OK:
+        raise BzError(fn, code)
+
+
+@dataclass
+class RenderOptions:
+    rho: float = 2.0
+    sigma0_sq: float = 0.3
+    g_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-6
+    tile_w: int = 16
+    tile_h: int = 16
+
+    def as_dict(self):
+        return dict(rho=self.rho, sigma0_sq=self.sigma0_sq, g_min=self.g_min,
+                    alpha_max=self.alpha_max, t_min=self.t_min)
+
+
+def make_opts(width, height, bg, ro: RenderOptions) -> Opts:
+    o = Opts()
+    o.width, o.height = int(width), int(height)
+    for i in range(3):
+        o.bg[i] = float(bg[i])
+    o.rho, o.sigma0_sq, o.g_min = ro.rho, ro.sigma0_sq, ro.g_min
+    o.alpha_max, o.t_min = ro.alpha_max, ro.t_min
+    o.tile_w, o.tile_h = int(ro.tile_w), int(ro.tile_h)
+    return o
+
+
+def layout_host(scene):
+    """order / gauss_off / max sizes of a scene (host call into libbz)."""
+    lib = load_library()
+    n = scene.n_curves
+    a = {k: np.ascontiguousarray(getattr(scene, k), np.int32)
+         for k in ("kind", "nseg", "k_samples", "r_interior", "ctrl_off", "tau_off", "opa_off",
+                   "rank")}
+    order = np.zeros(max(n, 1), np.int32)
+    goff = np.zeros(n + 1, np.int64)
+    mg, mk = C.c_int32(0), C.c_int32(0)
+    p = lambda x: x.ctypes.data_as(C.c_void_p)
+    st = lib.bz_layout_host(n, p(a["kind"]), p(a["nseg"]), p(a["k_samples"]),
+                            p(a["r_interior"]), p(a["ctrl_off"]), p(a["tau_off"]),
+                            p(a["opa_off"]), p(a["rank"]), p(order), p(goff), C.byref(mg),
+                            C.byref(mk))
+    _check("bz_layout_host", st)
+    return order[:n], goff, int(mg.value), int(mk.value)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+class Rasterizer:
+    """Device buffers of one scene and the four library calls on them.
+
+    Curve parameters live in float32 device tensors (``ctrl``, ``stroke_w``,
+    ``color``, ``opacity``) that an optimiser may update in place; gradients
+    land in ``d_ctrl``, ``d_width``, ``d_color``, ``d_opacity`` after
+    :meth:`backward`.
+    """
+
+    def __init__(self, scene, opts: RenderOptions | None = None, device: str = "cuda",
+                 cap_pairs: int | None = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libbz needs a GPU; none is visible")
+        self.lib = load_library()
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.scene = scene
+        self.ro = opts or RenderOptions()
+        self.W, self.H = scene.width, scene.height
+        self.opts = make_opts(self.W, self.H, scene.bg, self.ro)
+        order, goff, mg, mk = layout_host(scene)
+        self.n_gauss = int(goff[-1])
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
+        i32, f32 = torch.int32, torch.float32
+        self.kind = t(scene.kind, i32)
+        self.nseg = t(scene.nseg, i32)
+        self.k_samples = t(scene.k_samples, i32)
+        self.r_interior = t(scene.r_interior, i32)
+        self.ctrl = t(np.asarray(scene.ctrl, np.float32).reshape(-1, 2), f32)
+        self.ctrl_off = t(scene.ctrl_off, i32)
+        self.tau = t(np.asarray(scene.tau, np.float32), f32)
+        self.tau_off = t(scene.tau_off, i32)
+        self.stroke_w = t(np.asarray(scene.stroke_w, np.float32), f32)
+        self.color = t(np.asarray(scene.color, np.float32).reshape(-1, 3), f32)
+        self.opacity = t(np.asarray(scene.opacity, np.float32), f32)
+        self.opa_off = t(scene.opa_off, i32)
+        self.order = t(order, i32)
+        self.gauss_off = t(goff, torch.int64)
+        cv = Curves()
+        cv.n_curves, cv.n_gauss = scene.n_curves, self.n_gauss
+        cv.max_gauss_per_curve, cv.max_k = mg, mk
+        for f in ("kind", "nseg", "k_samples", "r_interior", "ctrl", "ctrl_off", "tau", "tau_off",
+                  "stroke_w", "color", "opacity", "opa_off", "order", "gauss_off"):
+            setattr(cv, f, _ptr(getattr(self, f)).value)
+        self.curves = cv
+        # Gaussians
+        self.rec = torch.empty(max(self.n_gauss, 1) * 12, dtype=f32, device=self.dev)
+        self.gauss = Gaussians(self.n_gauss, 0, _ptr(self.rec).value)
+        # tiles
+        nt = C.c_int64(0)
+        _check("bz_num_tiles", self.lib.bz_num_tiles(C.byref(self.opts), C.byref(nt)))
+        self.n_tiles = int(nt.value)
+        self.ranges = torch.zeros(2 * self.n_tiles, dtype=torch.int32, device=self.dev)
+        self.status = torch.zeros(4, dtype=torch.int64, device=self.dev)
+        self._alloc_pairs(cap_pairs if cap_pairs is not None else max(4 * self.n_gauss, 1 << 16))
+        # image and state
+        HW = self.W * self.H
+        self.image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
+        self.t_final = torch.empty((self.H, self.W), dtype=f32, device=self.dev)
+        self.n_last = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
+        self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
+        self.state = PixState(_ptr(self.t_final).value, _ptr(self.n_last).value,
+                              _ptr(self.n_contrib).value)
+        # gradients
+        self.d_image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
+        self.d_ctrl = torch.empty_like(self.ctrl)
+        self.d_width = torch.empty_like(self.stroke_w)
+        self.d_color = torch.empty_like(self.color)
+        self.d_opacity = torch.empty_like(self.opacity)
+        self.d_gauss = torch.empty(max(9 * self.n_gauss, 1), dtype=f32, device=self.dev)
+        self.grads = Grads(_ptr(self.d_ctrl).value, _ptr(self.d_width).value,
+                           _ptr(self.d_color).value, _ptr(self.d_opacity).value,
+                           _ptr(self.d_gauss).value)
+        self.loss = torch.zeros(1, dtype=f32, device=self.dev)
+        self._hw = HW
+
+    # -- capacity ------------------------------------------------------------
+    def _alloc_pairs(self, cap: int):
+        torch = self.torch
+        cap = int(min(max(cap, 1), (1 << 32) - 1))
+        self.cap_pairs = cap
+        self.ids = torch.empty(cap, dtype=torch.int32, device=self.dev)
+        wsb = C.c_int64(0)
+        _check("bz_workspace_size", self.lib.bz_workspace_size(C.byref(self.opts), self.n_gauss,
+                                                               cap, C.byref(wsb)))
+        self.workspace = torch.empty(int(wsb.value) + 256, dtype=torch.uint8, device=self.dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.bins = Bins(cap, _ptr(self.ids).value, _ptr(self.ranges).value, aligned,
+                         int(wsb.value), _ptr(self.status).value)
+
+    def pairs_required(self) -> int:
+        """Pair count of the last bz_bin (synchronises)."""
+        return int(self.status[0].item())
+
+    def flags(self) -> int:
+        return int(self.status[1].item())
+
+    def ensure_capacity(self, slack: float = 1.25) -> bool:
+        """After a bz_bin: grow the pair buffer if it overflowed (synchronises).
+        Returns True when it had to grow (the caller then bins again)."""
+        if self.flags() & STATUS_OVERFLOW:
+            self._alloc_pairs(int(math.ceil(self.pairs_required() * slack)) + 1024)
+            return True
+        return False
+
+    # -- library calls ---------------------------------------------------------
+    def sample(self):
+        _check("bz_sample", self.lib.bz_sample(C.byref(self.curves), C.byref(self.opts),
+                                               C.byref(self.gauss), _stream()))
+
+    def bin(self):
+        _check("bz_bin", self.lib.bz_bin(C.byref(self.gauss), C.byref(self.opts),
+                                         C.byref(self.bins), _stream()))
+
+    def forward(self):
+        _check("bz_render_fwd", self.lib.bz_render_fwd(C.byref(self.gauss), C.byref(self.bins),
+                                                       C.byref(self.opts), _ptr(self.image),
+                                                       C.byref(self.state), _stream()))
+        return self.image
+
+    def backward(self, d_image=None):
+        d = self.d_image if d_image is None else d_image
+        _check("bz_render_bwd", self.lib.bz_render_bwd(C.byref(self.curves), C.byref(self.gauss),
+                                                       C.byref(self.bins), C.byref(self.opts),
+                                                       _ptr(d), C.byref(self.state),
+                                                       C.byref(self.grads), _stream()))
+
+    def l2_grad(self, target, scale=None):
+        """d_image = scale (image - target), scale defaults to 2 / (3 H W) (mean
+        squared error); loss accumulates sum (image - target)^2."""
+        n = 3 * self._hw
+        s = 2.0 / n if scale is None else scale
+        _check("bz_l2_grad", self.lib.bz_l2_grad(_ptr(self.image), _ptr(target), n, C.c_float(s),
+                                                 _ptr(self.d_image), _ptr(self.loss), _stream()))
+
+    def render(self):
+        """sample + bin + forward, growing the pair buffer when needed (synchronises)."""
+        self.sample()
+        self.bin()
+        if self.ensure_capacity():
+            self.bin()
+        return self.forward()
+
+    def step(self, target):
+        """One fwd+bwd of the mean squared error against ``target`` (no sync)."""
+        self.sample()
+        self.bin()
+        self.forward()
+        self.l2_grad(target)
+        self.backward()
+
+    # -- host views --------------------------------------------------------------
+    def gaussians_host(self) -> dict:
+        r = self.rec[: 12 * self.n_gauss].view(-1, 12).cpu().numpy()
+        mu = r[:, 0:2].astype(np.float64) + r[:, 2:4].astype(np.float64)
+        return dict(mu=mu, conic=r[:, 4:7].astype(np.float64), opac=r[:, 7].astype(np.float64),
+                    color=r[:, 8:11].astype(np.float64), curve=r[:, 11].view(np.int32).copy(),
+                    hi=r[:, 0:2].copy(), lo=r[:, 2:4].copy())
+
+    def d_gauss_host(self) -> np.ndarray:
+        """Per-Gaussian gradients as [n][9] (mean x, mean y, Qxx, Qxy, Qyy, o, r, g, b)."""
+        return self.d_gauss[: 9 * self.n_gauss].view(9, -1).t().cpu().numpy().astype(np.float64)
+
+    def tile_lists(self):
+        ranges = self.ranges.view(-1, 2).cpu().numpy().astype(np.int64)
+        n = self.pairs_required()
+        ids = self.ids[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+        return ranges, ids

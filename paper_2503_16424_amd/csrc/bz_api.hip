@@ -1,0 +1,202 @@
+// bz_api.hip -- the C ABI of libbz: host-side validation and launches.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "bz_internal.h"
+
+using namespace bz;
+
+namespace {
+
+// Per-curve limits of the per-curve kernels (LDS sizes).
+constexpr int kMaxK = 1024;
+constexpr int kMaxR = 254;
+constexpr int64_t kMaxLdsBytes = 64 * 1024;
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
+
+bz_status check_opts(const bz_opts *o) {
+    if (!o) return BZ_ERR_ARG;
+    if (o->width < 1 || o->height < 1 || o->width > 32768 || o->height > 32768) return BZ_ERR_ARG;
+    if (o->tile_w < 8 || o->tile_h < 8 || o->tile_w % 8 || o->tile_h % 8) return BZ_ERR_ARG;
+    int64_t tp = (int64_t)o->tile_w * o->tile_h;
+    if (tp < 64 || tp > 1024) return BZ_ERR_ARG;
+    if (!finite_pos(o->rho) || !isfinite(o->sigma0_sq) || o->sigma0_sq < 0.f) return BZ_ERR_ARG;
+    if (!(o->g_min > 0.f && o->g_min < 1.f)) return BZ_ERR_ARG;
+    if (!(o->alpha_max > 0.f && o->alpha_max <= 1.f)) return BZ_ERR_ARG;
+    if (!(o->t_min >= 0.f && o->t_min < 1.f)) return BZ_ERR_ARG;
+    for (int c = 0; c < 3; ++c)
+        if (!isfinite(o->bg[c])) return BZ_ERR_ARG;
+    int64_t nt = tiles_x(*o) * tiles_y(*o);
+    if (nt > (int64_t(1) << 24)) return BZ_ERR_UNSUPPORTED;
+    return BZ_OK;
+}
+
+bz_status check_curves(const bz_curves *c) {
+    if (!c || c->n_curves < 0 || c->n_gauss < 0) return BZ_ERR_ARG;
+    if (c->n_gauss >= (int64_t(1) << 32)) return BZ_ERR_UNSUPPORTED;
+    if (c->n_curves == 0) return c->n_gauss == 0 ? BZ_OK : BZ_ERR_ARG;
+    if (!c->kind || !c->nseg || !c->k_samples || !c->r_interior || !c->ctrl || !c->ctrl_off ||
+        !c->tau || !c->tau_off || !c->stroke_w || !c->color || !c->opacity || !c->opa_off ||
+        !c->order || !c->gauss_off)
+        return BZ_ERR_ARG;
+    if (c->max_k < 2 || c->max_k > kMaxK || c->max_gauss_per_curve < 2) return BZ_ERR_ARG;
+    return BZ_OK;
+}
+
+bz_status check_bins(const bz_bins *b, const bz_opts *o, int64_t n_gauss, bool need_ws) {
+    if (!b || !b->ids || !b->ranges || !b->status) return BZ_ERR_ARG;
+    if (b->cap_pairs < 0 || b->cap_pairs >= (int64_t(1) << 32)) return BZ_ERR_ARG;
+    if (need_ws) {
+        if (!b->workspace || ((uintptr_t)b->workspace & 255)) return BZ_ERR_ARG;
+        if (b->workspace_bytes < bin_layout(*o, n_gauss, b->cap_pairs).total)
+            return BZ_ERR_CAPACITY;
+    }
+    return BZ_OK;
+}
+
+bz_status launched(hipError_t e) { return e == hipSuccess ? BZ_OK : BZ_ERR_HIP; }
+
+int64_t stage2_lds(const bz_curves *c) {
+    return 2 * 16 * (int64_t)c->max_k + 8 * (int64_t)c->max_gauss_per_curve + 8 * 6 * kMaxSeg;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bz_status_str(bz_status s) {
+    switch (s) {
+        case BZ_OK: return "ok";
+        case BZ_ERR_ARG: return "invalid argument";
+        case BZ_ERR_CAPACITY: return "buffer too small";
+        case BZ_ERR_HIP: return "HIP launch failed";
+        case BZ_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+bz_status bz_layout_host(int32_t n, const int32_t *kind, const int32_t *nseg,
+                         const int32_t *k_samples, const int32_t *r_interior,
+                         const int32_t *ctrl_off, const int32_t *tau_off,
+                         const int32_t *opa_off, const int32_t *rank, int32_t *order,
+                         int64_t *gauss_off, int32_t *max_gauss, int32_t *max_k) {
+    if (n < 0 || !gauss_off) return BZ_ERR_ARG;
+    if (n > 0 && (!kind || !nseg || !k_samples || !r_interior || !ctrl_off || !tau_off ||
+                  !opa_off || !rank || !order))
+        return BZ_ERR_ARG;
+    if (n > 0 && (ctrl_off[0] != 0 || tau_off[0] != 0 || opa_off[0] != 0)) return BZ_ERR_ARG;
+    std::vector<char> seen((size_t)n, 0);
+    std::vector<int64_t> per((size_t)n, 0);
+    int32_t mg = 0, mk = 0;
+    bz_status unsupported = BZ_OK;
+    for (int32_t i = 0; i < n; ++i) {
+        int S = nseg[i], K = k_samples[i];
+        bool closed = kind[i] == BZ_CLOSED;
+        if (kind[i] != BZ_OPEN && !closed) return BZ_ERR_ARG;
+        if (S < 1 || K < 2) return BZ_ERR_ARG;
+        int R = closed ? r_interior[i] : 0;
+        if (R < 0) return BZ_ERR_ARG;
+        if (S > kMaxSeg || K > kMaxK || R > kMaxR) unsupported = BZ_ERR_UNSUPPORTED;
+        int64_t need_ctrl = closed ? 6 * (int64_t)S : 3 * (int64_t)S + 1;
+        if ((int64_t)ctrl_off[i + 1] - ctrl_off[i] != need_ctrl) return BZ_ERR_ARG;
+        if ((int64_t)tau_off[i + 1] - tau_off[i] < R + 2) return BZ_ERR_ARG;
+        int nopa = opa_off[i + 1] - opa_off[i];
+        if (nopa != 1 && nopa != S) return BZ_ERR_ARG;
+        if (rank[i] < 0 || rank[i] >= n || seen[(size_t)rank[i]]) return BZ_ERR_ARG;
+        seen[(size_t)rank[i]] = 1;
+        order[rank[i]] = i;
+        int64_t ng = (int64_t)K * (closed ? R + 2 : 1);
+        per[(size_t)i] = ng;
+        if (ng > mg) mg = (int32_t)(ng > 0x7fffffff ? 0x7fffffff : ng);
+        if (K > mk) mk = K;
+    }
+    gauss_off[0] = 0;
+    for (int32_t p = 0; p < n; ++p) gauss_off[p + 1] = gauss_off[p] + per[(size_t)order[p]];
+    if (max_gauss) *max_gauss = mg;
+    if (max_k) *max_k = mk;
+    if (unsupported != BZ_OK) return unsupported;
+    if (2 * 16 * (int64_t)mk + 8 * (int64_t)mg + 8 * 6 * kMaxSeg > kMaxLdsBytes)
+        return BZ_ERR_UNSUPPORTED;
+    return BZ_OK;
+}
+
+bz_status bz_num_tiles(const bz_opts *o, int64_t *n_tiles) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!n_tiles) return BZ_ERR_ARG;
+    *n_tiles = tiles_x(*o) * tiles_y(*o);
+    return BZ_OK;
+}
+
+bz_status bz_workspace_size(const bz_opts *o, int64_t n_gauss, int64_t cap_pairs, int64_t *bytes) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!bytes || n_gauss < 0 || cap_pairs < 0 || cap_pairs >= (int64_t(1) << 32))
+        return BZ_ERR_ARG;
+    *bytes = bin_layout(*o, n_gauss, cap_pairs).total;
+    return BZ_OK;
+}
+
+bz_status bz_sample(const bz_curves *c, const bz_opts *o, bz_gaussians *g, hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if ((st = check_curves(c)) != BZ_OK) return st;
+    if (!g || (c->n_gauss > 0 && !g->rec)) return BZ_ERR_ARG;
+    if ((uintptr_t)g->rec & 15) return BZ_ERR_ARG;
+    if (g->cap < c->n_gauss) return BZ_ERR_CAPACITY;
+    if (c->n_curves > 0 && 2 * 16 * (int64_t)c->max_k > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
+    (void)hipGetLastError();
+    g->n = c->n_gauss;
+    return launched(launch_sample(*c, *o, g->rec, s));
+}
+
+bz_status bz_bin(const bz_gaussians *g, const bz_opts *o, bz_bins *b, hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!g || g->n < 0 || g->n > g->cap || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
+    if (g->n >= (int64_t(1) << 32)) return BZ_ERR_UNSUPPORTED;
+    if ((st = check_bins(b, o, g->n, true)) != BZ_OK) return st;
+    (void)hipGetLastError();
+    return launched(launch_bin(g->rec, g->n, *o, *b, s));
+}
+
+bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *o, float *image,
+                        bz_pixstate *state, hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!g || g->n < 0 || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
+    if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
+    if (!image || !state || !state->t_final || !state->n_last) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return launched(launch_fwd(g->rec, *b, *o, image, *state, s));
+}
+
+bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins *b,
+                        const bz_opts *o, const float *d_image, const bz_pixstate *state,
+                        bz_grads *gr, hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if ((st = check_curves(c)) != BZ_OK) return st;
+    if (!g || g->n != c->n_gauss || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
+    if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
+    if (!d_image || !state || !state->t_final || !state->n_last || !gr) return BZ_ERR_ARG;
+    if (c->n_curves > 0 &&
+        (!gr->d_ctrl || !gr->d_width || !gr->d_color || !gr->d_opacity || !gr->d_gauss))
+        return BZ_ERR_ARG;
+    if (c->n_curves > 0 && stage2_lds(c) > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
+    (void)hipGetLastError();
+    return launched(launch_bwd(*c, g->rec, g->n, *b, *o, d_image, *state, *gr, s));
+}
+
+bz_status bz_l2_grad(const float *image, const float *target, int64_t n, float scale,
+                     float *d_image, float *loss, hipStream_t s) {
+    if (n < 0 || (n > 0 && (!image || !target || !d_image))) return BZ_ERR_ARG;
+    if (!isfinite(scale)) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return launched(launch_l2(image, target, n, scale, d_image, loss, s));
+}
+
+}  // extern "C"

@@ -1,0 +1,434 @@
+// bz_bin.hip -- tile lists of the splatting pipeline (Sec. 3.4).
+//
+// 1. count : per Gaussian, the axis-aligned box of its truncated support
+//            1/2 d^T Q d <= -ln g_min (half extents sqrt(2 P Sigma_xx),
+//            sqrt(2 P Sigma_yy), padded), clipped to the canvas -> tile rectangle
+//            and number of tiles.
+// 2. scan  : exclusive scan of the counts -> pair offsets; the total is the pair
+//            count (status[0]); more than cap_pairs sets the overflow flag and
+//            every later stage of this call does nothing.
+// 3. emit  : (tile, Gaussian) pairs, Gaussians in draw order.
+// 4. sort  : stable LSD radix sort on the tile id only (8-bit digits, LDS
+//            ranking with wave ballots, LDS staging so that the scattered
+//            writes leave a block as contiguous runs).  Stability keeps the
+//            draw order inside every tile.
+// 5. ranges: first/last position of every tile in the sorted list.
+//
+// Sizes that depend on the data (the pair count) stay on the device: the
+// grids are sized for the capacity and idle blocks exit, so a call never
+// waits for the host.
+#include "bz_internal.h"
+
+namespace bz {
+
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlk * kItems;  // 4096 elements per block
+constexpr int kRadix = 256;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+__device__ inline int lds_pad(int i) { return i + (i >> 5); }
+
+// Block-wide exclusive scan of one 64-bit value per thread (256 threads).
+__device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t *s_wave, uint64_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    if (lane == 63) s_wave[w] = x;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlk / 64; ++i) {
+        uint64_t s = s_wave[i];
+        if (i < w) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + x - v;
+}
+
+__global__ void k_reset(int64_t *status) {
+    if (threadIdx.x == 0) {
+        status[0] = 0;
+        status[1] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, int64_t n, int W,
+                                               int H, int tw, int th, float two_p,
+                                               uint32_t *__restrict__ counts,
+                                               ushort4 *__restrict__ rects, int64_t *status) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    float4 m = rec[3 * g], q = rec[3 * g + 1];
+    float mx = m.x + m.z, my = m.y + m.w;
+    float det = q.x * q.z - q.y * q.y;
+    bool finite = isfinite(mx) && isfinite(my) && isfinite(q.x) && isfinite(q.y) &&
+                  isfinite(q.z) && isfinite(q.w);
+    uint32_t cnt = 0;
+    ushort4 rc = make_ushort4(1, 1, 0, 0);
+    if (finite && q.x > 0.f && q.z > 0.f && det > 0.f && isfinite(det)) {
+        float hx = sqrtf(two_p * q.z / det) * kCullSlackBox + kCullPadBox;
+        float hy = sqrtf(two_p * q.x / det) * kCullSlackBox + kCullPadBox;
+        // pixel x covers centre x + 1/2
+        float fx0 = ceilf(mx - hx - 0.5f), fx1 = floorf(mx + hx - 0.5f);
+        float fy0 = ceilf(my - hy - 0.5f), fy1 = floorf(my + hy - 0.5f);
+        fx0 = fmaxf(fx0, 0.f);
+        fy0 = fmaxf(fy0, 0.f);
+        fx1 = fminf(fx1, (float)(W - 1));
+        fy1 = fminf(fy1, (float)(H - 1));
+        if (fx0 <= fx1 && fy0 <= fy1) {
+            int tx0 = (int)fx0 / tw, tx1 = (int)fx1 / tw;
+            int ty0 = (int)fy0 / th, ty1 = (int)fy1 / th;
+            rc = make_ushort4(tx0, ty0, tx1, ty1);
+            cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        }
+    } else if (!finite) {
+        atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
+    }
+    counts[g] = cnt;
+    rects[g] = rc;
+}
+
+// --- device-wide exclusive scan of uint32 (64-bit partials) ---------------
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                     uint64_t *__restrict__ part) {
+    __shared__ uint64_t s_wave[kBlk / 64];
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        int64_t e = base + j * kBlk + threadIdx.x;
+        if (e < n) s += in[e];
+    }
+    uint64_t tot;
+    block_excl_scan(s, s_wave, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the block partials in place.  total_out (may be
+// null) receives the grand total; above cap the overflow flag is raised.
+__global__ __launch_bounds__(256) void k_scan_partials(uint64_t *part, int64_t nb,
+                                                       int64_t *total_out, int64_t cap,
+                                                       int64_t *status) {
+    __shared__ uint64_t s_wave[kBlk / 64];
+    uint64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kTile) {
+        uint64_t v[kItems];
+        uint64_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            int64_t e = base + threadIdx.x * kItems + j;
+            v[j] = e < nb ? part[e] : 0;
+            s += v[j];
+        }
+        uint64_t tot;
+        uint64_t ex = block_excl_scan(s, s_wave, tot) + carry;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            int64_t e = base + threadIdx.x * kItems + j;
+            if (e < nb) part[e] = ex;
+            ex += v[j];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total_out) {
+        *total_out = (int64_t)carry;
+        if ((int64_t)carry > cap)
+            atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kOverflow);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, uint32_t *out, int64_t n,
+                                                    const uint64_t *__restrict__ part) {
+    __shared__ uint32_t s_v[kTile + kTile / 32];
+    __shared__ uint64_t s_wave[kBlk / 64];
+    int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        int li = j * kBlk + threadIdx.x;
+        int64_t e = base + li;
+        s_v[lds_pad(li)] = e < n ? in[e] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        v[j] = s_v[lds_pad(threadIdx.x * kItems + j)];
+        s += v[j];
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan(s, s_wave, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        s_v[lds_pad(threadIdx.x * kItems + j)] = (uint32_t)ex;
+        ex += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        int li = j * kBlk + threadIdx.x;
+        int64_t e = base + li;
+        if (e < n) out[e] = s_v[lds_pad(li)];
+    }
+}
+
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part,
+                    int64_t *total_out, int64_t cap, int64_t *status, hipStream_t s) {
+    int64_t nb = cdiv(n, kTile);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlk), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlk), 0, s, part, nb, total_out, cap,
+                       status);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlk), 0, s, in, out, n,
+                       (const uint64_t *)part);
+    return hipGetLastError();
+}
+
+// --- pair emission ---------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
+                                              const ushort4 *__restrict__ rects, int64_t n,
+                                              int tiles_x, uint32_t *__restrict__ keys,
+                                              uint32_t *__restrict__ vals,
+                                              const int64_t *status) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n || (status[1] & Status::kOverflow)) return;
+    ushort4 rc = rects[g];
+    uint32_t o = offs[g];
+    for (int ty = rc.y; ty <= rc.w; ++ty)
+        for (int tx = rc.x; tx <= rc.z; ++tx) {
+            keys[o] = (uint32_t)(ty * tiles_x + tx);
+            vals[o] = (uint32_t)g;
+            ++o;
+        }
+}
+
+// --- stable LSD radix sort on tile ids --------------------------------------
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                    const int64_t *status, int shift, int nbits,
+                                                    uint32_t *__restrict__ hist,
+                                                    int64_t hist_blocks) {
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t n = (status[1] & Status::kOverflow) ? 0 : status[0];
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t mask = (1u << nbits) - 1u;
+    if (base < n) {
+#pragma unroll 4
+        for (int j = 0; j < kItems; ++j) {
+            int64_t e = base + j * kBlk + threadIdx.x;
+            if (e < n) atomicAdd(&h[(keys[e] >> shift) & mask], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * hist_blocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(
+    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+    const uint32_t *__restrict__ hist_scanned, int64_t hist_blocks, const int64_t *status,
+    int shift, int nbits) {
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_prefix[kRadix];
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_wcnt[kBlk / 64][kRadix];
+    __shared__ uint64_t s_wave[kBlk / 64];
+
+    if (status[1] & Status::kOverflow) return;
+    const int64_t n = status[0];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= n) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t dmask = (1u << nbits) - 1u;
+    const int cnt = (int)(n - base < kTile ? n - base : kTile);
+
+    s_run[tid] = 0;
+#pragma unroll
+    for (int q = 0; q < kBlk / 64; ++q) s_wcnt[q][tid] = 0;
+    __syncthreads();
+
+    uint32_t key[kItems], val[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        int li = j * kBlk + tid;
+        if (li < cnt) {
+            key[j] = keys_in[base + li];
+            val[j] = vals_in[base + li];
+            atomicAdd(&s_run[(key[j] >> shift) & dmask], 1u);
+        } else {
+            key[j] = 0;
+            val[j] = 0;
+        }
+    }
+    __syncthreads();
+    {
+        uint64_t tot;
+        uint32_t c = s_run[tid];
+        uint32_t ex = (uint32_t)block_excl_scan(c, s_wave, tot);
+        s_prefix[tid] = ex;
+        s_gbase[tid] = hist_scanned[(int64_t)tid * hist_blocks + blockIdx.x];
+        s_run[tid] = 0;
+    }
+    __syncthreads();
+
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int j = 0; j < kItems; ++j) {
+        int li = j * kBlk + tid;
+        bool valid = li < cnt;
+        uint32_t d = (key[j] >> shift) & dmask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        if (!valid) peers = 0;
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = s_run[d] + rank;
+            for (int q = 0; q < w; ++q) off += s_wcnt[q][d];
+            uint32_t slot = s_prefix[d] + off;
+            s_keys[slot] = key[j];
+            s_vals[slot] = val[j];
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+#pragma unroll
+            for (int q = 0; q < kBlk / 64; ++q) {
+                add += s_wcnt[q][tid];
+                s_wcnt[q][tid] = 0;
+            }
+            s_run[tid] += add;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < cnt; i += kBlk) {
+        uint32_t k = s_keys[i];
+        uint32_t d = (k >> shift) & dmask;
+        uint32_t pos = s_gbase[d] + (uint32_t)i - s_prefix[d];
+        keys_out[pos] = k;
+        vals_out[pos] = s_vals[i];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ keys,
+                                                const int64_t *status, int64_t cap,
+                                                uint32_t *__restrict__ ranges) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (status[1] & Status::kOverflow) return;
+    int64_t n = status[0];
+    if (i >= n || i >= cap) return;
+    uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+}
+
+}  // namespace
+
+BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
+    BinLayout L;
+    L.n_tiles = tiles_x(o) * tiles_y(o);
+    int bits = 0;
+    while ((int64_t(1) << bits) < L.n_tiles) ++bits;
+    if (bits == 0) bits = 1;
+    L.key_bits = bits;
+    L.passes = (bits + 7) / 8;
+    L.hist_blocks = cdiv(cap > 0 ? cap : 1, kTile);
+    int64_t off = 0;
+    L.off_counts = off;
+    off = align256(off + 4 * (n_gauss > 0 ? n_gauss : 1));
+    L.off_rects = off;
+    off = align256(off + 8 * (n_gauss > 0 ? n_gauss : 1));
+    L.off_keys_a = off;
+    off = align256(off + 4 * (cap > 0 ? cap : 1));
+    L.off_keys_b = off;
+    off = align256(off + 4 * (cap > 0 ? cap : 1));
+    L.off_vals_b = off;
+    off = align256(off + 4 * (cap > 0 ? cap : 1));
+    L.off_hist = off;
+    off = align256(off + 4 * kRadix * L.hist_blocks);
+    L.off_part = off;
+    int64_t nparts = cdiv(n_gauss > 0 ? n_gauss : 1, kTile);
+    int64_t nparts_h = cdiv(kRadix * L.hist_blocks, kTile);
+    off = align256(off + 8 * (nparts > nparts_h ? nparts : nparts_h));
+    L.total = off;
+    return L;
+}
+
+hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_bins &b,
+                      hipStream_t s) {
+    BinLayout L = bin_layout(o, n, b.cap_pairs);
+    char *ws = (char *)b.workspace;
+    uint32_t *counts = (uint32_t *)(ws + L.off_counts);
+    ushort4 *rects = (ushort4 *)(ws + L.off_rects);
+    uint32_t *keys_a = (uint32_t *)(ws + L.off_keys_a);
+    uint32_t *keys_b = (uint32_t *)(ws + L.off_keys_b);
+    uint32_t *vals_b = (uint32_t *)(ws + L.off_vals_b);
+    uint32_t *hist = (uint32_t *)(ws + L.off_hist);
+    uint64_t *part = (uint64_t *)(ws + L.off_part);
+    const float4 *rec = (const float4 *)rec_f;
+    const int tx = (int)tiles_x(o);
+
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, b.status);
+    hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(2 * L.n_tiles, 256)), dim3(256), 0, s, b.ranges,
+                       2 * L.n_tiles, 0u);
+    if (n > 0) {
+        float two_p = 2.0f * (-logf(o.g_min));
+        hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, rec, n, o.width,
+                           o.height, o.tile_w, o.tile_h, two_p, counts, rects, b.status);
+        hipError_t e = scan_u32(counts, counts, n, part, b.status, b.cap_pairs, b.status, s);
+        if (e != hipSuccess) return e;
+        // The final radix pass must land in (keys_a, ids).
+        bool even = (L.passes % 2) == 0;
+        uint32_t *k0 = even ? keys_a : keys_b, *v0 = even ? b.ids : vals_b;
+        hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 256)), dim3(256), 0, s, counts, rects, n, tx,
+                           k0, v0, (const int64_t *)b.status);
+        uint32_t *kin = k0, *vin = v0;
+        for (int p = 0; p < L.passes; ++p) {
+            int shift = 8 * p;
+            int nbits = L.key_bits - shift < 8 ? L.key_bits - shift : 8;
+            uint32_t *kout = (kin == keys_a) ? keys_b : keys_a;
+            uint32_t *vout = (vin == b.ids) ? vals_b : b.ids;
+            hipLaunchKernelGGL(k_radix_hist, dim3(L.hist_blocks), dim3(kBlk), 0, s, kin,
+                               (const int64_t *)b.status, shift, nbits, hist, L.hist_blocks);
+            e = scan_u32(hist, hist, kRadix * L.hist_blocks, part, nullptr, 0, b.status, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_radix_scatter, dim3(L.hist_blocks), dim3(kBlk), 0, s, kin, vin,
+                               kout, vout, (const uint32_t *)hist, L.hist_blocks,
+                               (const int64_t *)b.status, shift, nbits);
+            kin = kout;
+            vin = vout;
+        }
+        hipLaunchKernelGGL(k_ranges, dim3(cdiv(b.cap_pairs, 256)), dim3(256), 0, s, kin,
+                           (const int64_t *)b.status, b.cap_pairs, b.ranges);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bz

@@ -1,0 +1,154 @@
+// bz_geom.h -- per-curve sample geometry on the device (Sec. 3.3).
+//
+// One wave handles one curve.  The wave first evaluates the cubic Bernstein
+// form (Eq. bezier, bezier1) at the K uniform parameters of the two boundary
+// rows (open curves have one row) in double precision and keeps them in LDS;
+// the interior rows of a closed curve are the tau_r blends of the boundary
+// samples, which by linearity equal the samples of the blended control points
+// of Sec. 3.3.  Each lane then derives its Gaussians' means, neighbour
+// differences (Eq. sigma) and tangent chords (Eq. rotation) from LDS.
+#pragma once
+
+#include "bz_internal.h"
+
+namespace bz {
+
+struct CurveView {
+    int id;          // curve index
+    int kind;        // BZ_OPEN / BZ_CLOSED
+    int S, K, R;     // segments, samples per row, interior rows (0 for open)
+    int rows;        // 1 or R+2
+    int nopa;        // 1 or S
+    int64_t g0;      // first Gaussian
+    const float *P;  // control points
+    const float *tau;
+    float width;
+};
+
+__device__ inline CurveView load_curve_view(const bz_curves &c, int p) {
+    CurveView v;
+    int i = c.order[p];
+    v.id = i;
+    v.kind = c.kind[i];
+    v.S = c.nseg[i];
+    v.K = c.k_samples[i];
+    v.R = v.kind == BZ_CLOSED ? c.r_interior[i] : 0;
+    v.rows = v.kind == BZ_CLOSED ? v.R + 2 : 1;
+    v.nopa = c.opa_off[i + 1] - c.opa_off[i];
+    v.g0 = c.gauss_off[p];
+    v.P = c.ctrl + 2 * (int64_t)c.ctrl_off[i];
+    v.tau = c.tau + c.tau_off[i];
+    v.width = c.stroke_w[i];
+    return v;
+}
+
+// Column k of a row: segment s = min(floor(kS/(K-1)), S-1) in integers and the
+// local parameter t in [0, 1] of that segment.
+__device__ inline void column_param(int k, int K, int S, int &s, double &t) {
+    s = (k * S) / (K - 1);
+    if (s > S - 1) s = S - 1;
+    t = (double)(k * S - s * (K - 1)) / (double)(K - 1);
+}
+
+__device__ inline void bernstein3(double t, double B[4]) {
+    double u = 1.0 - t;
+    B[0] = u * u * u;
+    B[1] = 3.0 * u * u * t;
+    B[2] = 3.0 * u * t * t;
+    B[3] = t * t * t;
+}
+
+// Control point jj (0..3S) of boundary A or B of a closed curve (B shares A's
+// endpoints; its interior points follow A's 3S+1 points in storage).
+__device__ inline double2 ctrl_point(const CurveView &v, bool boundary_b, int jj) {
+    int m = 3 * v.S;
+    int idx = (boundary_b && jj != 0 && jj != m) ? m + jj : jj;
+    return make_double2((double)v.P[2 * idx], (double)v.P[2 * idx + 1]);
+}
+
+// Boundary samples XA[k] (and XB[k] for closed curves) into LDS.
+__device__ inline void boundary_samples(const CurveView &v, double2 *XA, double2 *XB, int lane,
+                                        int nlanes) {
+    for (int k = lane; k < v.K; k += nlanes) {
+        int s;
+        double t, B[4];
+        column_param(k, v.K, v.S, s, t);
+        bernstein3(t, B);
+        double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+        for (int j = 0; j < 4; ++j) {
+            double2 a = ctrl_point(v, false, 3 * s + j);
+            ax += B[j] * a.x;
+            ay += B[j] * a.y;
+            if (v.kind == BZ_CLOSED) {
+                double2 b = ctrl_point(v, true, 3 * s + j);
+                bx += B[j] * b.x;
+                by += B[j] * b.y;
+            }
+        }
+        XA[k] = make_double2(ax, ay);
+        if (v.kind == BZ_CLOSED) XB[k] = make_double2(bx, by);
+    }
+}
+
+// Sample point X_{r,k}.
+__device__ inline double2 sample_at(const CurveView &v, const double2 *XA, const double2 *XB,
+                                    int r, int k) {
+    double2 a = XA[k];
+    if (v.kind != BZ_CLOSED) return a;
+    double t = (double)v.tau[r];
+    double2 b = XB[k];
+    return make_double2((1.0 - t) * a.x + t * b.x, (1.0 - t) * a.y + t * b.y);
+}
+
+struct Geom {
+    double2 mu;
+    double sx2, sy2;       // dilated squared scales
+    double cs, sn;         // unit tangent
+    double2 d_along;       // X[r][ka] - X[r][kb]
+    double2 d_across;      // X[ra][k] - X[rb][k] (closed)
+    double2 v;             // X[r][kp] - X[r][km]
+    double nv;             // |v|
+    int ka, kb, ra, rb, kp, km;
+    int seg;
+};
+
+// Geometry of Gaussian (r, k): Eq. sigma with the nearest-neighbour rule at
+// the last column / row, Eq. rotation one-sided at the row ends, unit tangent
+// (1, 0) when the chord has zero length.
+__device__ inline void gauss_geom(const CurveView &v, const double2 *XA, const double2 *XB, int r,
+                                  int k, double inv_rho2, double s0, Geom &g) {
+    int K = v.K;
+    double t;
+    column_param(k, K, v.S, g.seg, t);
+    g.mu = sample_at(v, XA, XB, r, k);
+    if (k < K - 1) { g.ka = k + 1; g.kb = k; } else { g.ka = K - 1; g.kb = K - 2; }
+    double2 A = sample_at(v, XA, XB, r, g.ka), B = sample_at(v, XA, XB, r, g.kb);
+    g.d_along = make_double2(A.x - B.x, A.y - B.y);
+    g.sx2 = (g.d_along.x * g.d_along.x + g.d_along.y * g.d_along.y) * inv_rho2 + s0;
+    if (v.kind == BZ_CLOSED) {
+        int R1 = v.R + 1;
+        if (r < R1) { g.ra = r + 1; g.rb = r; } else { g.ra = R1; g.rb = R1 - 1; }
+        double2 P = sample_at(v, XA, XB, g.ra, k), Q = sample_at(v, XA, XB, g.rb, k);
+        g.d_across = make_double2(P.x - Q.x, P.y - Q.y);
+        g.sy2 = (g.d_across.x * g.d_across.x + g.d_across.y * g.d_across.y) * inv_rho2 + s0;
+    } else {
+        g.ra = g.rb = 0;
+        g.d_across = make_double2(0.0, 0.0);
+        double w = (double)v.width;
+        g.sy2 = w * w + s0;
+    }
+    g.kp = k + 1 < K ? k + 1 : K - 1;
+    g.km = k > 0 ? k - 1 : 0;
+    double2 Pp = sample_at(v, XA, XB, r, g.kp), Pm = sample_at(v, XA, XB, r, g.km);
+    g.v = make_double2(Pp.x - Pm.x, Pp.y - Pm.y);
+    g.nv = sqrt(g.v.x * g.v.x + g.v.y * g.v.y);
+    if (g.nv > 0.0) {
+        g.cs = g.v.x / g.nv;
+        g.sn = g.v.y / g.nv;
+    } else {
+        g.cs = 1.0;
+        g.sn = 0.0;
+    }
+}
+
+}  // namespace bz

@@ -1,0 +1,75 @@
+// bz_internal.h -- private declarations of libbz (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bz.h"
+
+namespace bz {
+
+// Gaussian record: three float4 per Gaussian (see bz_gaussians in bz.h).
+constexpr int kRecF4 = 3;
+
+// Per-Gaussian gradient planes (see bz_grads in bz.h).
+constexpr int kGradPlanes = 9;
+
+// Wave size of gfx950.
+constexpr int kWave = 64;
+
+// Quads: every wave owns one 8x8 block of pixels; tiles are made of quads.
+constexpr int kQuad = 8;
+
+// Largest number of segments per curve handled by the per-curve kernels.
+constexpr int kMaxSeg = 4;
+
+// log2(e)
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Relative slack on the support threshold used by the culling tests.  Culling
+// only needs to be conservative: every pixel whose float32 kernel value exceeds
+// g_min must survive both the tile bound and the per-wave quad test.
+constexpr float kCullSlackQuad = 1.001f;   // on the quadratic-form threshold
+constexpr float kCullSlackBox = 1.0012f;   // on the bounding-box half extents
+constexpr float kCullPadBox = 0.02f;       // px added to the half extents
+
+struct Status {
+    static constexpr int64_t kOverflow = 1;
+    static constexpr int64_t kNonFinite = 2;
+};
+
+// ---------------------------------------------------------------------------
+// host launchers implemented in the .hip files
+// ---------------------------------------------------------------------------
+hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipStream_t s);
+hipError_t launch_bin(const float *rec, int64_t n_gauss, const bz_opts &o, const bz_bins &b,
+                      hipStream_t s);
+hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
+                      const bz_pixstate &st, hipStream_t s);
+hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, const bz_bins &b,
+                      const bz_opts &o, const float *d_image, const bz_pixstate &st,
+                      const bz_grads &gr, hipStream_t s);
+hipError_t launch_l2(const float *image, const float *target, int64_t n, float scale,
+                     float *d_image, float *loss, hipStream_t s);
+
+// Workspace layout of bz_bin (bytes); shared by bz_workspace_size and the launcher.
+struct BinLayout {
+    int64_t n_tiles = 0;
+    int key_bits = 0;
+    int passes = 0;
+    int64_t hist_blocks = 0;      // radix blocks for cap_pairs
+    int64_t off_counts = 0;       // uint32 [n_gauss]      per-Gaussian tile count -> offsets
+    int64_t off_rects = 0;        // uint16x4 [n_gauss]    tile rectangles
+    int64_t off_keys_a = 0;       // uint32 [cap]
+    int64_t off_keys_b = 0;       // uint32 [cap]
+    int64_t off_vals_b = 0;       // uint32 [cap]
+    int64_t off_hist = 0;         // uint32 [radix][hist_blocks]
+    int64_t off_part = 0;         // uint64 partial sums of the scans
+    int64_t total = 0;
+};
+BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap_pairs);
+
+inline int64_t tiles_x(const bz_opts &o) { return (o.width + o.tile_w - 1) / o.tile_w; }
+inline int64_t tiles_y(const bz_opts &o) { return (o.height + o.tile_h - 1) / o.tile_h; }
+
+}  // namespace bz

@@ -1,0 +1,558 @@
+// bz_render.hip -- per-tile blending (Sec. 3.4) and its reverse pass.
+//
+// Work decomposition (forward and backward stage 1): one workgroup per tile,
+// one wave per 8x8 pixel quad of the tile, one pixel per lane.  Waves are
+// independent: each walks its tile's list in batches of 64 entries; lane j
+// loads entry j's record, tests the entry's truncated support against the
+// quad (exact minimum of the quadratic form over the quad's pixel centres),
+// and writes the derived per-Gaussian constants into the wave's LDS slice.
+// A ballot of the test gives the batch's mask; the wave then iterates only
+// over the surviving entries, reading each one's constants as an LDS
+// broadcast, so pixels never spend ALU on Gaussians that cannot reach their
+// quad.  A wave stops when all 64 of its pixels have terminated.
+//
+// Blocks are mapped to tiles XCD-contiguously: the dispatcher deals blocks
+// round robin to the 8 XCDs, so block b serves tile (b % 8) * per + b / 8 and
+// each XCD's L2 sees a compact band of neighbouring tiles, which share most
+// of their Gaussians.
+//
+// Stage 2 of the backward pass is per curve (one wave per curve, no atomics):
+// it chains the per-Gaussian gradients through the sampling of Sec. 3.3.
+#include "bz_geom.h"
+
+namespace bz {
+
+namespace {
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ inline int xcd_tile(int b, int per) { return (b & 7) * per + (b >> 3); }
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Minimum over the box [x0,x1]x[y0,y1] (offsets from the mean) of
+// f(d) = qa dx^2 + 2 qb dx dy + qc dy^2, compared against thr.
+__device__ inline bool box_hit(float x0, float x1, float y0, float y1, float qa, float qb,
+                               float qc, float thr) {
+    if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+    float best = 3.0e38f;
+    float ia = 1.0f / qa, ic = 1.0f / qc;
+    // vertical edges: dx fixed, minimise over dy
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        float dx = e ? x1 : x0;
+        float dy = fminf(fmaxf(-qb * dx * ic, y0), y1);
+        best = fminf(best, qa * dx * dx + 2.f * qb * dx * dy + qc * dy * dy);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        float dy = e ? y1 : y0;
+        float dx = fminf(fmaxf(-qb * dy * ia, x0), x1);
+        best = fminf(best, qa * dx * dx + 2.f * qb * dx * dy + qc * dy * dy);
+    }
+    return best <= thr;
+}
+
+struct TileArgs {
+    const float4 *rec;
+    const uint32_t *ids;
+    const uint32_t *ranges;
+    const int64_t *status;
+    int W, H, tile_w, tile_h, tiles_x, n_tiles, per_xcd, quads_x;
+    float bg0, bg1, bg2;
+    float g_min, alpha_max, t_min, inv_1mg, box_thr;
+    float *image;
+    float *t_final;
+    uint32_t *n_last;
+    uint32_t *n_contrib;
+    // backward
+    const float *d_image;
+    float *d_gauss;
+    int64_t n_gauss;
+};
+
+// Entry of the wave's LDS slice: mean (hi, lo), log2-scaled half conic and
+// the opacity divided by (1 - g_min), colour and opacity * g_min / (1 - g_min).
+struct Staged {
+    float4 m;   // hi.x, hi.y, lo.x, lo.y
+    float4 q;   // A, B, C (p*log2e = A dx^2 + B dx dy + C dy^2), o'
+    float4 c;   // r, g, b, o' * g_min
+};
+
+// Load entry j of the tile list, compute its LDS constants and its quad test.
+__device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, float qy0,
+                                   Staged &st) {
+    float4 m = a.rec[3 * (int64_t)id];
+    float4 q = a.rec[3 * (int64_t)id + 1];
+    float4 c = a.rec[3 * (int64_t)id + 2];
+    float op = q.w * a.inv_1mg;
+    st.m = m;
+    st.q = make_float4(0.5f * kLog2e * q.x, kLog2e * q.y, 0.5f * kLog2e * q.z, op);
+    st.c = make_float4(c.x, c.y, c.z, op * a.g_min);
+    float x0 = (qx0 - m.x) - m.z, y0 = (qy0 - m.y) - m.w;
+    return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, q.x, q.y, q.z, a.box_thr);
+}
+
+__global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
+    extern __shared__ Staged s_stage[];
+    const int tile = xcd_tile(blockIdx.x, a.per_xcd);
+    if (tile >= a.n_tiles) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int qx = w % a.quads_x, qy = w / a.quads_x;
+    const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
+    if (x0 >= a.W || y0 >= a.H) return;
+    const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
+    const bool valid = x < a.W && y < a.H;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
+    Staged *my = s_stage + w * 64;
+
+    const int64_t pix = (int64_t)y * a.W + x;
+    const int64_t plane = (int64_t)a.W * a.H;
+    if (a.status[1] & Status::kOverflow) {
+        if (valid) {
+            float nan = __int_as_float(0x7fc00000);
+            a.image[pix] = nan;
+            a.image[plane + pix] = nan;
+            a.image[2 * plane + pix] = nan;
+            a.t_final[pix] = nan;
+            a.n_last[pix] = 0;
+            if (a.n_contrib) a.n_contrib[pix] = 0;
+        }
+        return;
+    }
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    uint32_t last = 0, cnt = 0;
+    bool done = !valid;
+    const float g_min = a.g_min, amax = a.alpha_max, tmin = a.t_min;
+
+    for (uint32_t base = start; base < end; base += 64) {
+        uint32_t j = base + lane;
+        bool hit = false;
+        if (j < end) {
+            Staged st;
+            hit = stage_entry(a, a.ids[j], qx0, qy0, st);
+            my[lane] = st;
+        }
+        uint64_t mask = __ballot(hit);
+        wave_lds_sync();
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const Staged st = my[b];
+            if (!done) {
+                float dx = (px - st.m.x) - st.m.z;
+                float dy = (py - st.m.y) - st.m.w;
+                float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
+                float G = __builtin_amdgcn_exp2f(-p2);
+                if (G > g_min) {
+                    float al = fminf(fmaf(st.q.w, G, -st.c.w), amax);
+                    float wgt = al * T;
+                    C0 = fmaf(wgt, st.c.x, C0);
+                    C1 = fmaf(wgt, st.c.y, C1);
+                    C2 = fmaf(wgt, st.c.z, C2);
+                    T = T * (1.f - al);
+                    last = base + b + 1 - start;
+                    cnt += 1;
+                    done = T < tmin;
+                }
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        wave_lds_sync();
+    }
+    if (valid) {
+        a.image[pix] = fmaf(T, a.bg0, C0);
+        a.image[plane + pix] = fmaf(T, a.bg1, C1);
+        a.image[2 * plane + pix] = fmaf(T, a.bg2, C2);
+        a.t_final[pix] = T;
+        a.n_last[pix] = last;
+        if (a.n_contrib) a.n_contrib[pix] = cnt;
+    }
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
+    extern __shared__ Staged s_stage[];
+    __shared__ uint32_t s_ids[16][64];
+    const int tile = xcd_tile(blockIdx.x, a.per_xcd);
+    if (tile >= a.n_tiles) return;
+    if (a.status[1] & Status::kOverflow) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int qx = w % a.quads_x, qy = w / a.quads_x;
+    const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
+    if (x0 >= a.W || y0 >= a.H) return;
+    const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
+    const bool valid = x < a.W && y < a.H;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
+    Staged *my = s_stage + w * 64;
+    uint32_t *my_ids = s_ids[w];
+
+    const uint32_t start = a.ranges[2 * tile];
+    const int64_t pix = (int64_t)y * a.W + x;
+    const int64_t plane = (int64_t)a.W * a.H;
+    uint32_t nl = 0;
+    float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    if (valid) {
+        nl = a.n_last[pix];
+        T = a.t_final[pix];
+        g0 = a.d_image[pix];
+        g1 = a.d_image[plane + pix];
+        g2 = a.d_image[2 * plane + pix];
+    }
+    float A0 = a.bg0, A1 = a.bg1, A2 = a.bg2;
+    uint32_t top = nl;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
+    const float g_min = a.g_min, amax = a.alpha_max, inv_1mg = a.inv_1mg;
+    const int64_t ng = a.n_gauss;
+
+    for (int64_t hi = top; hi > 0; hi -= 64) {
+        int64_t lo = hi - 64 > 0 ? hi - 64 : 0;
+        int64_t j = lo + lane;
+        bool hit = false;
+        if (j < hi) {
+            uint32_t id = a.ids[start + j];
+            Staged st;
+            hit = stage_entry(a, id, qx0, qy0, st);
+            my[lane] = st;
+            my_ids[lane] = id;
+        }
+        uint64_t mask = __ballot(hit);
+        wave_lds_sync();
+        while (mask) {
+            const int b = 63 - __builtin_clzll(mask);
+            mask &= ~(1ull << b);
+            const Staged st = my[b];
+            const uint32_t pos = (uint32_t)(lo + b);
+            float s_dx = 0.f, s_dy = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f, s_o = 0.f;
+            float s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
+            bool contrib = false;
+            if (pos < nl) {
+                float dx = (px - st.m.x) - st.m.z;
+                float dy = (py - st.m.y) - st.m.w;
+                float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
+                float G = __builtin_amdgcn_exp2f(-p2);
+                if (G > g_min) {
+                    contrib = true;
+                    float araw = fmaf(st.q.w, G, -st.c.w);
+                    bool clamped = araw > amax;
+                    float al = clamped ? amax : araw;
+                    float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
+                    float wgt = al * Tb;
+                    s_c0 = wgt * g0;
+                    s_c1 = wgt * g1;
+                    s_c2 = wgt * g2;
+                    float abar = Tb * ((st.c.x - A0) * g0 + (st.c.y - A1) * g1 + (st.c.z - A2) * g2);
+                    A0 = fmaf(al, st.c.x - A0, A0);
+                    A1 = fmaf(al, st.c.y - A1, A1);
+                    A2 = fmaf(al, st.c.z - A2, A2);
+                    T = Tb;
+                    if (!clamped) {
+                        s_o = abar * (G - g_min) * inv_1mg;
+                        float pbar = -abar * st.q.w * G;
+                        s_dx = pbar * dx;
+                        s_dy = pbar * dy;
+                        s_xx = s_dx * dx;
+                        s_xy = s_dx * dy;
+                        s_yy = s_dy * dy;
+                    }
+                }
+            }
+            if (__ballot(contrib) == 0) continue;
+            s_dx = wave_sum(s_dx);
+            s_dy = wave_sum(s_dy);
+            s_xx = wave_sum(s_xx);
+            s_xy = wave_sum(s_xy);
+            s_yy = wave_sum(s_yy);
+            s_o = wave_sum(s_o);
+            s_c0 = wave_sum(s_c0);
+            s_c1 = wave_sum(s_c1);
+            s_c2 = wave_sum(s_c2);
+            if (lane == 0) {
+                const uint32_t id = my_ids[b];
+                const float4 q = a.rec[3 * (int64_t)id + 1];
+                float *dg = a.d_gauss + id;
+                // mean: -Q sum(pbar d); conic: sum(pbar (dx^2/2, dx dy, dy^2/2))
+                atomicAdd(dg, -(q.x * s_dx + q.y * s_dy));
+                atomicAdd(dg + ng, -(q.y * s_dx + q.z * s_dy));
+                atomicAdd(dg + 2 * ng, 0.5f * s_xx);
+                atomicAdd(dg + 3 * ng, s_xy);
+                atomicAdd(dg + 4 * ng, 0.5f * s_yy);
+                atomicAdd(dg + 5 * ng, s_o);
+                atomicAdd(dg + 6 * ng, s_c0);
+                atomicAdd(dg + 7 * ng, s_c1);
+                atomicAdd(dg + 8 * ng, s_c2);
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+__global__ void k_zero(float *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.f;
+}
+
+// Stage 2: one wave per curve.  Per Gaussian (r, k) the gradients of
+// (mean, Q, o, colour) are chained to the sample points of its stencil:
+//   Q = R diag(a, b) R^T, a = 1/sx2, b = 1/sy2, (c, s) = v/|v|,
+//   sx2 = |X[r][ka]-X[r][kb]|^2/rho^2 + s0, sy2 = |X[ra][k]-X[rb][k]|^2/rho^2 + s0
+//   (closed) or w^2 + s0 (open), mean = X[r][k];
+// the sample-point gradients (LDS, ds_add) then go to the control points:
+// X[r][k] = sum_j B_j(t_k) ((1-tau_r) A_{3s+j} + tau_r B_{3s+j}).
+__global__ __launch_bounds__(64) void k_bwd_curves(bz_curves c, double inv_rho2, double s0,
+                                                   const float *__restrict__ d_gauss,
+                                                   int64_t ng, float *__restrict__ d_ctrl,
+                                                   float *__restrict__ d_width,
+                                                   float *__restrict__ d_color,
+                                                   float *__restrict__ d_opacity) {
+    extern __shared__ double2 lds_xy[];
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    CurveView v = load_curve_view(c, p);
+    double2 *XA = lds_xy;
+    double2 *XB = lds_xy + c.max_k;
+    float *Xbar = reinterpret_cast<float *>(lds_xy + 2 * c.max_k);   // [rows*K][2]
+    float *Pacc = Xbar + 2 * c.max_gauss_per_curve;                  // [6*kMaxSeg][2]
+    boundary_samples(v, XA, XB, lane, 64);
+    const int n = v.rows * v.K;
+    for (int i = lane; i < 2 * n; i += 64) Xbar[i] = 0.f;
+    __syncthreads();
+
+    float wbar = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
+    float ob[kMaxSeg] = {0.f, 0.f, 0.f, 0.f};
+    const double rho2i = inv_rho2;
+    for (int idx = lane; idx < n; idx += 64) {
+        int r = idx / v.K, k = idx - r * v.K;
+        int64_t g = v.g0 + idx;
+        float dg[kGradPlanes];
+#pragma unroll
+        for (int q = 0; q < kGradPlanes; ++q) dg[q] = d_gauss[q * ng + g];
+        Geom ge;
+        gauss_geom(v, XA, XB, r, k, inv_rho2, s0, ge);
+        double a = 1.0 / ge.sx2, b = 1.0 / ge.sy2, cs = ge.cs, sn = ge.sn;
+        double qxx = dg[2], qxy = dg[3], qyy = dg[4];
+        double abar = qxx * cs * cs + qxy * cs * sn + qyy * sn * sn;
+        double bbar = qxx * sn * sn - qxy * cs * sn + qyy * cs * cs;
+        double cbar_t = qxx * 2.0 * cs * a + qxy * sn * (a - b) + qyy * 2.0 * cs * b;
+        double sbar_t = qxx * 2.0 * sn * b + qxy * cs * (a - b) + qyy * 2.0 * sn * a;
+        double sx2bar = -abar * a * a;
+        double sy2bar = -bbar * b * b;
+        atomicAdd(&Xbar[2 * idx], dg[0]);
+        atomicAdd(&Xbar[2 * idx + 1], dg[1]);
+        float f = (float)(2.0 * sx2bar * rho2i);
+        float fx = f * (float)ge.d_along.x, fy = f * (float)ge.d_along.y;
+        atomicAdd(&Xbar[2 * (r * v.K + ge.ka)], fx);
+        atomicAdd(&Xbar[2 * (r * v.K + ge.ka) + 1], fy);
+        atomicAdd(&Xbar[2 * (r * v.K + ge.kb)], -fx);
+        atomicAdd(&Xbar[2 * (r * v.K + ge.kb) + 1], -fy);
+        if (v.kind == BZ_CLOSED) {
+            float h = (float)(2.0 * sy2bar * rho2i);
+            float hx = h * (float)ge.d_across.x, hy = h * (float)ge.d_across.y;
+            atomicAdd(&Xbar[2 * (ge.ra * v.K + k)], hx);
+            atomicAdd(&Xbar[2 * (ge.ra * v.K + k) + 1], hy);
+            atomicAdd(&Xbar[2 * (ge.rb * v.K + k)], -hx);
+            atomicAdd(&Xbar[2 * (ge.rb * v.K + k) + 1], -hy);
+        } else {
+            wbar += (float)(2.0 * (double)v.width * sy2bar);
+        }
+        if (ge.nv > 0.0) {
+            double hd = cs * cbar_t + sn * sbar_t;
+            float vb0 = (float)((cbar_t - cs * hd) / ge.nv);
+            float vb1 = (float)((sbar_t - sn * hd) / ge.nv);
+            atomicAdd(&Xbar[2 * (r * v.K + ge.kp)], vb0);
+            atomicAdd(&Xbar[2 * (r * v.K + ge.kp) + 1], vb1);
+            atomicAdd(&Xbar[2 * (r * v.K + ge.km)], -vb0);
+            atomicAdd(&Xbar[2 * (r * v.K + ge.km) + 1], -vb1);
+        }
+        int slot = v.nopa == v.S ? ge.seg : 0;
+#pragma unroll
+        for (int q = 0; q < kMaxSeg; ++q)
+            if (q == slot) ob[q] += dg[5];
+        cb0 += dg[6];
+        cb1 += dg[7];
+        cb2 += dg[8];
+    }
+    wbar = wave_sum(wbar);
+    cb0 = wave_sum(cb0);
+    cb1 = wave_sum(cb1);
+    cb2 = wave_sum(cb2);
+#pragma unroll
+    for (int q = 0; q < kMaxSeg; ++q) ob[q] = wave_sum(ob[q]);
+    if (lane == 0) {
+        d_width[v.id] = v.kind == BZ_CLOSED ? 0.f : wbar;
+        d_color[3 * v.id] = cb0;
+        d_color[3 * v.id + 1] = cb1;
+        d_color[3 * v.id + 2] = cb2;
+        float *dop = d_opacity + c.opa_off[v.id];
+#pragma unroll
+        for (int q = 0; q < kMaxSeg; ++q)
+            if (q < v.nopa) dop[q] = ob[q];
+    }
+
+    // Control points.  Lanes own (row, coordinate) pairs and accumulate the
+    // gradient of the row's own control points, Pbar[jj] = sum_k B_{jj-3s_k}(t_k)
+    // Xbar[r][k]; the stored points then receive them with the row weights:
+    // open -> as is; closed -> A_j gets (1 - tau_r) (all of it at the shared
+    // endpoints), the interior points of B get tau_r.
+    const int m = 3 * v.S;
+    const int nstore = v.kind == BZ_CLOSED ? 2 * m : m + 1;
+    for (int t = lane; t < 2 * nstore; t += 64) Pacc[t] = 0.f;
+    __syncthreads();
+    for (int t = lane; t < 2 * v.rows; t += 64) {
+        const int coord = t & 1, r = t >> 1;
+        float acc[3 * kMaxSeg + 1];
+#pragma unroll
+        for (int j = 0; j < 3 * kMaxSeg + 1; ++j) acc[j] = 0.f;
+        for (int k = 0; k < v.K; ++k) {
+            int s;
+            double tt, B[4];
+            column_param(k, v.K, v.S, s, tt);
+            bernstein3(tt, B);
+            const float xb = Xbar[2 * (r * v.K + k) + coord];
+#pragma unroll
+            for (int s2 = 0; s2 < kMaxSeg; ++s2) {
+                if (s2 == s) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[3 * s2 + j] += (float)B[j] * xb;
+                }
+            }
+        }
+        const float tr = v.kind == BZ_CLOSED ? v.tau[r] : 0.f;
+#pragma unroll
+        for (int jj = 0; jj < 3 * kMaxSeg + 1; ++jj) {
+            if (jj <= m) {
+                const float gv = acc[jj];
+                if (v.kind != BZ_CLOSED || jj == 0 || jj == m) {
+                    atomicAdd(&Pacc[2 * jj + coord], gv);
+                } else {
+                    atomicAdd(&Pacc[2 * jj + coord], (1.f - tr) * gv);
+                    atomicAdd(&Pacc[2 * (m + jj) + coord], tr * gv);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    float *out = d_ctrl + 2 * (int64_t)c.ctrl_off[v.id];
+    for (int t = lane; t < 2 * nstore; t += 64) out[t] = Pacc[t];
+}
+
+__global__ void k_loss_zero(float *loss) {
+    if (threadIdx.x == 0) loss[0] = 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_l2(const float *__restrict__ img,
+                                            const float *__restrict__ tgt, int64_t n, float scale,
+                                            float *__restrict__ d, float *loss) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    float acc = 0.f;
+    for (; i < n; i += stride) {
+        float e = img[i] - tgt[i];
+        d[i] = scale * e;
+        acc = fmaf(e, e, acc);
+    }
+    if (loss) {
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc);
+    }
+}
+
+TileArgs tile_args(const float *rec, const bz_bins &b, const bz_opts &o) {
+    TileArgs a = {};
+    a.rec = (const float4 *)rec;
+    a.ids = b.ids;
+    a.ranges = b.ranges;
+    a.status = b.status;
+    a.W = o.width;
+    a.H = o.height;
+    a.tile_w = o.tile_w;
+    a.tile_h = o.tile_h;
+    a.tiles_x = (int)tiles_x(o);
+    a.n_tiles = (int)(tiles_x(o) * tiles_y(o));
+    a.per_xcd = (int)cdiv(a.n_tiles, 8);
+    a.quads_x = o.tile_w / kQuad;
+    a.bg0 = o.bg[0];
+    a.bg1 = o.bg[1];
+    a.bg2 = o.bg[2];
+    a.g_min = o.g_min;
+    a.alpha_max = o.alpha_max;
+    a.t_min = o.t_min;
+    a.inv_1mg = 1.0f / (1.0f - o.g_min);
+    a.box_thr = 2.0f * (-logf(o.g_min)) * kCullSlackQuad;
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
+                      const bz_pixstate &st, hipStream_t s) {
+    TileArgs a = tile_args(rec, b, o);
+    a.image = image;
+    a.t_final = st.t_final;
+    a.n_last = st.n_last;
+    a.n_contrib = st.n_contrib;
+    int threads = o.tile_w * o.tile_h;
+    size_t lds = sizeof(Staged) * (size_t)threads;
+    hipLaunchKernelGGL(k_fwd, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, const bz_bins &b,
+                      const bz_opts &o, const float *d_image, const bz_pixstate &st,
+                      const bz_grads &gr, hipStream_t s) {
+    int64_t nz = (int64_t)kGradPlanes * n_gauss;
+    if (nz > 0) {
+        int64_t blocks = cdiv(nz, 256);
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, gr.d_gauss, nz);
+    }
+    TileArgs a = tile_args(rec, b, o);
+    a.t_final = st.t_final;
+    a.n_last = st.n_last;
+    a.d_image = d_image;
+    a.d_gauss = gr.d_gauss;
+    a.n_gauss = n_gauss;
+    int threads = o.tile_w * o.tile_h;
+    size_t lds = sizeof(Staged) * (size_t)threads;
+    hipLaunchKernelGGL(k_bwd_tiles, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    if (c.n_curves > 0) {
+        size_t lds2 = 2 * sizeof(double2) * (size_t)c.max_k +
+                      2 * sizeof(float) * (size_t)c.max_gauss_per_curve +
+                      2 * sizeof(float) * (size_t)(6 * kMaxSeg);
+        double rho = (double)o.rho;
+        hipLaunchKernelGGL(k_bwd_curves, dim3(c.n_curves), dim3(64), lds2, s, c,
+                           1.0 / (rho * rho), (double)o.sigma0_sq, (const float *)gr.d_gauss,
+                           n_gauss, gr.d_ctrl, gr.d_width, gr.d_color, gr.d_opacity);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_l2(const float *image, const float *target, int64_t n, float scale,
+                     float *d_image, float *loss, hipStream_t s) {
+    if (loss) hipLaunchKernelGGL(k_loss_zero, dim3(1), dim3(64), 0, s, loss);
+    if (n > 0) {
+        int64_t blocks = cdiv(n, 256);
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_l2, dim3(blocks), dim3(256), 0, s, image, target, n, scale, d_image,
+                           loss);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bz

@@ -1,0 +1,57 @@
+// bz_sample.hip -- curves -> 2D Gaussians (Sec. 3.3).
+//
+// One 64-lane workgroup (one wave) per curve, in draw order.  The boundary
+// rows are evaluated once per curve in double precision (LDS), every lane then
+// emits Gaussians (r, k) of the curve: mean in double, split into a float
+// high part and a float low part; squared scales from the neighbour distances
+// of Eq. sigma plus the dilation sigma0^2; Q = Sigma^-1 from the unit tangent
+// of Eq. rotation (Eq. RSSR with R = [c -s; s c], S = diag(sx, sy)).  Records
+// of one curve are contiguous, so the stores of a wave are coalesced.
+#include "bz_geom.h"
+
+namespace bz {
+
+__global__ __launch_bounds__(64) void k_sample(bz_curves c, double inv_rho2, double s0,
+                                               float4 *__restrict__ rec) {
+    extern __shared__ double2 lds_xy[];
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    CurveView v = load_curve_view(c, p);
+    double2 *XA = lds_xy;
+    double2 *XB = lds_xy + c.max_k;
+    boundary_samples(v, XA, XB, lane, 64);
+    __syncthreads();
+
+    const float *col = c.color + 3 * (int64_t)v.id;
+    const float cr = col[0], cg = col[1], cb = col[2];
+    const float *opa = c.opacity + c.opa_off[v.id];
+    const float cid = __int_as_float(v.id);
+    const int n = v.rows * v.K;
+    for (int idx = lane; idx < n; idx += 64) {
+        int r = idx / v.K, k = idx - r * v.K;
+        Geom g;
+        gauss_geom(v, XA, XB, r, k, inv_rho2, s0, g);
+        double a = 1.0 / g.sx2, b = 1.0 / g.sy2;
+        double qxx = g.cs * g.cs * a + g.sn * g.sn * b;
+        double qxy = g.cs * g.sn * (a - b);
+        double qyy = g.sn * g.sn * a + g.cs * g.cs * b;
+        float hx = (float)g.mu.x, hy = (float)g.mu.y;
+        float lx = (float)(g.mu.x - (double)hx), ly = (float)(g.mu.y - (double)hy);
+        float o = opa[v.nopa == v.S ? g.seg : 0];
+        int64_t gi = v.g0 + idx;
+        rec[3 * gi + 0] = make_float4(hx, hy, lx, ly);
+        rec[3 * gi + 1] = make_float4((float)qxx, (float)qxy, (float)qyy, o);
+        rec[3 * gi + 2] = make_float4(cr, cg, cb, cid);
+    }
+}
+
+hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipStream_t s) {
+    if (c.n_curves == 0) return hipSuccess;
+    size_t lds = 2 * sizeof(double2) * (size_t)c.max_k;
+    double rho = (double)o.rho;
+    hipLaunchKernelGGL(k_sample, dim3(c.n_curves), dim3(64), lds, s, c, 1.0 / (rho * rho),
+                       (double)o.sigma0_sq, reinterpret_cast<float4 *>(rec));
+    return hipGetLastError();
+}
+
+}  // namespace bz

@@ -1,0 +1,147 @@
+"""The C ABI without a GPU: exports, host-side layout and argument validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_16424_amd import bz, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "bz.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bz_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = bz.load_library()
+    names = _declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(bz.EXPORTS)
+
+
+def test_status_strings():
+    lib = bz.load_library()
+    for code in (0, -1, -2, -3, -4):
+        assert lib.bz_status_str(code)
+    assert lib.bz_status_str(7) == b"unknown status"
+
+
+def test_layout_matches_rank_order():
+    sc = scenes.small_mixed(3, n_closed=4, n_open=5)
+    order, goff, mg, mk = bz.layout_host(sc)
+    assert sorted(order) == list(range(sc.n_curves))
+    assert np.all(sc.rank[order] == np.arange(sc.n_curves))
+    per = sc.n_gauss_per_curve()[order]
+    assert np.array_equal(np.diff(goff), per)
+    assert goff[-1] == sc.n_gauss
+    assert mg == per.max() and mk == sc.k_samples.max()
+
+
+@pytest.mark.parametrize("mutate", ["rank_dup", "k_one", "ctrl_count", "opa_count", "tau_short",
+                                    "kind", "negative_r"])
+def test_layout_rejects_inconsistent_curves(mutate):
+    sc = scenes.small_mixed(5, n_closed=3, n_open=3)
+    if mutate == "rank_dup":
+        sc.rank[1] = sc.rank[0]
+    elif mutate == "k_one":
+        sc.k_samples[0] = 1
+    elif mutate == "ctrl_count":
+        sc.ctrl_off[1:] += 1
+    elif mutate == "opa_count":
+        i = int(np.nonzero(sc.kind == 0)[0][0])
+        sc.opa_off[i + 1:] += 1                          # S + 1 opacities
+    elif mutate == "tau_short":
+        i = int(np.nonzero(sc.kind == 1)[0][0])
+        sc.tau_off[i + 1:] -= 1
+    elif mutate == "kind":
+        sc.kind[0] = 7
+    elif mutate == "negative_r":
+        i = int(np.nonzero(sc.kind == 1)[0][0])
+        sc.r_interior[i] = -1
+    with pytest.raises(bz.BzError) as e:
+        bz.layout_host(sc)
+    assert e.value.code == bz.BZ_ERR_ARG
+
+
+def test_layout_flags_unsupported_sizes():
+    sc = scenes.uniform_open(0, 64, 64, 3, 8, S=1)
+    sc.k_samples[1] = 2000
+    with pytest.raises(bz.BzError) as e:
+        bz.layout_host(sc)
+    assert e.value.code == bz.BZ_ERR_UNSUPPORTED
+
+
+def _opts(**kw):
+    ro = bz.RenderOptions(**{k: v for k, v in kw.items() if k in bz.RenderOptions.__dataclass_fields__})
+    return bz.make_opts(kw.get("W", 128), kw.get("H", 96), (1, 1, 1), ro)
+
+
+@pytest.mark.parametrize("tw,th,ok", [(16, 16, True), (8, 8, True), (32, 8, True), (32, 32, True),
+                                      (12, 16, False), (4, 16, False), (64, 32, False),
+                                      (8, 4, False)])
+def test_tile_shape_validation(tw, th, ok):
+    lib = bz.load_library()
+    o = _opts(tile_w=tw, tile_h=th)
+    n = C.c_int64(0)
+    st = lib.bz_num_tiles(C.byref(o), C.byref(n))
+    assert (st == bz.BZ_OK) == ok
+    if ok:
+        assert n.value == -(-128 // tw) * -(-96 // th)
+
+
+@pytest.mark.parametrize("field,value", [("g_min", 0.0), ("g_min", 1.0), ("alpha_max", 0.0),
+                                         ("alpha_max", 1.5), ("t_min", -1e-3), ("rho", 0.0),
+                                         ("sigma0_sq", -0.1), ("width", 0)])
+def test_option_validation(field, value):
+    lib = bz.load_library()
+    o = _opts()
+    setattr(o, field, value)
+    n = C.c_int64(0)
+    assert lib.bz_num_tiles(C.byref(o), C.byref(n)) == bz.BZ_ERR_ARG
+
+
+def test_workspace_size_monotone():
+    lib = bz.load_library()
+    o = _opts()
+    sizes = []
+    for cap in (0, 1000, 100000, 10 ** 7):
+        b = C.c_int64(0)
+        assert lib.bz_workspace_size(C.byref(o), 5000, cap, C.byref(b)) == bz.BZ_OK
+        sizes.append(b.value)
+    assert sizes == sorted(sizes) and sizes[-1] > 3 * 4 * 10 ** 7
+    b = C.c_int64(0)
+    assert lib.bz_workspace_size(C.byref(o), 5000, 1 << 32, C.byref(b)) == bz.BZ_ERR_ARG
+
+
+def test_device_calls_reject_null_arguments_before_launch():
+    """Argument errors are caught on the host, so these calls never touch HIP."""
+    lib = bz.load_library()
+    o = _opts()
+    assert lib.bz_sample(None, C.byref(o), None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_bin(None, C.byref(o), None, None) == bz.BZ_ERR_ARG
+    g = bz.Gaussians(10, 10, 0)
+    assert lib.bz_bin(C.byref(g), C.byref(o), None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_render_fwd(None, None, C.byref(o), None, None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_render_bwd(None, None, None, C.byref(o), None, None, None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_l2_grad(None, None, 10, C.c_float(1.0), None, None, None) == bz.BZ_ERR_ARG
+    bad = _opts(tile_w=12)
+    assert lib.bz_sample(None, C.byref(bad), None, None) == bz.BZ_ERR_ARG
+
+
+def test_sample_rejects_small_capacity_on_host():
+    lib = bz.load_library()
+    o = _opts()
+    cv = bz.Curves()
+    cv.n_curves, cv.n_gauss, cv.max_gauss_per_curve, cv.max_k = 1, 16, 16, 16
+    for f in ("kind", "nseg", "k_samples", "r_interior", "ctrl", "ctrl_off", "tau", "tau_off",
+              "stroke_w", "color", "opacity", "opa_off", "order", "gauss_off"):
+        setattr(cv, f, 4096)                               # never dereferenced on the host
+    g = bz.Gaussians(8, 0, 4096)
+    assert lib.bz_sample(C.byref(cv), C.byref(o), C.byref(g), None) == bz.BZ_ERR_CAPACITY

@@ -1,0 +1,265 @@
+"""Parity of the HIP rasterizer (through the C ABI) with the FP64 CPU oracle.
+
+Bars: images within 1e-5 max abs of the oracle; per-group gradients
+(control points, widths, colours, opacities) within 1e-3 relative L2; tile
+lists valid and complete; images bitwise identical across tile shapes and
+runs.  Inputs come from the seeded scene generator only.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16424_amd import scenes
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+def _note(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return torch
+
+
+def _rast(scene, tile=(16, 16), **kw):
+    from paper_2503_16424_amd import bz
+    ro = bz.RenderOptions(tile_w=tile[0], tile_h=tile[1])
+    return bz.Rasterizer(scene, ro, **kw)
+
+
+def _upstream(scene, img_oracle, seed=7):
+    tgt = scenes.target_noise(seed, scene.width, scene.height).astype(np.float64)
+    return (2.0 * (img_oracle - tgt) / img_oracle.size).astype(np.float32)
+
+
+SCENES = {
+    "tiny_128": lambda: scenes.tiny_128(0),
+    "mixed_small_a": lambda: scenes.small_mixed(1, W=96, H=80, n_closed=6, n_open=8, K=10, R=4,
+                                                extent=(6.0, 40.0)),
+    "mixed_small_b": lambda: scenes.small_mixed(2, W=131, H=77, n_closed=9, n_open=12, K=12,
+                                                R=6, extent=(4.0, 60.0)),
+    "mixed_R20": lambda: scenes.mixed(3, 200, 168, 40, 30, K=24, R=20, S_open=3,
+                                      extent=(4.0, 120.0)),
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_sample_matches_oracle(torch_cuda, name):
+    sc = SCENES[name]()
+    _note(f"sample parity {name} n_gauss={sc.n_gauss}")
+    r = _rast(sc)
+    r.sample()
+    g = r.gaussians_host()
+    o = oracle.sample(sc)
+    assert np.abs(g["mu"] - o["mu"]).max() < 1e-6
+    # the low part carries what float32 cannot: hi is the rounded mean
+    assert np.all(np.abs(g["hi"].astype(np.float64) - o["mu"]) <= np.spacing(np.abs(g["hi"])))
+    scale = np.maximum(np.abs(o["conic"][:, 0]), np.abs(o["conic"][:, 2]))[:, None]
+    assert (np.abs(g["conic"] - o["conic"]) / scale).max() < 1e-6
+    assert np.array_equal(g["opac"], o["opac"].astype(np.float32).astype(np.float64))
+    assert np.array_equal(g["color"], o["color"].astype(np.float32).astype(np.float64))
+    assert np.array_equal(g["curve"], o["curve"])
+
+
+def _aabb_tiles(mu, conic, W, H, tw, th, g_min, scale, pad):
+    """Tile rectangles of the support bounding box (float64 reference)."""
+    P = -math.log(g_min)
+    det = conic[:, 0] * conic[:, 2] - conic[:, 1] ** 2
+    hx = np.sqrt(2 * P * conic[:, 2] / det) * scale + pad
+    hy = np.sqrt(2 * P * conic[:, 0] / det) * scale + pad
+    x0 = np.maximum(np.ceil(mu[:, 0] - hx - 0.5), 0)
+    x1 = np.minimum(np.floor(mu[:, 0] + hx - 0.5), W - 1)
+    y0 = np.maximum(np.ceil(mu[:, 1] - hy - 0.5), 0)
+    y1 = np.minimum(np.floor(mu[:, 1] + hy - 0.5), H - 1)
+    ok = (x0 <= x1) & (y0 <= y1)
+    return ok, (x0 // tw).astype(int), (x1 // tw).astype(int), (y0 // th).astype(int), (y1 // th).astype(int)
+
+
+@pytest.mark.parametrize("name", ["tiny_128", "mixed_small_b", "mixed_R20"])
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_tile_lists_valid_and_complete(torch_cuda, name, tile):
+    sc = SCENES[name]()
+    _note(f"tile lists {name} tile={tile}")
+    r = _rast(sc, tile)
+    r.sample()
+    r.bin()
+    assert not r.ensure_capacity()
+    ranges, ids = r.tile_lists()
+    o = oracle.sample(sc)
+    tw, th = tile
+    tx = -(-sc.width // tw)
+    got = set()
+    for t, (s, e) in enumerate(ranges):
+        lst = ids[s:e]
+        assert np.all(np.diff(lst) > 0), "tile list not in strictly increasing draw order"
+        got.update((int(g), t) for g in lst)
+    assert len(got) == r.pairs_required() == sum(e - s for s, e in ranges)
+    gm = oracle.DEFAULTS["g_min"]
+    must = _aabb_tiles(o["mu"], o["conic"], sc.width, sc.height, tw, th, gm, 1.0, -1e-3)
+    may = _aabb_tiles(o["mu"], o["conic"], sc.width, sc.height, tw, th, gm, 1.0012, 0.02 + 1e-3)
+    want_min, want_max = set(), set()
+    for which, (ok, x0, x1, y0, y1) in ((want_min, must), (want_max, may)):
+        for g in np.nonzero(ok)[0]:
+            for ty in range(y0[g], y1[g] + 1):
+                for txx in range(x0[g], x1[g] + 1):
+                    which.add((int(g), ty * tx + txx))
+    assert want_min <= got, f"{len(want_min - got)} required pairs missing"
+    assert got <= want_max, f"{len(got - want_max)} pairs outside the padded support box"
+
+
+@pytest.mark.parametrize("name", list(SCENES) + ["open_512"])
+def test_forward_matches_oracle(torch_cuda, name):
+    sc = scenes.open_512(0) if name == "open_512" else SCENES[name]()
+    _note(f"forward parity {name} n_gauss={sc.n_gauss}")
+    r = _rast(sc)
+    img = r.render().cpu().numpy().astype(np.float64)
+    T = r.t_final.cpu().numpy().astype(np.float64)
+    nc = r.n_contrib.cpu().numpy()
+    o = oracle.forward_backward(sc)
+    err = np.abs(img - o["image"])
+    _note(f"  max |img - oracle| = {err.max():.3e}")
+    assert err.max() <= IMG_TOL
+    assert np.abs(T - o["t_final"]).max() <= IMG_TOL
+    # contributor counts: identical except where a float32/float64 decision
+    # sits on the support boundary or the termination threshold
+    mism = np.mean(nc != o["n_contrib"])
+    assert mism < 2e-3
+    assert abs(int(nc.sum()) - o["pairs"]) <= 2e-3 * max(o["pairs"], 1)
+
+
+def test_forward_bitwise_across_tile_shapes_and_runs(torch_cuda):
+    sc = SCENES["mixed_small_b"]()
+    imgs = []
+    for tile in [(16, 16), (8, 8), (32, 8), (8, 32), (16, 8), (32, 32)]:
+        r = _rast(sc, tile)
+        imgs.append((tile, r.render().cpu().numpy().copy(), r.t_final.cpu().numpy().copy()))
+    imgs.append(("again", _rast(sc).render().cpu().numpy().copy(), None))
+    ref = imgs[0][1]
+    for tile, im, _ in imgs[1:]:
+        assert np.array_equal(im.view(np.uint32), ref.view(np.uint32)), f"tile {tile} differs"
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_backward_matches_oracle(torch_cuda, name):
+    import torch
+    sc = SCENES[name]()
+    _note(f"backward parity {name} n_gauss={sc.n_gauss}")
+    o0 = oracle.forward_backward(sc)
+    dimg = _upstream(sc, o0["image"])
+    o = oracle.forward_backward(sc, dimg.astype(np.float64))
+    r = _rast(sc)
+    r.render()
+    r.backward(torch.as_tensor(dimg, device="cuda"))
+    torch.cuda.synchronize()
+    got = dict(d_ctrl=r.d_ctrl.cpu().numpy(), d_width=r.d_width.cpu().numpy(),
+               d_color=r.d_color.cpu().numpy(), d_opacity=r.d_opacity.cpu().numpy())
+    for k in ("d_ctrl", "d_color", "d_opacity"):
+        e = rel_l2(got[k], o[k])
+        _note(f"  {k}: rel L2 = {e:.3e}")
+        assert e <= GRAD_TOL, k
+    if np.any(sc.kind == 0):
+        e = rel_l2(got["d_width"], o["d_width"])
+        _note(f"  d_width: rel L2 = {e:.3e}")
+        assert e <= GRAD_TOL
+    assert np.all(got["d_width"][sc.kind == 1] == 0.0)
+    dg = r.d_gauss_host()
+    for j, label in enumerate(["mu_x", "mu_y", "Qxx", "Qxy", "Qyy", "o", "r", "g", "b"]):
+        e = rel_l2(dg[:, j], o["d_gauss"][:, j])
+        assert e <= GRAD_TOL, label
+
+
+def test_step_with_l2_kernel_matches_oracle_gradient(torch_cuda):
+    """The fused step (sample, bin, forward, L2 gradient kernel, backward)."""
+    import torch
+    sc = scenes.tiny_128(0)
+    tgt = scenes.tiny_128_target(0)
+    r = _rast(sc)
+    r.render()
+    t = torch.as_tensor(tgt, device="cuda")
+    r.step(t)
+    torch.cuda.synchronize()
+    o0 = oracle.forward_backward(sc)
+    d = 2.0 * (o0["image"] - tgt.astype(np.float64)) / o0["image"].size
+    o = oracle.forward_backward(sc, d)
+    assert np.abs(r.d_image.cpu().numpy() - d).max() < 1e-9
+    mse = float(np.mean((o0["image"] - tgt) ** 2))
+    assert abs(r.loss.item() / o0["image"].size - mse) < 1e-6
+    for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
+        assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= GRAD_TOL, k
+
+
+def test_overflow_is_flagged_and_recovers(torch_cuda):
+    sc = SCENES["mixed_small_a"]()
+    r = _rast(sc, cap_pairs=16)
+    r.sample()
+    r.bin()
+    from paper_2503_16424_amd import bz
+    assert r.flags() & bz.STATUS_OVERFLOW
+    need = r.pairs_required()
+    assert need > 16
+    r.forward()
+    assert np.all(np.isnan(r.image.cpu().numpy()))
+    assert r.ensure_capacity()
+    r.bin()
+    assert not (r.flags() & bz.STATUS_OVERFLOW)
+    img = r.forward().cpu().numpy()
+    o = oracle.forward_backward(sc)
+    assert np.abs(img - o["image"]).max() <= IMG_TOL
+
+
+def test_degenerate_scenes(torch_cuda):
+    # every curve far outside the canvas
+    sc = scenes.small_mixed(9, W=64, H=48)
+    sc.ctrl = sc.ctrl + np.float32(5000.0)
+    r = _rast(sc)
+    img = r.render().cpu().numpy()
+    assert np.all(img == 1.0) and r.pairs_required() == 0
+    # zero opacity: background exactly
+    sc = scenes.small_mixed(10, W=64, H=48)
+    sc.opacity[:] = 0.0
+    sc.bg = np.array([0.25, 0.5, 0.75], np.float32)
+    r = _rast(sc)
+    img = r.render().cpu().numpy()
+    assert np.all(img == sc.bg[:, None, None])
+    assert np.all(r.t_final.cpu().numpy() == 1.0)
+    # a one-pixel canvas and a ragged canvas
+    for W, H in [(1, 1), (17, 9), (8, 200)]:
+        sc = scenes.small_mixed(11, W=W, H=H, n_closed=2, n_open=2, extent=(3.0, 20.0))
+        r = _rast(sc)
+        img = r.render().cpu().numpy()
+        o = oracle.forward_backward(sc)
+        assert np.abs(img - o["image"]).max() <= IMG_TOL
+
+
+def test_paper_scale_sampled_parity(torch_cuda):
+    """2048x2048, 20,000 curves (6,528,000 Gaussians) in the benchmark's launch
+    configuration: Gaussians sampled one by one, pixels checked one by one."""
+    sc = scenes.paper_2048(0)
+    _note(f"paper-scale n_gauss={sc.n_gauss}")
+    r = _rast(sc)
+    img = r.render().cpu().numpy()
+    rng = np.random.default_rng(123)
+    g = r.gaussians_host()
+    o = oracle.sample(sc)
+    assert g["mu"].shape == o["mu"].shape
+    assert np.abs(g["mu"] - o["mu"]).max() < 1e-6
+    scale = np.maximum(np.abs(o["conic"][:, 0]), np.abs(o["conic"][:, 2]))[:, None]
+    assert (np.abs(g["conic"] - o["conic"]) / scale).max() < 1e-6
+    xs = rng.integers(0, sc.width, 400)
+    ys = rng.integers(0, sc.height, 400)
+    p = oracle.render_pixels(o, sc.width, sc.height, sc.bg, xs, ys)
+    err = np.abs(img[:, ys, xs].T - p["rgb"]).max()
+    _note(f"  sampled pixels max err {err:.3e}")
+    assert err <= IMG_TOL

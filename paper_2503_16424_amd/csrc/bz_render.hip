@@ -183,9 +183,85 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xF, 0xF, false));
+}
+
+// Exchange lanes 32..63 of x with lanes 0..31 of y (v_permlane32_swap), and
+// the odd 16-lane rows of x with the even rows of y (v_permlane16_swap).  Both
+// registers are outputs of the instruction; the compiler builtins of this
+// toolchain return the first one twice, so the instruction is written here
+// with both operands read-write.  s_nop 1 gives the two wait states a swap
+// needs after a VALU write of its operands.
+__device__ inline void swap32(float &x, float &y) {
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+}
+
+__device__ inline void swap16(float &x, float &y) {
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+}
+
+// Transposed reduction of 64 per-lane values: on return lane l holds the sum
+// over all 64 lanes of v[l].  Each level halves the values a lane holds by
+// exchanging half of them with a partner lane: lanes l and l^32 (permlane32
+// swap), l^16 (permlane16 swap), l^8 (DPP row rotate by 8), l^7 (DPP half-row
+// mirror), l^3 and l^1 (DPP quad permutes).  Bit b of the lane index decides
+// which half a lane keeps, so after the six levels lane l holds index l.
+// 141 VALU instructions for 64 sums (a butterfly per value would need 384).
+__device__ inline float reduce_scatter64(float (&v)[64], int lane) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        float x = v[i], y = v[i + 32];
+        swap32(x, y);
+        v[i] = x + y;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float x = v[i], y = v[i + 16];
+        swap16(x, y);
+        v[i] = x + y;
+    }
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
+        v[i] = keep + dpp_f<0x128>(send);          // row_ror:8  (lane ^ 8)
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
+        v[i] = keep + dpp_f<0x141>(send);          // row_half_mirror (lane ^ 7)
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
+        v[i] = keep + dpp_f<0x1B>(send);           // quad_perm [3,2,1,0] (lane ^ 3)
+    }
+    {
+        float keep = b0 ? v[1] : v[0], send = b0 ? v[0] : v[1];
+        v[0] = keep + dpp_f<0xB1>(send);           // quad_perm [1,0,3,2] (lane ^ 1)
+    }
+    return v[0];
+}
+
+constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
+
+// Backward stage 1.  Each wave walks its tile list from the last entry any of
+// its pixels used down to the first.  Per pixel and contributor (reverse
+// order): T before it = T after / (1 - alpha); colour gradient alpha T g;
+// alpha gradient T sum_ch (c - A) g with A the colour composited behind it
+// (starts at the background, A <- alpha c + (1 - alpha) A); then, unless alpha
+// was clamped, the opacity gradient and dL/dp = -alpha_bar o' G, which gives
+// the mean gradient -dL/dp Q d and the conic gradient dL/dp (dx^2/2, dx dy,
+// dy^2/2).  The nine per-lane values of seven Gaussians are summed over the
+// wave in one transposed reduction and added to the per-Gaussian planes with
+// one 63-lane atomic instruction.
 __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_ids[16][64];
+    __shared__ uint32_t s_slot[16][8];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
     if (tile >= a.n_tiles) return;
     if (a.status[1] & Status::kOverflow) return;
@@ -200,6 +276,7 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
     uint32_t *my_ids = s_ids[w];
+    uint32_t *my_slot = s_slot[w];
 
     const uint32_t start = a.ranges[2 * tile];
     const int64_t pix = (int64_t)y * a.W + x;
@@ -218,87 +295,108 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
     const float g_min = a.g_min, amax = a.alpha_max, inv_1mg = a.inv_1mg;
+    const float ln2 = 0.69314718056f;
     const int64_t ng = a.n_gauss;
+    const int my_v = lane % 9, my_s = lane / 9;
 
-    for (int64_t hi = top; hi > 0; hi -= 64) {
-        int64_t lo = hi - 64 > 0 ? hi - 64 : 0;
-        int64_t j = lo + lane;
-        bool hit = false;
-        if (j < hi) {
-            uint32_t id = a.ids[start + j];
-            Staged st;
-            hit = stage_entry(a, id, qx0, qy0, st);
-            my[lane] = st;
-            my_ids[lane] = id;
-        }
-        uint64_t mask = __ballot(hit);
-        wave_lds_sync();
-        while (mask) {
-            const int b = 63 - __builtin_clzll(mask);
-            mask &= ~(1ull << b);
-            const Staged st = my[b];
-            const uint32_t pos = (uint32_t)(lo + b);
-            float s_dx = 0.f, s_dy = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f, s_o = 0.f;
-            float s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
-            bool contrib = false;
-            if (pos < nl) {
-                float dx = (px - st.m.x) - st.m.z;
-                float dy = (py - st.m.y) - st.m.w;
-                float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
-                float G = __builtin_amdgcn_exp2f(-p2);
-                if (G > g_min) {
-                    contrib = true;
-                    float araw = fmaf(st.q.w, G, -st.c.w);
-                    bool clamped = araw > amax;
-                    float al = clamped ? amax : araw;
-                    float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
-                    float wgt = al * Tb;
-                    s_c0 = wgt * g0;
-                    s_c1 = wgt * g1;
-                    s_c2 = wgt * g2;
-                    float abar = Tb * ((st.c.x - A0) * g0 + (st.c.y - A1) * g1 + (st.c.z - A2) * g2);
-                    A0 = fmaf(al, st.c.x - A0, A0);
-                    A1 = fmaf(al, st.c.y - A1, A1);
-                    A2 = fmaf(al, st.c.z - A2, A2);
-                    T = Tb;
-                    if (!clamped) {
-                        s_o = abar * (G - g_min) * inv_1mg;
-                        float pbar = -abar * st.q.w * G;
-                        s_dx = pbar * dx;
-                        s_dy = pbar * dy;
-                        s_xx = s_dx * dx;
-                        s_xy = s_dx * dy;
-                        s_yy = s_dy * dy;
+    int64_t hi = top;      // entries [0, hi) not yet staged
+    int64_t lo = 0;        // first entry of the staged batch
+    uint64_t mask = 0;     // staged entries not yet visited
+    bool more = true;
+    while (more) {
+        float acc[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) acc[i] = 0.f;
+        int filled = 0;
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            if (s == filled && more) {
+                bool got = false;
+                while (!got) {
+                    while (mask == 0 && hi > 0) {
+                        const int64_t nlo = hi - 64 > 0 ? hi - 64 : 0;
+                        const int64_t j = nlo + lane;
+                        bool hit = false;
+                        wave_lds_sync();
+                        if (j < hi) {
+                            const uint32_t id = a.ids[start + j];
+                            Staged st;
+                            hit = stage_entry(a, id, qx0, qy0, st);
+                            my[lane] = st;
+                            my_ids[lane] = id;
+                        }
+                        mask = __ballot(hit);
+                        lo = nlo;
+                        hi = nlo;
+                        wave_lds_sync();
+                    }
+                    if (mask == 0) {
+                        more = false;
+                        break;
+                    }
+                    const int b = 63 - __builtin_clzll(mask);
+                    mask &= ~(1ull << b);
+                    const Staged st = my[b];
+                    const uint32_t pos = (uint32_t)(lo + b);
+                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
+                    float v6 = 0.f, v7 = 0.f, v8 = 0.f;
+                    bool contrib = false;
+                    if (pos < nl) {
+                        const float dx = (px - st.m.x) - st.m.z;
+                        const float dy = (py - st.m.y) - st.m.w;
+                        const float t1 = st.q.x * dx + st.q.y * dy;
+                        const float p2 = dx * t1 + st.q.z * dy * dy;
+                        const float G = __builtin_amdgcn_exp2f(-p2);
+                        if (G > g_min) {
+                            contrib = true;
+                            const float araw = fmaf(st.q.w, G, -st.c.w);
+                            const bool clamped = araw > amax;
+                            const float al = clamped ? amax : araw;
+                            const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
+                            const float wgt = al * Tb;
+                            v6 = wgt * g0;
+                            v7 = wgt * g1;
+                            v8 = wgt * g2;
+                            const float abar = Tb * ((st.c.x - A0) * g0 + (st.c.y - A1) * g1 +
+                                                     (st.c.z - A2) * g2);
+                            A0 = fmaf(al, st.c.x - A0, A0);
+                            A1 = fmaf(al, st.c.y - A1, A1);
+                            A2 = fmaf(al, st.c.z - A2, A2);
+                            T = Tb;
+                            if (!clamped) {
+                                v5 = abar * (G - g_min) * inv_1mg;
+                                const float pbar = -abar * st.q.w * G;
+                                const float pl = pbar * ln2;
+                                v0 = -pl * (t1 + st.q.x * dx);
+                                v1 = -pl * (st.q.y * dx + 2.f * st.q.z * dy);
+                                const float ph = 0.5f * pbar;
+                                v2 = ph * dx * dx;
+                                v3 = pbar * dx * dy;
+                                v4 = ph * dy * dy;
+                            }
+                        }
+                    }
+                    if (__ballot(contrib) != 0) {
+                        got = true;
+                        acc[9 * s + 0] = v0;
+                        acc[9 * s + 1] = v1;
+                        acc[9 * s + 2] = v2;
+                        acc[9 * s + 3] = v3;
+                        acc[9 * s + 4] = v4;
+                        acc[9 * s + 5] = v5;
+                        acc[9 * s + 6] = v6;
+                        acc[9 * s + 7] = v7;
+                        acc[9 * s + 8] = v8;
+                        if (lane == 0) my_slot[s] = my_ids[b];
                     }
                 }
-            }
-            if (__ballot(contrib) == 0) continue;
-            s_dx = wave_sum(s_dx);
-            s_dy = wave_sum(s_dy);
-            s_xx = wave_sum(s_xx);
-            s_xy = wave_sum(s_xy);
-            s_yy = wave_sum(s_yy);
-            s_o = wave_sum(s_o);
-            s_c0 = wave_sum(s_c0);
-            s_c1 = wave_sum(s_c1);
-            s_c2 = wave_sum(s_c2);
-            if (lane == 0) {
-                const uint32_t id = my_ids[b];
-                const float4 q = a.rec[3 * (int64_t)id + 1];
-                float *dg = a.d_gauss + id;
-                // mean: -Q sum(pbar d); conic: sum(pbar (dx^2/2, dx dy, dy^2/2))
-                atomicAdd(dg, -(q.x * s_dx + q.y * s_dy));
-                atomicAdd(dg + ng, -(q.y * s_dx + q.z * s_dy));
-                atomicAdd(dg + 2 * ng, 0.5f * s_xx);
-                atomicAdd(dg + 3 * ng, s_xy);
-                atomicAdd(dg + 4 * ng, 0.5f * s_yy);
-                atomicAdd(dg + 5 * ng, s_o);
-                atomicAdd(dg + 6 * ng, s_c0);
-                atomicAdd(dg + 7 * ng, s_c1);
-                atomicAdd(dg + 8 * ng, s_c2);
+                if (got) filled = s + 1;
             }
         }
+        if (filled == 0) break;
         wave_lds_sync();
+        const float r = reduce_scatter64(acc, lane);
+        if (lane < 9 * filled) atomicAdd(a.d_gauss + (int64_t)my_v * ng + my_slot[my_s], r);
     }
 }
 
@@ -468,8 +566,11 @@ __global__ __launch_bounds__(256) void k_l2(const float *__restrict__ img,
         acc = fmaf(e, e, acc);
     }
     if (loss) {
+        __shared__ float s_part[4];
         acc = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(loss, s_part[0] + s_part[1] + s_part[2] + s_part[3]);
     }
 }
 
@@ -548,7 +649,7 @@ hipError_t launch_l2(const float *image, const float *target, int64_t n, float s
     if (loss) hipLaunchKernelGGL(k_loss_zero, dim3(1), dim3(64), 0, s, loss);
     if (n > 0) {
         int64_t blocks = cdiv(n, 256);
-        if (blocks > 8192) blocks = 8192;
+        if (blocks > 1024) blocks = 1024;
         hipLaunchKernelGGL(k_l2, dim3(blocks), dim3(256), 0, s, image, target, n, scale, d_image,
                            loss);
     }

@@ -50,6 +50,9 @@ def parse():
                                                                  "tiny_128"])
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the timed steps, copy a MIB-sized buffer once (a known-size "
+                         "kernel to scale hardware byte counters against)")
     ap.add_argument("--cpu-rows", type=int, default=128,
                     help="rows of the frame the CPU oracle renders for its baseline")
     return ap.parse_args()
@@ -117,6 +120,16 @@ def main():
         r._alloc_pairs(int(need * 1.1) + 1024)
     for _ in range(a.warmup):
         r.step(tgt)
+    if a.copy_calibration > 0:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {a.copy_calibration} MiB read + {a.copy_calibration} MiB "
+              "written", file=sys.stderr, flush=True)
+        del src, dst
     torch.cuda.synchronize()
     print(f"# warmup done, {need} pairs", file=sys.stderr, flush=True)
 

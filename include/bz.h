@@ -134,13 +134,21 @@ typedef struct {
     int64_t *status;
 } bz_bins;
 
-/* Per-pixel forward state kept for the reverse pass ([height][width] each).
- * n_last: number of list entries up to and including the pixel's last
- * contributor.  n_contrib (optional, may be NULL): contributors per pixel. */
+/* Forward state kept for the reverse pass.
+ * t_final, n_last: [height][width]; n_last is the number of tile-list entries up
+ *   to and including the pixel's last contributor.
+ * n_contrib (optional, may be NULL): contributors per pixel, [height][width].
+ * visit: per 8x8 pixel block and per 64-entry batch of its tile list, the bit
+ *   mask of entries that contributed to at least one pixel of the block; the
+ *   reverse pass visits only those.  visit_words 64-bit words, at least what
+ *   bz_visit_words reports for the same options and cap_pairs.  Written by
+ *   bz_render_fwd, read by bz_render_bwd; no initialisation needed. */
 typedef struct {
     float *t_final;
     uint32_t *n_last;
     uint32_t *n_contrib;
+    uint64_t *visit;
+    int64_t visit_words;
 } bz_pixstate;
 
 /* Gradients.  Per curve, same layouts as the inputs: d_ctrl [n_ctrl][2],
@@ -175,6 +183,9 @@ bz_status bz_workspace_size(const bz_opts *opts, int64_t n_gauss, int64_t cap_pa
 /* Host: number of tiles of the canvas for the options' tile shape. */
 bz_status bz_num_tiles(const bz_opts *opts, int64_t *n_tiles);
 
+/* Host: 64-bit words of bz_pixstate.visit for tile lists of cap_pairs entries. */
+bz_status bz_visit_words(const bz_opts *opts, int64_t cap_pairs, int64_t *words);
+
 /* Sec. 3.3: sample K Gaussians per row along every curve (one row for open
  * curves, R+2 rows for closed ones), scales from neighbour distances (Eq.
  * sigma), orientation from the neighbour chord (Eq. rotation), covariance
@@ -204,7 +215,9 @@ bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *
  * gradients into grads->d_gauss.  Stage 2, per curve, chains them through the
  * sampling of Sec. 3.3 to control points, widths, colours and opacities.
  * d_image: dL/dimage, [3][H][W].  c, g, b, opts and state must be those of the
- * forward pass. */
+ * forward pass.  Requires alpha_max < 1 (the division recovering T).
+ * Per-Gaussian sums use float atomics, so d_gauss and the curve gradients
+ * vary in the last bits from run to run. */
 bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins *b,
                         const bz_opts *opts, const float *d_image, const bz_pixstate *state,
                         bz_grads *grads, hipStream_t stream);

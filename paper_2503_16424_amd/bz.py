@@ -50,7 +50,8 @@ class Bins(C.Structure):
 
 
 class PixState(C.Structure):
-    _fields_ = [("t_final", C.c_void_p), ("n_last", C.c_void_p), ("n_contrib", C.c_void_p)]
+    _fields_ = [("t_final", C.c_void_p), ("n_last", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("visit", C.c_void_p), ("visit_words", C.c_int64)]
 
 
 class Grads(C.Structure):
@@ -58,7 +59,8 @@ class Grads(C.Structure):
                 ("d_opacity", C.c_void_p), ("d_gauss", C.c_void_p)]
 
 
-EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_sample", "bz_bin",
+EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_visit_words", "bz_sample",
+           "bz_bin",
            "bz_render_fwd", "bz_render_bwd", "bz_l2_grad", "bz_status_str")
 
 _lib = None
@@ -82,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.bz_workspace_size.argtypes = [P(Opts), C.c_int64, C.c_int64, P(C.c_int64)]
     lib.bz_num_tiles.restype = C.c_int
     lib.bz_num_tiles.argtypes = [P(Opts), P(C.c_int64)]
+    lib.bz_visit_words.restype = C.c_int
+    lib.bz_visit_words.argtypes = [P(Opts), C.c_int64, P(C.c_int64)]
     lib.bz_sample.restype = C.c_int
     lib.bz_sample.argtypes = [P(Curves), P(Opts), P(Gaussians), C.c_void_p]
     lib.bz_bin.restype = C.c_int
@@ -220,7 +224,6 @@ class Rasterizer:
         self.n_tiles = int(nt.value)
         self.ranges = torch.zeros(2 * self.n_tiles, dtype=torch.int32, device=self.dev)
         self.status = torch.zeros(4, dtype=torch.int64, device=self.dev)
-        self._alloc_pairs(cap_pairs if cap_pairs is not None else max(4 * self.n_gauss, 1 << 16))
         # image and state
         HW = self.W * self.H
         self.image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
@@ -228,7 +231,8 @@ class Rasterizer:
         self.n_last = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
         self.state = PixState(_ptr(self.t_final).value, _ptr(self.n_last).value,
-                              _ptr(self.n_contrib).value)
+                              _ptr(self.n_contrib).value, None, 0)
+        self._alloc_pairs(cap_pairs if cap_pairs is not None else max(4 * self.n_gauss, 1 << 16))
         # gradients
         self.d_image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
         self.d_ctrl = torch.empty_like(self.ctrl)
@@ -256,6 +260,11 @@ class Rasterizer:
         aligned = (base + 255) & ~255
         self.bins = Bins(cap, _ptr(self.ids).value, _ptr(self.ranges).value, aligned,
                          int(wsb.value), _ptr(self.status).value)
+        vw = C.c_int64(0)
+        _check("bz_visit_words", self.lib.bz_visit_words(C.byref(self.opts), cap, C.byref(vw)))
+        self.visit = torch.empty(int(vw.value), dtype=torch.int64, device=self.dev)
+        self.state.visit = _ptr(self.visit).value
+        self.state.visit_words = int(vw.value)
 
     def pairs_required(self) -> int:
         """Pair count of the last bz_bin (synchronises)."""

@@ -131,6 +131,14 @@ bz_status bz_num_tiles(const bz_opts *o, int64_t *n_tiles) {
     return BZ_OK;
 }
 
+bz_status bz_visit_words(const bz_opts *o, int64_t cap_pairs, int64_t *words) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!words || cap_pairs < 0 || cap_pairs >= (int64_t(1) << 32)) return BZ_ERR_ARG;
+    *words = visit_words(*o, cap_pairs);
+    return BZ_OK;
+}
+
 bz_status bz_workspace_size(const bz_opts *o, int64_t n_gauss, int64_t cap_pairs, int64_t *bytes) {
     bz_status st = check_opts(o);
     if (st != BZ_OK) return st;
@@ -169,7 +177,8 @@ bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *
     if (st != BZ_OK) return st;
     if (!g || g->n < 0 || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
     if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
-    if (!image || !state || !state->t_final || !state->n_last) return BZ_ERR_ARG;
+    if (!image || !state || !state->t_final || !state->n_last || !state->visit) return BZ_ERR_ARG;
+    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
     (void)hipGetLastError();
     return launched(launch_fwd(g->rec, *b, *o, image, *state, s));
 }
@@ -182,7 +191,10 @@ bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins
     if ((st = check_curves(c)) != BZ_OK) return st;
     if (!g || g->n != c->n_gauss || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
     if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
-    if (!d_image || !state || !state->t_final || !state->n_last || !gr) return BZ_ERR_ARG;
+    if (!d_image || !state || !state->t_final || !state->n_last || !state->visit || !gr)
+        return BZ_ERR_ARG;
+    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
+    if (!(o->alpha_max < 1.f)) return BZ_ERR_UNSUPPORTED;
     if (c->n_curves > 0 &&
         (!gr->d_ctrl || !gr->d_width || !gr->d_color || !gr->d_opacity || !gr->d_gauss))
         return BZ_ERR_ARG;

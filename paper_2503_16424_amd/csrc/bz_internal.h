@@ -72,4 +72,13 @@ BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap_pairs);
 inline int64_t tiles_x(const bz_opts &o) { return (o.width + o.tile_w - 1) / o.tile_w; }
 inline int64_t tiles_y(const bz_opts &o) { return (o.height + o.tile_h - 1) / o.tile_h; }
 
+// Visit masks: one plane per 8x8 quad of a tile; a plane holds, for every tile,
+// ceil(len/64) words starting at word start/64 + tile (see visit_word).
+inline int64_t visit_words_per_plane(const bz_opts &o, int64_t cap_pairs) {
+    return cap_pairs / 64 + tiles_x(o) * tiles_y(o) + 2;
+}
+inline int64_t visit_words(const bz_opts &o, int64_t cap_pairs) {
+    return (int64_t)(o.tile_w / 8) * (o.tile_h / 8) * visit_words_per_plane(o, cap_pairs);
+}
+
 }  // namespace bz

@@ -69,6 +69,8 @@ struct TileArgs {
     float *t_final;
     uint32_t *n_last;
     uint32_t *n_contrib;
+    uint64_t *visit;          // per (quad plane, tile batch) contribution masks
+    int64_t words_per_plane;
     // backward
     const float *d_image;
     float *d_gauss;
@@ -83,25 +85,40 @@ struct Staged {
     float4 c;   // r, g, b, o' * g_min
 };
 
-// Load entry j of the tile list, compute its LDS constants and its quad test.
-__device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, float qy0,
-                                   Staged &st) {
-    float4 m = a.rec[3 * (int64_t)id];
-    float4 q = a.rec[3 * (int64_t)id + 1];
-    float4 c = a.rec[3 * (int64_t)id + 2];
-    float op = q.w * a.inv_1mg;
+// Load a record and compute its LDS constants.
+__device__ inline void stage_record(const TileArgs &a, uint32_t id, Staged &st, float4 &q) {
+    const float4 m = a.rec[3 * (int64_t)id];
+    q = a.rec[3 * (int64_t)id + 1];
+    const float4 c = a.rec[3 * (int64_t)id + 2];
+    const float op = q.w * a.inv_1mg;
     st.m = m;
     st.q = make_float4(0.5f * kLog2e * q.x, kLog2e * q.y, 0.5f * kLog2e * q.z, op);
     st.c = make_float4(c.x, c.y, c.z, op * a.g_min);
-    float x0 = (qx0 - m.x) - m.z, y0 = (qy0 - m.y) - m.w;
+}
+
+// Load a tile-list entry, compute its LDS constants and test its support
+// against the wave's 8x8 quad (first pixel centre qx0, qy0).
+__device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, float qy0,
+                                   Staged &st) {
+    float4 q;
+    stage_record(a, id, st, q);
+    const float x0 = (qx0 - st.m.x) - st.m.z, y0 = (qy0 - st.m.y) - st.m.w;
     return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, q.x, q.y, q.z, a.box_thr);
+}
+
+// Word of the visit mask of batch k of tile t inside one quad plane: tile t's
+// batches occupy [start_t / 64 + t, start_t / 64 + t + ceil(len_t / 64)), which
+// never overlaps the next tile's range, so every word has one writer.
+__device__ inline int64_t visit_word(uint32_t start, int tile) {
+    return (int64_t)(start >> 6) + tile;
 }
 
 __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
     extern __shared__ Staged s_stage[];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
     if (tile >= a.n_tiles) return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int qx = w % a.quads_x, qy = w / a.quads_x;
     const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
@@ -127,13 +144,15 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
         return;
     }
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    uint64_t *vis = a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     uint32_t last = 0, cnt = 0;
     bool done = !valid;
     const float g_min = a.g_min, amax = a.alpha_max, tmin = a.t_min;
 
-    for (uint32_t base = start; base < end; base += 64) {
-        uint32_t j = base + lane;
+    uint32_t k = 0;
+    for (uint32_t base = start; base < end; base += 64, ++k) {
+        const uint32_t j = base + lane;
         bool hit = false;
         if (j < end) {
             Staged st;
@@ -141,29 +160,29 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
             my[lane] = st;
         }
         uint64_t mask = __ballot(hit);
+        uint64_t vbits = 0;
         wave_lds_sync();
         while (mask) {
             const int b = __builtin_ctzll(mask);
             mask &= mask - 1;
             const Staged st = my[b];
-            if (!done) {
-                float dx = (px - st.m.x) - st.m.z;
-                float dy = (py - st.m.y) - st.m.w;
-                float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
-                float G = __builtin_amdgcn_exp2f(-p2);
-                if (G > g_min) {
-                    float al = fminf(fmaf(st.q.w, G, -st.c.w), amax);
-                    float wgt = al * T;
-                    C0 = fmaf(wgt, st.c.x, C0);
-                    C1 = fmaf(wgt, st.c.y, C1);
-                    C2 = fmaf(wgt, st.c.z, C2);
-                    T = T * (1.f - al);
-                    last = base + b + 1 - start;
-                    cnt += 1;
-                    done = T < tmin;
-                }
-            }
+            const float dx = (px - st.m.x) - st.m.z;
+            const float dy = (py - st.m.y) - st.m.w;
+            const float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
+            const float G = __builtin_amdgcn_exp2f(-p2);
+            const bool c = !done && G > g_min;
+            const float al = c ? fminf(fmaf(st.q.w, G, -st.c.w), amax) : 0.f;
+            const float wgt = al * T;
+            C0 = fmaf(wgt, st.c.x, C0);
+            C1 = fmaf(wgt, st.c.y, C1);
+            C2 = fmaf(wgt, st.c.z, C2);
+            T = fmaf(-al, T, T);
+            last = c ? k * 64 + b + 1 : last;
+            cnt += c ? 1u : 0u;
+            done = done || T < tmin;
+            if (__ballot(c)) vbits |= 1ull << b;
         }
+        if (lane == 0) vis[k] = vbits;
         if (__ballot(!done) == 0) break;
         wave_lds_sync();
     }
@@ -265,7 +284,8 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
     if (tile >= a.n_tiles) return;
     if (a.status[1] & Status::kOverflow) return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int qx = w % a.quads_x, qy = w / a.quads_x;
     const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
@@ -273,12 +293,12 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
     const bool valid = x < a.W && y < a.H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
     uint32_t *my_ids = s_ids[w];
     uint32_t *my_slot = s_slot[w];
 
     const uint32_t start = a.ranges[2 * tile];
+    const uint64_t *vis = a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
     const int64_t pix = (int64_t)y * a.W + x;
     const int64_t plane = (int64_t)a.W * a.H;
     uint32_t nl = 0;
@@ -299,98 +319,77 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const int64_t ng = a.n_gauss;
     const int my_v = lane % 9, my_s = lane / 9;
 
-    int64_t hi = top;      // entries [0, hi) not yet staged
-    int64_t lo = 0;        // first entry of the staged batch
-    uint64_t mask = 0;     // staged entries not yet visited
-    bool more = true;
-    while (more) {
-        float acc[64];
+    // Batches are visited last to first; inside a batch, entries from the
+    // highest position down.  Only entries whose bit the forward pass set (at
+    // least one pixel of this quad used them) are staged and visited.
+    int64_t k = ((int64_t)top + 63) / 64;
+    uint64_t mask = 0;
+    uint32_t lo = 0;
+    // Slots not refilled in a round only feed sums that are never stored.
+    float acc[64];
 #pragma unroll
-        for (int i = 0; i < 64; ++i) acc[i] = 0.f;
+    for (int i = 0; i < 64; ++i) acc[i] = 0.f;
+    while (true) {
         int filled = 0;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            if (s == filled && more) {
-                bool got = false;
-                while (!got) {
-                    while (mask == 0 && hi > 0) {
-                        const int64_t nlo = hi - 64 > 0 ? hi - 64 : 0;
-                        const int64_t j = nlo + lane;
-                        bool hit = false;
+            if (s == filled) {
+                while (mask == 0 && k > 0) {
+                    --k;
+                    const uint64_t vm = vis[k];
+                    lo = (uint32_t)k * 64;
+                    if (vm != 0) {
                         wave_lds_sync();
-                        if (j < hi) {
-                            const uint32_t id = a.ids[start + j];
+                        if ((vm >> lane) & 1ull) {
+                            const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
-                            hit = stage_entry(a, id, qx0, qy0, st);
+                            float4 q;
+                            stage_record(a, id, st, q);
                             my[lane] = st;
                             my_ids[lane] = id;
                         }
-                        mask = __ballot(hit);
-                        lo = nlo;
-                        hi = nlo;
                         wave_lds_sync();
                     }
-                    if (mask == 0) {
-                        more = false;
-                        break;
-                    }
+                    mask = vm;
+                }
+                if (mask != 0) {
                     const int b = 63 - __builtin_clzll(mask);
                     mask &= ~(1ull << b);
                     const Staged st = my[b];
-                    const uint32_t pos = (uint32_t)(lo + b);
-                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
-                    float v6 = 0.f, v7 = 0.f, v8 = 0.f;
-                    bool contrib = false;
-                    if (pos < nl) {
-                        const float dx = (px - st.m.x) - st.m.z;
-                        const float dy = (py - st.m.y) - st.m.w;
-                        const float t1 = st.q.x * dx + st.q.y * dy;
-                        const float p2 = dx * t1 + st.q.z * dy * dy;
-                        const float G = __builtin_amdgcn_exp2f(-p2);
-                        if (G > g_min) {
-                            contrib = true;
-                            const float araw = fmaf(st.q.w, G, -st.c.w);
-                            const bool clamped = araw > amax;
-                            const float al = clamped ? amax : araw;
-                            const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
-                            const float wgt = al * Tb;
-                            v6 = wgt * g0;
-                            v7 = wgt * g1;
-                            v8 = wgt * g2;
-                            const float abar = Tb * ((st.c.x - A0) * g0 + (st.c.y - A1) * g1 +
-                                                     (st.c.z - A2) * g2);
-                            A0 = fmaf(al, st.c.x - A0, A0);
-                            A1 = fmaf(al, st.c.y - A1, A1);
-                            A2 = fmaf(al, st.c.z - A2, A2);
-                            T = Tb;
-                            if (!clamped) {
-                                v5 = abar * (G - g_min) * inv_1mg;
-                                const float pbar = -abar * st.q.w * G;
-                                const float pl = pbar * ln2;
-                                v0 = -pl * (t1 + st.q.x * dx);
-                                v1 = -pl * (st.q.y * dx + 2.f * st.q.z * dy);
-                                const float ph = 0.5f * pbar;
-                                v2 = ph * dx * dx;
-                                v3 = pbar * dx * dy;
-                                v4 = ph * dy * dy;
-                            }
-                        }
-                    }
-                    if (__ballot(contrib) != 0) {
-                        got = true;
-                        acc[9 * s + 0] = v0;
-                        acc[9 * s + 1] = v1;
-                        acc[9 * s + 2] = v2;
-                        acc[9 * s + 3] = v3;
-                        acc[9 * s + 4] = v4;
-                        acc[9 * s + 5] = v5;
-                        acc[9 * s + 6] = v6;
-                        acc[9 * s + 7] = v7;
-                        acc[9 * s + 8] = v8;
-                        if (lane == 0) my_slot[s] = my_ids[b];
-                    }
+                    const uint32_t pos = lo + (uint32_t)b;
+                    const float dx = (px - st.m.x) - st.m.z;
+                    const float dy = (py - st.m.y) - st.m.w;
+                    const float t1 = st.q.x * dx + st.q.y * dy;
+                    const float p2 = dx * t1 + st.q.z * dy * dy;
+                    const float G = __builtin_amdgcn_exp2f(-p2);
+                    const bool c = pos < nl && G > g_min;
+                    const float araw = fmaf(st.q.w, G, -st.c.w);
+                    const bool shaped = c && araw <= amax;       // alpha not clamped
+                    const float al = c ? fminf(araw, amax) : 0.f;
+                    const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
+                    const float wgt = al * Tb;
+                    const float e0 = st.c.x - A0, e1 = st.c.y - A1, e2 = st.c.z - A2;
+                    const float abar = c ? Tb * (e0 * g0 + e1 * g1 + e2 * g2) : 0.f;
+                    A0 = fmaf(al, e0, A0);
+                    A1 = fmaf(al, e1, A1);
+                    A2 = fmaf(al, e2, A2);
+                    T = Tb;
+                    const float f = shaped ? abar : 0.f;
+                    const float pbar = -f * st.q.w * G;
+                    const float pl = pbar * ln2;
+                    const float ph = 0.5f * pbar;
+                    acc[9 * s + 0] = -pl * (t1 + st.q.x * dx);
+                    acc[9 * s + 1] = -pl * (st.q.y * dx + 2.f * st.q.z * dy);
+                    acc[9 * s + 2] = ph * dx * dx;
+                    acc[9 * s + 3] = pbar * dx * dy;
+                    acc[9 * s + 4] = ph * dy * dy;
+                    acc[9 * s + 5] = f * (G - g_min) * inv_1mg;
+                    acc[9 * s + 6] = wgt * g0;
+                    acc[9 * s + 7] = wgt * g1;
+                    acc[9 * s + 8] = wgt * g2;
+                    if (lane == 0) my_slot[s] = my_ids[b];
+                    filled = s + 1;
                 }
-                if (got) filled = s + 1;
             }
         }
         if (filled == 0) break;
@@ -596,6 +595,7 @@ TileArgs tile_args(const float *rec, const bz_bins &b, const bz_opts &o) {
     a.t_min = o.t_min;
     a.inv_1mg = 1.0f / (1.0f - o.g_min);
     a.box_thr = 2.0f * (-logf(o.g_min)) * kCullSlackQuad;
+    a.words_per_plane = visit_words_per_plane(o, b.cap_pairs);
     return a;
 }
 
@@ -608,6 +608,7 @@ hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, floa
     a.t_final = st.t_final;
     a.n_last = st.n_last;
     a.n_contrib = st.n_contrib;
+    a.visit = st.visit;
     int threads = o.tile_w * o.tile_h;
     size_t lds = sizeof(Staged) * (size_t)threads;
     hipLaunchKernelGGL(k_fwd, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
@@ -626,6 +627,7 @@ hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, con
     TileArgs a = tile_args(rec, b, o);
     a.t_final = st.t_final;
     a.n_last = st.n_last;
+    a.visit = st.visit;
     a.d_image = d_image;
     a.d_gauss = gr.d_gauss;
     a.n_gauss = n_gauss;

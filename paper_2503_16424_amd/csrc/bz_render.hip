@@ -113,6 +113,7 @@ __device__ inline int64_t visit_word(uint32_t start, int tile) {
     return (int64_t)(start >> 6) + tile;
 }
 
+template <bool kCount>
 __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
     extern __shared__ Staged s_stage[];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
@@ -171,14 +172,15 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
             const float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
             const float G = __builtin_amdgcn_exp2f(-p2);
             const bool c = !done && G > g_min;
-            const float al = c ? fminf(fmaf(st.q.w, G, -st.c.w), amax) : 0.f;
+            const float araw = fmaf(st.q.w, G, -st.c.w);
+            const float al = c ? (araw < amax ? araw : amax) : 0.f;
             const float wgt = al * T;
             C0 = fmaf(wgt, st.c.x, C0);
             C1 = fmaf(wgt, st.c.y, C1);
             C2 = fmaf(wgt, st.c.z, C2);
             T = fmaf(-al, T, T);
             last = c ? k * 64 + b + 1 : last;
-            cnt += c ? 1u : 0u;
+            if (kCount) cnt += c ? 1u : 0u;
             done = done || T < tmin;
             if (__ballot(c)) vbits |= 1ull << b;
         }
@@ -194,6 +196,15 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
         a.n_last[pix] = last;
         if (a.n_contrib) a.n_contrib[pix] = cnt;
     }
+}
+
+// Broadcast lane 0's 64-bit value as a wave-uniform (scalar) value.  The
+// builtin returns a signed int: each half goes through uint32_t so that the
+// low half is zero-extended, not sign-extended into the high word.
+__device__ inline uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
 }
 
 __device__ inline float wave_sum(float v) {
@@ -280,7 +291,6 @@ constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
 __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_ids[16][64];
-    __shared__ uint32_t s_slot[16][8];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
     if (tile >= a.n_tiles) return;
     if (a.status[1] & Status::kOverflow) return;
@@ -295,9 +305,9 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     Staged *my = s_stage + w * 64;
     uint32_t *my_ids = s_ids[w];
-    uint32_t *my_slot = s_slot[w];
 
     const uint32_t start = a.ranges[2 * tile];
+    const uint32_t len = a.ranges[2 * tile + 1] - start;
     const uint64_t *vis = a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
     const int64_t pix = (int64_t)y * a.W + x;
     const int64_t plane = (int64_t)a.W * a.H;
@@ -314,10 +324,15 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     uint32_t top = nl;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
+    top = (uint32_t)__builtin_amdgcn_readfirstlane((int)top);   // equal in all lanes
+    top = top < len ? top : len;
     const float g_min = a.g_min, amax = a.alpha_max, inv_1mg = a.inv_1mg;
     const float ln2 = 0.69314718056f;
     const int64_t ng = a.n_gauss;
     const int my_v = lane % 9, my_s = lane / 9;
+    uint32_t slot_id[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) slot_id[i] = 0;
 
     // Batches are visited last to first; inside a batch, entries from the
     // highest position down.  Only entries whose bit the forward pass set (at
@@ -336,8 +351,11 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
             if (s == filled) {
                 while (mask == 0 && k > 0) {
                     --k;
-                    const uint64_t vm = vis[k];
+                    const uint64_t vraw = vis[k];
                     lo = (uint32_t)k * 64;
+                    // only entries of this tile's list can be visited
+                    const uint32_t avail = len - lo;
+                    const uint64_t vm = uniform_u64(vraw) & (avail >= 64 ? ~0ull : ((1ull << avail) - 1ull));
                     if (vm != 0) {
                         wave_lds_sync();
                         if ((vm >> lane) & 1ull) {
@@ -365,7 +383,7 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
                     const bool c = pos < nl && G > g_min;
                     const float araw = fmaf(st.q.w, G, -st.c.w);
                     const bool shaped = c && araw <= amax;       // alpha not clamped
-                    const float al = c ? fminf(araw, amax) : 0.f;
+                    const float al = c ? (araw < amax ? araw : amax) : 0.f;
                     const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
                     const float wgt = al * Tb;
                     const float e0 = st.c.x - A0, e1 = st.c.y - A1, e2 = st.c.z - A2;
@@ -387,15 +405,17 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
                     acc[9 * s + 6] = wgt * g0;
                     acc[9 * s + 7] = wgt * g1;
                     acc[9 * s + 8] = wgt * g2;
-                    if (lane == 0) my_slot[s] = my_ids[b];
+                    slot_id[s] = (uint32_t)__builtin_amdgcn_readfirstlane((int)my_ids[b]);
                     filled = s + 1;
                 }
             }
         }
         if (filled == 0) break;
-        wave_lds_sync();
         const float r = reduce_scatter64(acc, lane);
-        if (lane < 9 * filled) atomicAdd(a.d_gauss + (int64_t)my_v * ng + my_slot[my_s], r);
+        uint32_t my_id = slot_id[0];
+#pragma unroll
+        for (int i = 1; i < kSlots; ++i) my_id = my_s == i ? slot_id[i] : my_id;
+        if (lane < 9 * filled) atomicAdd(a.d_gauss + (int64_t)my_v * ng + my_id, r);
     }
 }
 
@@ -611,7 +631,10 @@ hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, floa
     a.visit = st.visit;
     int threads = o.tile_w * o.tile_h;
     size_t lds = sizeof(Staged) * (size_t)threads;
-    hipLaunchKernelGGL(k_fwd, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    if (st.n_contrib)
+        hipLaunchKernelGGL(k_fwd<true>, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_fwd<false>, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

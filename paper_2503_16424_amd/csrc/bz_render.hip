@@ -71,6 +71,7 @@ struct TileArgs {
     uint32_t *n_contrib;
     uint64_t *visit;          // per (quad plane, tile batch) contribution masks
     int64_t words_per_plane;
+    int tab_cap;              // positions of the backward's per-tile sum table
     // backward
     const float *d_image;
     float *d_gauss;
@@ -277,6 +278,7 @@ __device__ inline float reduce_scatter64(float (&v)[64], int lane) {
 }
 
 constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
+constexpr int kTableCap = 640;   // tile-list positions pooled in LDS by the backward
 
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
 // its pixels used down to the first.  Per pixel and contributor (reverse
@@ -289,22 +291,29 @@ constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
 // wave in one transposed reduction and added to the per-Gaussian planes with
 // one 63-lane atomic instruction.
 __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
-    extern __shared__ Staged s_stage[];
+    extern __shared__ Staged s_stage[];   // [waves][64] staged records, then the sum table
     __shared__ uint32_t s_ids[16][64];
+    __shared__ uint32_t s_top[16];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
-    if (tile >= a.n_tiles) return;
-    if (a.status[1] & Status::kOverflow) return;
+    if (tile >= a.n_tiles) return;                       // whole block
+    if (a.status[1] & Status::kOverflow) return;         // whole block
+    const int nwaves = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int qx = w % a.quads_x, qy = w / a.quads_x;
     const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
-    if (x0 >= a.W || y0 >= a.H) return;
+    const bool wave_on = x0 < a.W && y0 < a.H;           // quad inside the canvas
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
-    const bool valid = x < a.W && y < a.H;
+    const bool valid = wave_on && x < a.W && y < a.H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     Staged *my = s_stage + w * 64;
     uint32_t *my_ids = s_ids[w];
+    // Per-tile sums, plane-major [9][tab_cap], indexed by tile-list position:
+    // the quads of a tile share most of their Gaussians, so their sums meet
+    // here and leave the block with one global atomic per (Gaussian, plane).
+    const int tab_cap = a.tab_cap;
+    float *table = reinterpret_cast<float *>(s_stage + nwaves * 64);
 
     const uint32_t start = a.ranges[2 * tile];
     const uint32_t len = a.ranges[2 * tile + 1] - start;
@@ -326,18 +335,32 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
     top = (uint32_t)__builtin_amdgcn_readfirstlane((int)top);   // equal in all lanes
     top = top < len ? top : len;
+    if (lane == 0) s_top[w] = top;
+    __syncthreads();
+    uint32_t top_block = 0;
+    for (int i = 0; i < nwaves; ++i) top_block = max(top_block, s_top[i]);
+    const int tab_n = (int)(top_block < (uint32_t)tab_cap ? top_block : (uint32_t)tab_cap);
+    for (int i = threadIdx.x; i < 9 * tab_n; i += blockDim.x) {
+        const int v = i / tab_n;
+        table[v * tab_cap + (i - v * tab_n)] = 0.f;
+    }
+    __syncthreads();
+
     const float g_min = a.g_min, amax = a.alpha_max, inv_1mg = a.inv_1mg;
     const float ln2 = 0.69314718056f;
     const int64_t ng = a.n_gauss;
     const int my_v = lane % 9, my_s = lane / 9;
-    uint32_t slot_id[kSlots];
+    uint32_t slot_id[kSlots], slot_pos[kSlots];
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i) slot_id[i] = 0;
+    for (int i = 0; i < kSlots; ++i) {
+        slot_id[i] = 0;
+        slot_pos[i] = 0;
+    }
 
     // Batches are visited last to first; inside a batch, entries from the
     // highest position down.  Only entries whose bit the forward pass set (at
     // least one pixel of this quad used them) are staged and visited.
-    int64_t k = ((int64_t)top + 63) / 64;
+    int64_t k = wave_on ? ((int64_t)top + 63) / 64 : 0;
     uint64_t mask = 0;
     uint32_t lo = 0;
     // Slots not refilled in a round only feed sums that are never stored.
@@ -406,16 +429,31 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
                     acc[9 * s + 7] = wgt * g1;
                     acc[9 * s + 8] = wgt * g2;
                     slot_id[s] = (uint32_t)__builtin_amdgcn_readfirstlane((int)my_ids[b]);
+                    slot_pos[s] = pos;
                     filled = s + 1;
                 }
             }
         }
         if (filled == 0) break;
         const float r = reduce_scatter64(acc, lane);
-        uint32_t my_id = slot_id[0];
+        uint32_t my_id = slot_id[0], my_pos = slot_pos[0];
 #pragma unroll
-        for (int i = 1; i < kSlots; ++i) my_id = my_s == i ? slot_id[i] : my_id;
-        if (lane < 9 * filled) atomicAdd(a.d_gauss + (int64_t)my_v * ng + my_id, r);
+        for (int i = 1; i < kSlots; ++i) {
+            my_id = my_s == i ? slot_id[i] : my_id;
+            my_pos = my_s == i ? slot_pos[i] : my_pos;
+        }
+        if (lane < 9 * filled) {
+            if (my_pos < (uint32_t)tab_cap)
+                atomicAdd(&table[my_v * tab_cap + my_pos], r);
+            else
+                atomicAdd(a.d_gauss + (int64_t)my_v * ng + my_id, r);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 9 * tab_n; i += blockDim.x) {
+        const int v = i / tab_n, p = i - v * tab_n;
+        const float val = table[v * tab_cap + p];
+        if (val != 0.f) atomicAdd(a.d_gauss + (int64_t)v * ng + a.ids[start + p], val);
     }
 }
 
@@ -655,7 +693,8 @@ hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, con
     a.d_gauss = gr.d_gauss;
     a.n_gauss = n_gauss;
     int threads = o.tile_w * o.tile_h;
-    size_t lds = sizeof(Staged) * (size_t)threads;
+    a.tab_cap = kTableCap;
+    size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * 9 * (size_t)kTableCap;
     hipLaunchKernelGGL(k_bwd_tiles, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
     if (c.n_curves > 0) {
         size_t lds2 = 2 * sizeof(double2) * (size_t)c.max_k +

@@ -60,7 +60,7 @@ bz_status check_bins(const bz_bins *b, const bz_opts *o, int64_t n_gauss, bool n
 bz_status launched(hipError_t e) { return e == hipSuccess ? BZ_OK : BZ_ERR_HIP; }
 
 int64_t stage2_lds(const bz_curves *c) {
-    return 2 * 16 * (int64_t)c->max_k + 8 * (int64_t)c->max_gauss_per_curve + 8 * 6 * kMaxSeg;
+    return stage2_lds_bytes(c->max_k, c->max_gauss_per_curve);
 }
 
 }  // namespace
@@ -118,8 +118,7 @@ bz_status bz_layout_host(int32_t n, const int32_t *kind, const int32_t *nseg,
     if (max_gauss) *max_gauss = mg;
     if (max_k) *max_k = mk;
     if (unsupported != BZ_OK) return unsupported;
-    if (2 * 16 * (int64_t)mk + 8 * (int64_t)mg + 8 * 6 * kMaxSeg > kMaxLdsBytes)
-        return BZ_ERR_UNSUPPORTED;
+    if (stage2_lds_bytes(mk, mg) > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
     return BZ_OK;
 }
 

@@ -204,16 +204,44 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
                                               int tiles_x, uint32_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals,
                                               const int64_t *status) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n || (status[1] & Status::kOverflow)) return;
-    ushort4 rc = rects[g];
-    uint32_t o = offs[g];
-    for (int ty = rc.y; ty <= rc.w; ++ty)
-        for (int tx = rc.x; tx <= rc.z; ++tx) {
-            keys[o] = (uint32_t)(ty * tiles_x + tx);
-            vals[o] = (uint32_t)g;
-            ++o;
+    // The 256 Gaussians of a block own one contiguous output range (their
+    // scan offsets are consecutive), so the block writes that range with
+    // consecutive threads on consecutive positions; each position finds its
+    // Gaussian by binary search over the block's offsets in LDS.
+    __shared__ uint32_t s_off[257];
+    __shared__ ushort4 s_rect[256];
+    if (status[1] & Status::kOverflow) return;
+    const int64_t g0 = (int64_t)blockIdx.x * 256;
+    const int nb = (int)(n - g0 < 256 ? n - g0 : 256);
+    const int t = threadIdx.x;
+    if (t < nb) {
+        s_off[t] = offs[g0 + t];
+        s_rect[t] = rects[g0 + t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        const ushort4 rc = s_rect[nb - 1];
+        const uint32_t c = rc.x <= rc.z && rc.y <= rc.w
+                               ? (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1)
+                               : 0u;
+        s_off[nb] = s_off[nb - 1] + c;
+    }
+    __syncthreads();
+    const uint32_t begin = s_off[0], total = s_off[nb] - begin;
+    for (uint32_t i = t; i < total; i += 256) {
+        const uint32_t o = begin + i;
+        int lo = 0, hi = nb - 1;                 // last Gaussian whose offset <= o
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= o) lo = mid; else hi = mid - 1;
         }
+        const ushort4 rc = s_rect[lo];
+        const uint32_t w = (uint32_t)(rc.z - rc.x + 1);
+        const uint32_t li = o - s_off[lo];
+        const uint32_t ty = rc.y + li / w, tx = rc.x + li % w;
+        keys[o] = ty * (uint32_t)tiles_x + tx;
+        vals[o] = (uint32_t)(g0 + lo);
+    }
 }
 
 // --- stable LSD radix sort on tile ids --------------------------------------

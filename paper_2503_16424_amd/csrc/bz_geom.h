@@ -66,6 +66,14 @@ __device__ inline double2 ctrl_point(const CurveView &v, bool boundary_b, int jj
     return make_double2((double)v.P[2 * idx], (double)v.P[2 * idx + 1]);
 }
 
+// Copy a closed curve's row weights into LDS (rows <= 256) and point the view
+// at the copy; sample_at reads them for every sample point.
+__device__ inline void stage_tau(CurveView &v, float *s_tau, int lane, int nlanes) {
+    if (v.kind != BZ_CLOSED) return;
+    for (int r = lane; r < v.rows; r += nlanes) s_tau[r] = v.tau[r];
+    v.tau = s_tau;
+}
+
 // Boundary samples XA[k] (and XB[k] for closed curves) into LDS.
 __device__ inline void boundary_samples(const CurveView &v, double2 *XA, double2 *XB, int lane,
                                         int nlanes) {

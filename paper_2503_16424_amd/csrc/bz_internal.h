@@ -23,6 +23,9 @@ constexpr int kQuad = 8;
 // Largest number of segments per curve handled by the per-curve kernels.
 constexpr int kMaxSeg = 4;
 
+// Threads of the per-curve kernels (one workgroup per curve).
+constexpr int kCurveThreads = 256;
+
 // log2(e)
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -71,6 +74,13 @@ BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap_pairs);
 
 inline int64_t tiles_x(const bz_opts &o) { return (o.width + o.tile_w - 1) / o.tile_w; }
 inline int64_t tiles_y(const bz_opts &o) { return (o.height + o.tile_h - 1) / o.tile_h; }
+
+// LDS of the per-curve backward: boundary samples (2 x double2 per column),
+// Bernstein weights and segment per column, sample-point gradients and the
+// four per-Gaussian stencil terms (float2 each).
+inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
+    return 2 * 16 * max_k + 16 * max_k + 4 * max_k + 5 * 8 * max_gauss;
+}
 
 // Visit masks: one plane per 8x8 quad of a tile; a plane holds, for every tile,
 // ceil(len/64) words starting at word start/64 + tile (see visit_word).

@@ -463,79 +463,110 @@ __global__ void k_zero(float *p, int64_t n) {
     for (; i < n; i += stride) p[i] = 0.f;
 }
 
-// Stage 2: one wave per curve.  Per Gaussian (r, k) the gradients of
+// Stage 2: one workgroup per curve.  Per Gaussian (r, k) the gradients of
 // (mean, Q, o, colour) are chained to the sample points of its stencil:
 //   Q = R diag(a, b) R^T, a = 1/sx2, b = 1/sy2, (c, s) = v/|v|,
 //   sx2 = |X[r][ka]-X[r][kb]|^2/rho^2 + s0, sy2 = |X[ra][k]-X[rb][k]|^2/rho^2 + s0
-//   (closed) or w^2 + s0 (open), mean = X[r][k];
-// the sample-point gradients (LDS, ds_add) then go to the control points:
-// X[r][k] = sum_j B_j(t_k) ((1-tau_r) A_{3s+j} + tau_r B_{3s+j}).
-__global__ __launch_bounds__(64) void k_bwd_curves(bz_curves c, double inv_rho2, double s0,
-                                                   const float *__restrict__ d_gauss,
-                                                   int64_t ng, float *__restrict__ d_ctrl,
-                                                   float *__restrict__ d_width,
-                                                   float *__restrict__ d_color,
-                                                   float *__restrict__ d_opacity) {
+//   (closed) or w^2 + s0 (open), mean = X[r][k].
+// Each Gaussian stores its four stencil terms (mean, along-row, across-row,
+// tangent) in LDS; every sample point then gathers the terms that reference
+// it (the exact inverse of the stencil's index rules), so no atomics are
+// needed and the result is deterministic.  The sample-point gradients then go
+// to the control points: X[r][k] = sum_j B_j(t_k) ((1-tau_r) A_{3s+j} + tau_r B_{3s+j}).
+// Sample points and their differences are double precision (coordinates of
+// thousands of pixels, differences of a pixel); the chain itself is float.
+__global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, double inv_rho2,
+                                                              double s0,
+                                                              const float *__restrict__ d_gauss,
+                                                              int64_t ng, float *__restrict__ d_ctrl,
+                                                              float *__restrict__ d_width,
+                                                              float *__restrict__ d_color,
+                                                              float *__restrict__ d_opacity) {
     extern __shared__ double2 lds_xy[];
+    __shared__ float s_tau[256];
+    __shared__ float s_red[kCurveThreads / 64][8];
+    __shared__ float s_cp[kCurveThreads / 64][2][3 * kMaxSeg + 1][2];
+    constexpr int NT = kCurveThreads;
     const int p = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x;          // thread of the curve's workgroup
     CurveView v = load_curve_view(c, p);
+    stage_tau(v, s_tau, lane, NT);
+    const int mg = c.max_gauss_per_curve;
     double2 *XA = lds_xy;
     double2 *XB = lds_xy + c.max_k;
-    float *Xbar = reinterpret_cast<float *>(lds_xy + 2 * c.max_k);   // [rows*K][2]
-    float *Pacc = Xbar + 2 * c.max_gauss_per_curve;                  // [6*kMaxSeg][2]
-    boundary_samples(v, XA, XB, lane, 64);
+    float4 *Bw = reinterpret_cast<float4 *>(lds_xy + 2 * c.max_k);     // [K] Bernstein weights
+    int *Bs = reinterpret_cast<int *>(Bw + c.max_k);                   // [K] segment of column k
+    float2 *Xbar = reinterpret_cast<float2 *>(Bs + c.max_k);           // [rows*K]
+    float2 *Tm = Xbar + mg;                                            // mean term
+    float2 *Tf = Tm + mg;                                              // along-row term
+    float2 *Th = Tf + mg;                                              // across-row term
+    float2 *Tv = Th + mg;                                              // tangent term
+    boundary_samples(v, XA, XB, lane, NT);
+    for (int k = lane; k < v.K; k += NT) {
+        int s;
+        double t, B[4];
+        column_param(k, v.K, v.S, s, t);
+        bernstein3(t, B);
+        Bw[k] = make_float4((float)B[0], (float)B[1], (float)B[2], (float)B[3]);
+        Bs[k] = s;
+    }
     const int n = v.rows * v.K;
-    for (int i = lane; i < 2 * n; i += 64) Xbar[i] = 0.f;
     __syncthreads();
 
     float wbar = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
     float ob[kMaxSeg] = {0.f, 0.f, 0.f, 0.f};
-    const double rho2i = inv_rho2;
-    for (int idx = lane; idx < n; idx += 64) {
-        int r = idx / v.K, k = idx - r * v.K;
-        int64_t g = v.g0 + idx;
+    const float rho2f = (float)inv_rho2;
+    const bool closed = v.kind == BZ_CLOSED;
+    const int K = v.K, R1 = v.R + 1;
+    for (int idx = lane; idx < n; idx += NT) {
+        const int r = idx / K, k = idx - r * K;
         float dg[kGradPlanes];
 #pragma unroll
-        for (int q = 0; q < kGradPlanes; ++q) dg[q] = d_gauss[q * ng + g];
-        Geom ge;
-        gauss_geom(v, XA, XB, r, k, inv_rho2, s0, ge);
-        double a = 1.0 / ge.sx2, b = 1.0 / ge.sy2, cs = ge.cs, sn = ge.sn;
-        double qxx = dg[2], qxy = dg[3], qyy = dg[4];
-        double abar = qxx * cs * cs + qxy * cs * sn + qyy * sn * sn;
-        double bbar = qxx * sn * sn - qxy * cs * sn + qyy * cs * cs;
-        double cbar_t = qxx * 2.0 * cs * a + qxy * sn * (a - b) + qyy * 2.0 * cs * b;
-        double sbar_t = qxx * 2.0 * sn * b + qxy * cs * (a - b) + qyy * 2.0 * sn * a;
-        double sx2bar = -abar * a * a;
-        double sy2bar = -bbar * b * b;
-        atomicAdd(&Xbar[2 * idx], dg[0]);
-        atomicAdd(&Xbar[2 * idx + 1], dg[1]);
-        float f = (float)(2.0 * sx2bar * rho2i);
-        float fx = f * (float)ge.d_along.x, fy = f * (float)ge.d_along.y;
-        atomicAdd(&Xbar[2 * (r * v.K + ge.ka)], fx);
-        atomicAdd(&Xbar[2 * (r * v.K + ge.ka) + 1], fy);
-        atomicAdd(&Xbar[2 * (r * v.K + ge.kb)], -fx);
-        atomicAdd(&Xbar[2 * (r * v.K + ge.kb) + 1], -fy);
-        if (v.kind == BZ_CLOSED) {
-            float h = (float)(2.0 * sy2bar * rho2i);
-            float hx = h * (float)ge.d_across.x, hy = h * (float)ge.d_across.y;
-            atomicAdd(&Xbar[2 * (ge.ra * v.K + k)], hx);
-            atomicAdd(&Xbar[2 * (ge.ra * v.K + k) + 1], hy);
-            atomicAdd(&Xbar[2 * (ge.rb * v.K + k)], -hx);
-            atomicAdd(&Xbar[2 * (ge.rb * v.K + k) + 1], -hy);
+        for (int q = 0; q < kGradPlanes; ++q) dg[q] = d_gauss[q * ng + v.g0 + idx];
+        // stencil (Eq. sigma with nearest-neighbour ends, Eq. rotation)
+        const int ka = k < K - 1 ? k + 1 : K - 1, kb = k < K - 1 ? k : K - 2;
+        const int kp = k + 1 < K ? k + 1 : K - 1, km = k > 0 ? k - 1 : 0;
+        const double2 Xa = sample_at(v, XA, XB, r, ka), Xb = sample_at(v, XA, XB, r, kb);
+        const double2 Xp = sample_at(v, XA, XB, r, kp), Xm = sample_at(v, XA, XB, r, km);
+        const float dax = (float)(Xa.x - Xb.x), day = (float)(Xa.y - Xb.y);
+        const float vx = (float)(Xp.x - Xm.x), vy = (float)(Xp.y - Xm.y);
+        const float sx2 = (dax * dax + day * day) * rho2f + (float)s0;
+        float dyx = 0.f, dyy = 0.f, sy2;
+        if (closed) {
+            const int ra = r < R1 ? r + 1 : R1, rb = r < R1 ? r : R1 - 1;
+            const double2 Ya = sample_at(v, XA, XB, ra, k), Yb = sample_at(v, XA, XB, rb, k);
+            dyx = (float)(Ya.x - Yb.x);
+            dyy = (float)(Ya.y - Yb.y);
+            sy2 = (dyx * dyx + dyy * dyy) * rho2f + (float)s0;
         } else {
-            wbar += (float)(2.0 * (double)v.width * sy2bar);
+            sy2 = v.width * v.width + (float)s0;
         }
-        if (ge.nv > 0.0) {
-            double hd = cs * cbar_t + sn * sbar_t;
-            float vb0 = (float)((cbar_t - cs * hd) / ge.nv);
-            float vb1 = (float)((sbar_t - sn * hd) / ge.nv);
-            atomicAdd(&Xbar[2 * (r * v.K + ge.kp)], vb0);
-            atomicAdd(&Xbar[2 * (r * v.K + ge.kp) + 1], vb1);
-            atomicAdd(&Xbar[2 * (r * v.K + ge.km)], -vb0);
-            atomicAdd(&Xbar[2 * (r * v.K + ge.km) + 1], -vb1);
+        const float nv2 = vx * vx + vy * vy;
+        const float inv_nv = nv2 > 0.f ? __frsqrt_rn(nv2) : 0.f;
+        const float cs = nv2 > 0.f ? vx * inv_nv : 1.f, sn = nv2 > 0.f ? vy * inv_nv : 0.f;
+        const float ia = 1.f / sx2, ib = 1.f / sy2;
+        const float qxx = dg[2], qxy = dg[3], qyy = dg[4];
+        const float abar = qxx * cs * cs + qxy * cs * sn + qyy * sn * sn;
+        const float bbar = qxx * sn * sn - qxy * cs * sn + qyy * cs * cs;
+        const float cbar_t = qxx * 2.f * cs * ia + qxy * sn * (ia - ib) + qyy * 2.f * cs * ib;
+        const float sbar_t = qxx * 2.f * sn * ib + qxy * cs * (ia - ib) + qyy * 2.f * sn * ia;
+        const float f = 2.f * (-abar * ia * ia) * rho2f;
+        const float sy2bar = -bbar * ib * ib;
+        Tm[idx] = make_float2(dg[0], dg[1]);
+        Tf[idx] = make_float2(f * dax, f * day);
+        if (closed) {
+            const float h = 2.f * sy2bar * rho2f;
+            Th[idx] = make_float2(h * dyx, h * dyy);
+        } else {
+            wbar += 2.f * v.width * sy2bar;
         }
-        int slot = v.nopa == v.S ? ge.seg : 0;
+        if (nv2 > 0.f) {
+            const float hd = cs * cbar_t + sn * sbar_t;
+            Tv[idx] = make_float2((cbar_t - cs * hd) * inv_nv, (sbar_t - sn * hd) * inv_nv);
+        } else {
+            Tv[idx] = make_float2(0.f, 0.f);
+        }
+        const int slot = v.nopa == v.S ? Bs[k] : 0;
 #pragma unroll
         for (int q = 0; q < kMaxSeg; ++q)
             if (q == slot) ob[q] += dg[5];
@@ -543,14 +574,54 @@ __global__ __launch_bounds__(64) void k_bwd_curves(bz_curves c, double inv_rho2,
         cb1 += dg[7];
         cb2 += dg[8];
     }
+    __syncthreads();
+    // Gather: the terms each sample point (r, k) receives.
+    //  along  +Tf(j) where ka(j) = k: j = k-1 (k >= 1), and j = K-1 when k = K-1
+    //         -Tf(j) where kb(j) = k: j = k (k < K-1), and j = K-1 when k = K-2
+    //  tangent+Tv(j) where kp(j) = k: j = k-1 (k >= 1), and j = K-1 when k = K-1
+    //         -Tv(j) where km(j) = k: j = k+1 (k < K-1), and j = 0 when k = 0
+    //  across +Th(i) where ra(i) = r: i = r-1 (r >= 1), and i = R+1 when r = R+1
+    //         -Th(i) where rb(i) = r: i = r (r <= R), and i = R+1 when r = R
+    for (int idx = lane; idx < n; idx += NT) {
+        const int r = idx / K, k = idx - r * K;
+        const int row = r * K;
+        float2 x = Tm[idx];
+        float ax = 0.f, ay = 0.f;
+        if (k >= 1) { ax += Tf[row + k - 1].x + Tv[row + k - 1].x; ay += Tf[row + k - 1].y + Tv[row + k - 1].y; }
+        if (k == K - 1) { ax += Tf[row + K - 1].x + Tv[row + K - 1].x; ay += Tf[row + K - 1].y + Tv[row + K - 1].y; }
+        if (k < K - 1) { ax -= Tf[row + k].x + Tv[row + k + 1].x; ay -= Tf[row + k].y + Tv[row + k + 1].y; }
+        if (k == K - 2) { ax -= Tf[row + K - 1].x; ay -= Tf[row + K - 1].y; }
+        if (k == 0) { ax -= Tv[row].x; ay -= Tv[row].y; }
+        if (closed) {
+            if (r >= 1) { ax += Th[idx - K].x; ay += Th[idx - K].y; }
+            if (r == R1) { ax += Th[idx].x; ay += Th[idx].y; }
+            if (r <= R1 - 1) { ax -= Th[idx].x; ay -= Th[idx].y; }
+            if (r == R1 - 1) { ax -= Th[idx + K].x; ay -= Th[idx + K].y; }
+        }
+        Xbar[idx] = make_float2(x.x + ax, x.y + ay);
+    }
+
+    // per-curve sums: wave reduction, then across the workgroup's waves
     wbar = wave_sum(wbar);
     cb0 = wave_sum(cb0);
     cb1 = wave_sum(cb1);
     cb2 = wave_sum(cb2);
 #pragma unroll
     for (int q = 0; q < kMaxSeg; ++q) ob[q] = wave_sum(ob[q]);
+    if ((lane & 63) == 0) {
+        float *sr = s_red[lane >> 6];
+        sr[0] = wbar; sr[1] = cb0; sr[2] = cb1; sr[3] = cb2;
+#pragma unroll
+        for (int q = 0; q < kMaxSeg; ++q) sr[4 + q] = ob[q];
+    }
+    __syncthreads();
     if (lane == 0) {
-        d_width[v.id] = v.kind == BZ_CLOSED ? 0.f : wbar;
+        for (int wv = 1; wv < NT / 64; ++wv) {
+            wbar += s_red[wv][0]; cb0 += s_red[wv][1]; cb1 += s_red[wv][2]; cb2 += s_red[wv][3];
+#pragma unroll
+            for (int q = 0; q < kMaxSeg; ++q) ob[q] += s_red[wv][4 + q];
+        }
+        d_width[v.id] = closed ? 0.f : wbar;
         d_color[3 * v.id] = cb0;
         d_color[3 * v.id + 1] = cb1;
         d_color[3 * v.id + 2] = cb2;
@@ -560,51 +631,74 @@ __global__ __launch_bounds__(64) void k_bwd_curves(bz_curves c, double inv_rho2,
             if (q < v.nopa) dop[q] = ob[q];
     }
 
-    // Control points.  Lanes own (row, coordinate) pairs and accumulate the
-    // gradient of the row's own control points, Pbar[jj] = sum_k B_{jj-3s_k}(t_k)
-    // Xbar[r][k]; the stored points then receive them with the row weights:
-    // open -> as is; closed -> A_j gets (1 - tau_r) (all of it at the shared
-    // endpoints), the interior points of B get tau_r.
+    // Control points.  Thread t owns row r = t/2 (and r + NT/2, ...) and
+    // coordinate t&1; it accumulates the gradient of the row's own control
+    // points, sum_k B_{jj-3s_k}(t_k) Xbar[r][k], weighted for the stored points:
+    // open -> as is; closed -> A_jj with (1 - tau_r) (all of it at the shared
+    // endpoints), B's interior points with tau_r.  Sums over rows are
+    // parity-split wave reductions (lanes 0 and 1 end with the x and y sums).
     const int m = 3 * v.S;
-    const int nstore = v.kind == BZ_CLOSED ? 2 * m : m + 1;
-    for (int t = lane; t < 2 * nstore; t += 64) Pacc[t] = 0.f;
-    __syncthreads();
-    for (int t = lane; t < 2 * v.rows; t += 64) {
-        const int coord = t & 1, r = t >> 1;
+    float accA[3 * kMaxSeg + 1], accB[3 * kMaxSeg + 1];
+#pragma unroll
+    for (int j = 0; j < 3 * kMaxSeg + 1; ++j) accA[j] = accB[j] = 0.f;
+    for (int t = lane; t < 2 * v.rows; t += NT) {
+        const int coord = t & 1, rr = t >> 1;
         float acc[3 * kMaxSeg + 1];
 #pragma unroll
         for (int j = 0; j < 3 * kMaxSeg + 1; ++j) acc[j] = 0.f;
-        for (int k = 0; k < v.K; ++k) {
-            int s;
-            double tt, B[4];
-            column_param(k, v.K, v.S, s, tt);
-            bernstein3(tt, B);
-            const float xb = Xbar[2 * (r * v.K + k) + coord];
+        for (int kk = 0; kk < K; ++kk) {
+            const float4 B = Bw[kk];
+            const int s = Bs[kk];
+            const float2 xb2 = Xbar[rr * K + kk];
+            const float xb = coord ? xb2.y : xb2.x;
 #pragma unroll
             for (int s2 = 0; s2 < kMaxSeg; ++s2) {
                 if (s2 == s) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[3 * s2 + j] += (float)B[j] * xb;
+                    acc[3 * s2 + 0] += B.x * xb;
+                    acc[3 * s2 + 1] += B.y * xb;
+                    acc[3 * s2 + 2] += B.z * xb;
+                    acc[3 * s2 + 3] += B.w * xb;
                 }
             }
         }
-        const float tr = v.kind == BZ_CLOSED ? v.tau[r] : 0.f;
+        const float tr = closed ? v.tau[rr] : 0.f;
 #pragma unroll
         for (int jj = 0; jj < 3 * kMaxSeg + 1; ++jj) {
-            if (jj <= m) {
-                const float gv = acc[jj];
-                if (v.kind != BZ_CLOSED || jj == 0 || jj == m) {
-                    atomicAdd(&Pacc[2 * jj + coord], gv);
-                } else {
-                    atomicAdd(&Pacc[2 * jj + coord], (1.f - tr) * gv);
-                    atomicAdd(&Pacc[2 * (m + jj) + coord], tr * gv);
-                }
+            if (!closed || jj == 0 || jj == m) {
+                accA[jj] += acc[jj];
+            } else {
+                accA[jj] += (1.f - tr) * acc[jj];
+                accB[jj] += tr * acc[jj];
+            }
+        }
+    }
+    __syncthreads();   // Xbar reads done before s_cp is written
+#pragma unroll
+    for (int jj = 0; jj < 3 * kMaxSeg + 1; ++jj) {
+        if (jj <= m) {
+            float sa = accA[jj], sb = accB[jj];
+#pragma unroll
+            for (int d = 32; d >= 2; d >>= 1) {
+                sa += __shfl_xor(sa, d, 64);
+                sb += __shfl_xor(sb, d, 64);
+            }
+            if ((lane & 63) < 2) {
+                s_cp[lane >> 6][0][jj][lane & 1] = sa;
+                s_cp[lane >> 6][1][jj][lane & 1] = sb;
             }
         }
     }
     __syncthreads();
+    const int nstore = closed ? 2 * m : m + 1;
     float *out = d_ctrl + 2 * (int64_t)c.ctrl_off[v.id];
-    for (int t = lane; t < 2 * nstore; t += 64) out[t] = Pacc[t];
+    for (int t = lane; t < 2 * nstore; t += NT) {
+        const int coord = t & 1, j = t >> 1;
+        const int which = j <= m ? 0 : 1;       // A (or open) points, then B's interior
+        const int jj = j <= m ? j : j - m;
+        float sum = 0.f;
+        for (int wv = 0; wv < NT / 64; ++wv) sum += s_cp[wv][which][jj][coord];
+        out[t] = sum;
+    }
 }
 
 __global__ void k_loss_zero(float *loss) {
@@ -697,11 +791,9 @@ hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, con
     size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * 9 * (size_t)kTableCap;
     hipLaunchKernelGGL(k_bwd_tiles, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
     if (c.n_curves > 0) {
-        size_t lds2 = 2 * sizeof(double2) * (size_t)c.max_k +
-                      2 * sizeof(float) * (size_t)c.max_gauss_per_curve +
-                      2 * sizeof(float) * (size_t)(6 * kMaxSeg);
+        size_t lds2 = stage2_lds_bytes(c.max_k, c.max_gauss_per_curve);
         double rho = (double)o.rho;
-        hipLaunchKernelGGL(k_bwd_curves, dim3(c.n_curves), dim3(64), lds2, s, c,
+        hipLaunchKernelGGL(k_bwd_curves, dim3(c.n_curves), dim3(kCurveThreads), lds2, s, c,
                            1.0 / (rho * rho), (double)o.sigma0_sq, (const float *)gr.d_gauss,
                            n_gauss, gr.d_ctrl, gr.d_width, gr.d_color, gr.d_opacity);
     }

@@ -1,6 +1,6 @@
 // bz_sample.hip -- curves -> 2D Gaussians (Sec. 3.3).
 //
-// One 64-lane workgroup (one wave) per curve, in draw order.  The boundary
+// One workgroup per curve, in draw order.  The boundary
 // rows are evaluated once per curve in double precision (LDS), every lane then
 // emits Gaussians (r, k) of the curve: mean in double, split into a float
 // high part and a float low part; squared scales from the neighbour distances
@@ -11,15 +11,17 @@
 
 namespace bz {
 
-__global__ __launch_bounds__(64) void k_sample(bz_curves c, double inv_rho2, double s0,
+__global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double inv_rho2, double s0,
                                                float4 *__restrict__ rec) {
     extern __shared__ double2 lds_xy[];
+    __shared__ float s_tau[256];
     const int p = blockIdx.x;
     const int lane = threadIdx.x;
     CurveView v = load_curve_view(c, p);
+    stage_tau(v, s_tau, lane, kCurveThreads);
     double2 *XA = lds_xy;
     double2 *XB = lds_xy + c.max_k;
-    boundary_samples(v, XA, XB, lane, 64);
+    boundary_samples(v, XA, XB, lane, kCurveThreads);
     __syncthreads();
 
     const float *col = c.color + 3 * (int64_t)v.id;
@@ -27,7 +29,7 @@ __global__ __launch_bounds__(64) void k_sample(bz_curves c, double inv_rho2, dou
     const float *opa = c.opacity + c.opa_off[v.id];
     const float cid = __int_as_float(v.id);
     const int n = v.rows * v.K;
-    for (int idx = lane; idx < n; idx += 64) {
+    for (int idx = lane; idx < n; idx += kCurveThreads) {
         int r = idx / v.K, k = idx - r * v.K;
         Geom g;
         gauss_geom(v, XA, XB, r, k, inv_rho2, s0, g);
@@ -49,7 +51,7 @@ hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipSt
     if (c.n_curves == 0) return hipSuccess;
     size_t lds = 2 * sizeof(double2) * (size_t)c.max_k;
     double rho = (double)o.rho;
-    hipLaunchKernelGGL(k_sample, dim3(c.n_curves), dim3(64), lds, s, c, 1.0 / (rho * rho),
+    hipLaunchKernelGGL(k_sample, dim3(c.n_curves), dim3(kCurveThreads), lds, s, c, 1.0 / (rho * rho),
                        (double)o.sigma0_sq, reinterpret_cast<float4 *>(rec));
     return hipGetLastError();
 }

@@ -58,6 +58,25 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel, workload, tw, th):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE x its copy-calibrated factor + WRITE_SIZE x its factor),
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{tw}x{th}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    src = os.path.join(ROOT, "paper_2503_16424_amd", "csrc", kv.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if digest != kv.get("source_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(sc, target, rows):
     """Time the FP64 oracle on a band of rows of the same workload and scale
     to one full step (sampling and the per-curve chain are timed whole)."""
@@ -133,7 +152,9 @@ def main():
     torch.cuda.synchronize()
     print(f"# warmup done, {need} pairs", file=sys.stderr, flush=True)
 
-    stages = ["sample", "bin", "fwd", "l2", "bwd"]
+    stages = ["sample", "bin", "fwd", "l2", "bwd_gauss", "bwd_curves"]
+    calls = [r.sample, r.bin, r.forward, lambda: r.l2_grad(tgt), r.backward_gauss,
+             r.backward_curves]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
           for _ in range(a.steps)]
     torch.cuda.synchronize()
@@ -141,16 +162,9 @@ def main():
     for i in range(a.steps):
         e = ev[i]
         e[0].record()
-        r.sample()
-        e[1].record()
-        r.bin()
-        e[2].record()
-        r.forward()
-        e[3].record()
-        r.l2_grad(tgt)
-        e[4].record()
-        r.backward()
-        e[5].record()
+        for j, call in enumerate(calls):
+            call()
+            e[j + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = sum(ev[i][0].elapsed_time(ev[i][-1]) for i in range(a.steps)) / a.steps
@@ -167,15 +181,20 @@ def main():
           f"contributing pairs {n_alg}; mse {loss:.5f}", file=sys.stderr, flush=True)
 
     # Roofline of the dominant stage's kernel.
-    dom = max(("fwd", "bwd", "bin", "sample"), key=lambda s: stage_ms[s])
+    dom = max(("fwd", "bwd_gauss", "bwd_curves", "bin", "sample"), key=lambda s: stage_ms[s])
     if dom == "fwd":
         ach = n_alg * FLOPS_FWD_PAIR / (stage_ms["fwd"] * 1e-3) / 1e12
         roof = dict(kernel="k_fwd (bz_render_fwd)", bound="alu", achieved=ach,
                     peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
-    elif dom == "bwd":
-        ach = n_alg * FLOPS_BWD_PAIR / (stage_ms["bwd"] * 1e-3) / 1e12
-        roof = dict(kernel="bz_render_bwd (k_bwd_tiles + k_bwd_curves)", bound="alu",
-                    achieved=ach, peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
+    elif dom == "bwd_gauss":
+        ach = n_alg * FLOPS_BWD_PAIR / (stage_ms["bwd_gauss"] * 1e-3) / 1e12
+        roof = dict(kernel="k_bwd_tiles (bz_render_bwd_gauss, with its d_gauss clear)",
+                    bound="alu", achieved=ach, peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
+    elif dom == "bwd_curves":
+        byts = sc.n_gauss * 36
+        ach = byts / (stage_ms["bwd_curves"] * 1e-3) / 1e9
+        roof = dict(kernel="k_bwd_curves", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
+                    unit="GB/s")
     elif dom == "bin":
         byts = sc.n_gauss * 28 + need * 4 + r.n_tiles * 8
         ach = byts / (stage_ms["bin"] * 1e-3) / 1e9
@@ -185,7 +204,7 @@ def main():
         ach = byts / (stage_ms["sample"] * 1e-3) / 1e9
         roof = dict(kernel="k_sample", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(roof["kernel"].split()[0], a.workload, tw, th)
 
     out = {
         "metric": METRIC,

@@ -222,6 +222,21 @@ bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins
                         const bz_opts *opts, const float *d_image, const bz_pixstate *state,
                         bz_grads *grads, hipStream_t stream);
 
+/* Stage 1 of bz_render_bwd alone: per-Gaussian gradients into d_gauss (9 planes
+ * of g->n floats, overwritten), the derivative of the blending of Sec. 3.4.
+ * For callers that want gradients with respect to the Gaussians themselves. */
+bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_opts *opts,
+                              const float *d_image, const bz_pixstate *state, float *d_gauss,
+                              hipStream_t stream);
+
+/* Stage 2 of bz_render_bwd alone: chain per-Gaussian gradients d_gauss (9
+ * planes of c->n_gauss floats, as written by bz_render_bwd_gauss, possibly
+ * modified by the caller) through the sampling of Sec. 3.3 into
+ * grads->d_ctrl, d_width, d_color, d_opacity (overwritten; grads->d_gauss is
+ * ignored).  Deterministic. */
+bz_status bz_render_bwd_curves(const bz_curves *c, const bz_opts *opts, const float *d_gauss,
+                               bz_grads *grads, hipStream_t stream);
+
 /* Mean squared error loss of Sec. 3.5 (the L2 term): d_image = scale*(image - target)
  * elementwise over n floats, and loss[0] = sum (image - target)^2 accumulated
  * (loss is zeroed by the call; may be NULL). */

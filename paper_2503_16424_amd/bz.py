@@ -61,7 +61,8 @@ class Grads(C.Structure):
 
 EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_visit_words", "bz_sample",
            "bz_bin",
-           "bz_render_fwd", "bz_render_bwd", "bz_l2_grad", "bz_status_str")
+           "bz_render_fwd", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
+           "bz_l2_grad", "bz_status_str")
 
 _lib = None
 
@@ -96,6 +97,11 @@ def load_library(path: str = LIB_PATH):
     lib.bz_render_bwd.restype = C.c_int
     lib.bz_render_bwd.argtypes = [P(Curves), P(Gaussians), P(Bins), P(Opts), C.c_void_p,
                                   P(PixState), P(Grads), C.c_void_p]
+    lib.bz_render_bwd_gauss.restype = C.c_int
+    lib.bz_render_bwd_gauss.argtypes = [P(Gaussians), P(Bins), P(Opts), C.c_void_p, P(PixState),
+                                        C.c_void_p, C.c_void_p]
+    lib.bz_render_bwd_curves.restype = C.c_int
+    lib.bz_render_bwd_curves.argtypes = [P(Curves), P(Opts), C.c_void_p, P(Grads), C.c_void_p]
     lib.bz_l2_grad.restype = C.c_int
     lib.bz_l2_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p,
                                C.c_void_p, C.c_void_p]
@@ -302,6 +308,19 @@ class Rasterizer:
                                                        C.byref(self.bins), C.byref(self.opts),
                                                        _ptr(d), C.byref(self.state),
                                                        C.byref(self.grads), _stream()))
+
+    def backward_gauss(self, d_image=None):
+        """Stage 1 only: per-Gaussian gradients into ``d_gauss``."""
+        d = self.d_image if d_image is None else d_image
+        _check("bz_render_bwd_gauss", self.lib.bz_render_bwd_gauss(
+            C.byref(self.gauss), C.byref(self.bins), C.byref(self.opts), _ptr(d),
+            C.byref(self.state), _ptr(self.d_gauss), _stream()))
+
+    def backward_curves(self):
+        """Stage 2 only: ``d_gauss`` -> per-curve gradients."""
+        _check("bz_render_bwd_curves", self.lib.bz_render_bwd_curves(
+            C.byref(self.curves), C.byref(self.opts), _ptr(self.d_gauss), C.byref(self.grads),
+            _stream()))
 
     def l2_grad(self, target, scale=None):
         """d_image = scale (image - target), scale defaults to 2 / (3 H W) (mean

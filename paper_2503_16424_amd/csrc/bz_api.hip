@@ -182,24 +182,45 @@ bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *
     return launched(launch_fwd(g->rec, *b, *o, image, *state, s));
 }
 
+bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_opts *o,
+                              const float *d_image, const bz_pixstate *state, float *d_gauss,
+                              hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!g || g->n < 0 || (g->n > 0 && (!g->rec || !d_gauss))) return BZ_ERR_ARG;
+    if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
+    if (!d_image || !state || !state->t_final || !state->n_last || !state->visit)
+        return BZ_ERR_ARG;
+    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
+    if (!(o->alpha_max < 1.f)) return BZ_ERR_UNSUPPORTED;
+    (void)hipGetLastError();
+    return launched(launch_bwd_gauss(g->rec, g->n, *b, *o, d_image, *state, d_gauss, s));
+}
+
+bz_status bz_render_bwd_curves(const bz_curves *c, const bz_opts *o, const float *d_gauss,
+                               bz_grads *gr, hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if ((st = check_curves(c)) != BZ_OK) return st;
+    if (!gr) return BZ_ERR_ARG;
+    if (c->n_curves > 0 &&
+        (!d_gauss || !gr->d_ctrl || !gr->d_width || !gr->d_color || !gr->d_opacity))
+        return BZ_ERR_ARG;
+    if (c->n_curves > 0 && stage2_lds(c) > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
+    (void)hipGetLastError();
+    return launched(launch_bwd_curves(*c, *o, d_gauss, *gr, s));
+}
+
 bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins *b,
                         const bz_opts *o, const float *d_image, const bz_pixstate *state,
                         bz_grads *gr, hipStream_t s) {
     bz_status st = check_opts(o);
     if (st != BZ_OK) return st;
     if ((st = check_curves(c)) != BZ_OK) return st;
-    if (!g || g->n != c->n_gauss || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
-    if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
-    if (!d_image || !state || !state->t_final || !state->n_last || !state->visit || !gr)
-        return BZ_ERR_ARG;
-    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
-    if (!(o->alpha_max < 1.f)) return BZ_ERR_UNSUPPORTED;
-    if (c->n_curves > 0 &&
-        (!gr->d_ctrl || !gr->d_width || !gr->d_color || !gr->d_opacity || !gr->d_gauss))
-        return BZ_ERR_ARG;
-    if (c->n_curves > 0 && stage2_lds(c) > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
-    (void)hipGetLastError();
-    return launched(launch_bwd(*c, g->rec, g->n, *b, *o, d_image, *state, *gr, s));
+    if (!g || g->n != c->n_gauss) return BZ_ERR_ARG;
+    if (!gr || (c->n_curves > 0 && !gr->d_gauss)) return BZ_ERR_ARG;
+    if ((st = bz_render_bwd_gauss(g, b, o, d_image, state, gr->d_gauss, s)) != BZ_OK) return st;
+    return bz_render_bwd_curves(c, o, gr->d_gauss, gr, s);
 }
 
 bz_status bz_l2_grad(const float *image, const float *target, int64_t n, float scale,

@@ -49,9 +49,11 @@ hipError_t launch_bin(const float *rec, int64_t n_gauss, const bz_opts &o, const
                       hipStream_t s);
 hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
                       const bz_pixstate &st, hipStream_t s);
-hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, const bz_bins &b,
-                      const bz_opts &o, const float *d_image, const bz_pixstate &st,
-                      const bz_grads &gr, hipStream_t s);
+hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
+                            const bz_opts &o, const float *d_image, const bz_pixstate &st,
+                            float *d_gauss, hipStream_t s);
+hipError_t launch_bwd_curves(const bz_curves &c, const bz_opts &o, const float *d_gauss,
+                             const bz_grads &gr, hipStream_t s);
 hipError_t launch_l2(const float *image, const float *target, int64_t n, float scale,
                      float *d_image, float *loss, hipStream_t s);
 

@@ -770,32 +770,37 @@ hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, floa
     return hipGetLastError();
 }
 
-hipError_t launch_bwd(const bz_curves &c, const float *rec, int64_t n_gauss, const bz_bins &b,
-                      const bz_opts &o, const float *d_image, const bz_pixstate &st,
-                      const bz_grads &gr, hipStream_t s) {
+hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
+                            const bz_opts &o, const float *d_image, const bz_pixstate &st,
+                            float *d_gauss, hipStream_t s) {
     int64_t nz = (int64_t)kGradPlanes * n_gauss;
     if (nz > 0) {
         int64_t blocks = cdiv(nz, 256);
         if (blocks > 16384) blocks = 16384;
-        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, gr.d_gauss, nz);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, d_gauss, nz);
     }
     TileArgs a = tile_args(rec, b, o);
     a.t_final = st.t_final;
     a.n_last = st.n_last;
     a.visit = st.visit;
     a.d_image = d_image;
-    a.d_gauss = gr.d_gauss;
+    a.d_gauss = d_gauss;
     a.n_gauss = n_gauss;
     int threads = o.tile_w * o.tile_h;
     a.tab_cap = kTableCap;
     size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * 9 * (size_t)kTableCap;
     hipLaunchKernelGGL(k_bwd_tiles, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_curves(const bz_curves &c, const bz_opts &o, const float *d_gauss,
+                             const bz_grads &gr, hipStream_t s) {
     if (c.n_curves > 0) {
         size_t lds2 = stage2_lds_bytes(c.max_k, c.max_gauss_per_curve);
         double rho = (double)o.rho;
         hipLaunchKernelGGL(k_bwd_curves, dim3(c.n_curves), dim3(kCurveThreads), lds2, s, c,
-                           1.0 / (rho * rho), (double)o.sigma0_sq, (const float *)gr.d_gauss,
-                           n_gauss, gr.d_ctrl, gr.d_width, gr.d_color, gr.d_opacity);
+                           1.0 / (rho * rho), (double)o.sigma0_sq, d_gauss, c.n_gauss, gr.d_ctrl,
+                           gr.d_width, gr.d_color, gr.d_opacity);
     }
     return hipGetLastError();
 }

@@ -263,3 +263,35 @@ def test_paper_scale_sampled_parity(torch_cuda):
     err = np.abs(img[:, ys, xs].T - p["rgb"]).max()
     _note(f"  sampled pixels max err {err:.3e}")
     assert err <= IMG_TOL
+
+
+def test_split_backward_stages_match_combined_call(torch_cuda):
+    """bz_render_bwd_gauss followed by bz_render_bwd_curves gives the same
+    gradients as bz_render_bwd; the per-curve stage is deterministic."""
+    import torch
+    sc = SCENES["mixed_small_b"]()
+    o0 = oracle.forward_backward(sc)
+    dimg = torch.as_tensor(_upstream(sc, o0["image"]), device="cuda")
+    r = _rast(sc)
+    r.render()
+    r.backward(dimg)
+    torch.cuda.synchronize()
+    combined = {k: getattr(r, k).clone() for k in ("d_ctrl", "d_width", "d_color", "d_opacity")}
+    r.backward_gauss(dimg)
+    dg = r.d_gauss.clone()
+    r.backward_curves()
+    first = {k: getattr(r, k).clone() for k in combined}
+    r.backward_curves()
+    torch.cuda.synchronize()
+    for k in combined:
+        assert torch.equal(first[k], getattr(r, k)), f"{k}: stage 2 not deterministic"
+        assert rel_l2(first[k].cpu().numpy(), combined[k].cpu().numpy()) <= 1e-6, k
+    # stage 2 alone on the oracle's own per-Gaussian gradients
+    o = oracle.forward_backward(sc, dimg.cpu().numpy().astype(np.float64))
+    r.d_gauss[: 9 * sc.n_gauss].copy_(
+        torch.as_tensor(o["d_gauss"].T.astype(np.float32).reshape(-1), device="cuda"))
+    r.backward_curves()
+    torch.cuda.synchronize()
+    for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
+        assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= 1e-5, k
+    assert rel_l2(dg[: 9 * sc.n_gauss].cpu().numpy(), o["d_gauss"].T.reshape(-1)) <= GRAD_TOL

@@ -287,6 +287,20 @@ class Rasterizer:
             return True
         return False
 
+    # -- parameters --------------------------------------------------------------
+    def set_params(self, ctrl=None, stroke_w=None, color=None, opacity=None):
+        """Copy new curve parameters into the device buffers the curve set points
+        at (shapes must match; the layout - kinds, S, K, R, draw order - is fixed
+        at construction)."""
+        for dst, src in ((self.ctrl, ctrl), (self.stroke_w, stroke_w), (self.color, color),
+                         (self.opacity, opacity)):
+            if src is None:
+                continue
+            src = self.torch.as_tensor(src, device=self.dev)
+            if src.numel() != dst.numel():
+                raise ValueError(f"parameter has {src.numel()} values, the curve set {dst.numel()}")
+            dst.copy_(src.detach().reshape(dst.shape))
+
     # -- library calls ---------------------------------------------------------
     def sample(self):
         _check("bz_sample", self.lib.bz_sample(C.byref(self.curves), C.byref(self.opts),

@@ -1,0 +1,191 @@
+"""Differentiation and optimisation on top of libbz (Sec. 3.5).
+
+* :class:`BzRender` -- a ``torch.autograd.Function``: curve parameters in,
+  image out; its backward runs ``bz_render_bwd`` on the incoming image
+  gradient, so any torch loss can sit on top of the rasterizer.
+* :func:`fit` -- the image-vectorisation loop of Sec. 3.5 / Sec. 4.1: a
+  gradient optimiser (Adam by default) on control points, colours, opacities
+  and stroke widths against the mean squared error.  Each step is sample + bin
+  + forward + L2 gradient + backward in libbz; torch supplies the optimiser
+  update and device memory.
+
+Control points are optimised in the normalised coordinates [-1, 1]^2 of the
+canvas (x_n = 2 x / W - 1, the coordinates of the paper's SVG export), to
+which the control-point learning rate refers; the chain factor W/2 (H/2) is
+applied to the pixel-space gradient.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import bz
+
+
+class BzRender(torch.autograd.Function):
+    """image [3, H, W] = render(ctrl, stroke_w, color, opacity) through ``rast``.
+
+    ``BzRender.apply(rast, ctrl, stroke_w, color, opacity)``: the four tensors
+    (shapes of ``rast.ctrl`` etc.) are copied into the rasterizer's curve
+    buffers, the scene is sampled, binned (growing the pair buffer when it
+    overflows) and blended.  The backward returns the gradients of all four;
+    the draw order, kinds, segment and sample counts stay those of ``rast``.
+    The returned image is a fresh tensor; one rasterizer serves one graph at a
+    time (its blend state is kept for the backward).
+    """
+
+    @staticmethod
+    def forward(ctx, rast, ctrl, stroke_w, color, opacity):
+        rast.set_params(ctrl=ctrl, stroke_w=stroke_w, color=color, opacity=opacity)
+        img = rast.render()
+        ctx.rast = rast
+        return img.clone()
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        rast = ctx.rast
+        rast.backward(grad_img.contiguous())
+        return (None, rast.d_ctrl.clone(), rast.d_width.clone(), rast.d_color.clone(),
+                rast.d_opacity.clone())
+
+
+def psnr_from_mse(mse: float) -> float:
+    """Peak signal-to-noise ratio of images in [0, 1]."""
+    return float("inf") if mse <= 0 else 10.0 * math.log10(1.0 / mse)
+
+
+@dataclass
+class FitConfig:
+    steps: int = 500
+    optimizer: str = "adam"     # "adam" or "sgd"
+    lr_ctrl: float = 1e-2       # normalised coordinates
+    lr_color: float = 1e-2      # Sec. 4.1
+    lr_opacity: float = 1e-1    # Sec. 4.1
+    lr_width: float = 1e-2      # px (the paper states none)
+    min_width: float = 0.5      # px
+    log_every: int = 50         # PSNR / timing samples
+    check_every: int = 10       # pair-buffer overflow checks (each one synchronises)
+
+
+@dataclass
+class FitResult:
+    psnr: list = field(default_factory=list)        # (step, PSNR of that step's render)
+    fwd_ms: list = field(default_factory=list)      # sample + bin + forward, per logged step
+    bwd_ms: list = field(default_factory=list)      # L2 gradient + backward, per logged step
+    opt_ms: list = field(default_factory=list)      # optimiser update, per logged step
+    step_ms: float = 0.0                            # wall clock per step over the loop
+    final_psnr: float = 0.0
+    regrown: int = 0                                # pair-buffer growths during the loop
+
+
+class Fitter:
+    """Parameters, optimiser and rasterizer of one optimisation."""
+
+    def __init__(self, rast: "bz.Rasterizer", cfg: FitConfig | None = None):
+        self.rast, self.cfg = rast, cfg or FitConfig()
+        self.half = torch.tensor([rast.W / 2.0, rast.H / 2.0], device=rast.dev)
+        self.ctrl_n = torch.nn.Parameter(rast.ctrl / self.half - 1.0)
+        self.color = torch.nn.Parameter(rast.color.clone())
+        self.opacity = torch.nn.Parameter(rast.opacity.clone())
+        self.width = torch.nn.Parameter(rast.stroke_w.clone())
+        c = self.cfg
+        groups = [{"params": [self.ctrl_n], "lr": c.lr_ctrl},
+                  {"params": [self.color], "lr": c.lr_color},
+                  {"params": [self.opacity], "lr": c.lr_opacity},
+                  {"params": [self.width], "lr": c.lr_width}]
+        if c.optimizer == "adam":
+            self.opt = torch.optim.Adam(groups)
+        elif c.optimizer == "sgd":
+            self.opt = torch.optim.SGD(groups)
+        else:
+            raise ValueError(f"unknown optimizer {c.optimizer!r}")
+
+    def push(self):
+        """Parameters -> the rasterizer's curve buffers."""
+        with torch.no_grad():
+            self.rast.set_params(ctrl=(self.ctrl_n + 1.0) * self.half, color=self.color,
+                                 opacity=self.opacity, stroke_w=self.width)
+
+    def update(self):
+        """One optimiser step from the rasterizer's last backward, then the
+        box constraints (colours and opacities in [0, 1], widths >= min)."""
+        r = self.rast
+        self.ctrl_n.grad = r.d_ctrl * self.half
+        self.color.grad = r.d_color.clone()
+        self.opacity.grad = r.d_opacity.clone()
+        self.width.grad = r.d_width.clone()
+        self.opt.step()
+        with torch.no_grad():
+            self.color.clamp_(0.0, 1.0)
+            self.opacity.clamp_(0.0, 1.0)
+            self.width.clamp_(min=self.cfg.min_width)
+
+    def params_host(self) -> dict:
+        """Current parameters in the rasterizer's units (px for points)."""
+        with torch.no_grad():
+            return dict(ctrl=((self.ctrl_n + 1.0) * self.half).cpu().numpy(),
+                        color=self.color.cpu().numpy(), opacity=self.opacity.cpu().numpy(),
+                        stroke_w=self.width.cpu().numpy())
+
+
+def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=None) -> FitResult:
+    """Optimise the curve parameters of ``rast`` against ``target`` ([3, H, W]
+    float32 on the device) for ``cfg.steps`` steps; the rasterizer ends up
+    holding the optimised parameters.
+
+    The pair buffer is checked for overflow every ``check_every`` steps (and
+    on logged steps); a step whose binning overflowed is binned again with the
+    grown buffer before its gradient is used.  A step that overflows between
+    checks yields zero gradients (libbz skips blending on overflow)."""
+    f = Fitter(rast, cfg)
+    cfg = f.cfg
+    res = FitResult()
+    n = 3 * rast.W * rast.H
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(cfg.steps):
+        f.push()
+        logged = step % cfg.log_every == 0 or step == cfg.steps - 1
+        if logged:
+            ev[0].record()
+        rast.sample()
+        rast.bin()
+        if (logged or step % cfg.check_every == 0) and rast.ensure_capacity():
+            res.regrown += 1
+            rast.bin()
+        rast.forward()
+        if logged:
+            ev[1].record()
+        rast.l2_grad(target)
+        rast.backward()
+        if logged:
+            ev[2].record()
+        f.update()
+        if logged:
+            ev[3].record()
+            res.psnr.append((step, psnr_from_mse(float(rast.loss.item()) / n)))
+            res.fwd_ms.append(ev[0].elapsed_time(ev[1]))
+            res.bwd_ms.append(ev[1].elapsed_time(ev[2]))
+            res.opt_ms.append(ev[2].elapsed_time(ev[3]))
+            if callback:
+                callback(step, res.psnr[-1][1])
+    torch.cuda.synchronize()
+    res.step_ms = (time.perf_counter() - t0) * 1000.0 / max(cfg.steps, 1)
+    f.push()
+    rast.render()
+    rast.l2_grad(target)
+    res.final_psnr = psnr_from_mse(float(rast.loss.item()) / n)
+    return res
+
+
+def noisy_target(clean, seed_noise: int = 2, sigma: float = 0.02):
+    """Optimisation target of the 512x512 workload: a clean render of the hidden
+    curve set plus N(0, sigma^2) noise, clipped to [0, 1] ([3, H, W] float32)."""
+    from . import scenes
+    c = np.asarray(clean, np.float64)
+    return np.clip(c + scenes.gaussian_noise(seed_noise, c.shape, sigma), 0.0, 1.0).astype(np.float32)

@@ -272,3 +272,8 @@ WORKLOADS = {
     "open_512": open_512,
     "paper_2048": paper_2048,
 }
+
+
+def gaussian_noise(seed: int, shape, sigma: float) -> np.ndarray:
+    """Additive N(0, sigma^2) noise of the given shape (float64), seeded."""
+    return np.random.default_rng(seed).normal(0.0, sigma, shape)

@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--workload", default="paper_2048", choices=["paper_2048", "open_512",
                                                                  "tiny_128"])
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--blend-state", default="stored", choices=["stored", "recompute"],
+                    help="keep the forward's per-pixel blend state for the backward, or "
+                         "recompute it per tile inside the backward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the timed steps, copy a MIB-sized buffer once (a known-size "
@@ -131,10 +134,17 @@ def main():
         sc, target = scenes.tiny_128(0), scenes.tiny_128_target(0)
     print(f"# workload {sc.name}: {sc.n_curves} curves, {sc.n_gauss} Gaussians", file=sys.stderr,
           flush=True)
-    r = bz.Rasterizer(sc, bz.RenderOptions(tile_w=tw, tile_h=th), device="cuda:0")
+    ro = bz.RenderOptions(tile_w=tw, tile_h=th)
+    r = bz.Rasterizer(sc, ro, device="cuda:0")
     tgt = torch.as_tensor(target, device=dev)
     r.render()                                    # sizes the pair buffer (synchronises)
     need = r.pairs_required()
+    # contributing (pixel, Gaussian) pairs, from the stored state's counters
+    n_alg = int(r.n_contrib.to(torch.int64).sum().item())
+    if a.blend_state == "recompute":
+        del r
+        torch.cuda.empty_cache()
+        r = bz.Rasterizer(sc, ro, device="cuda:0", blend_state="recompute")
     if need * 1.1 > r.cap_pairs:
         r._alloc_pairs(int(need * 1.1) + 1024)
     for _ in range(a.warmup):
@@ -174,7 +184,6 @@ def main():
     flags = r.flags()
     if flags & bz.STATUS_OVERFLOW:
         raise RuntimeError("pair buffer overflowed during the timed steps")
-    n_alg = int(r.n_contrib.to(torch.int64).sum().item())
     loss = float(r.loss.item()) / (3 * sc.width * sc.height)
     print(f"# {a.steps} steps: {ms_per_step:.3f} ms/step wall, {gpu_ms:.3f} ms/step events; "
           f"stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}; "
@@ -221,7 +230,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "canvas": [sc.width, sc.height],
                    "curves": sc.n_curves, "gaussians": sc.n_gauss, "seed": 0,
-                   "tile": [tw, th], "parallelism": "single GPU"},
+                   "tile": [tw, th], "blend_state": a.blend_state,
+                   "parallelism": "single GPU"},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs": {"tile_pairs": need, "contributing": n_alg},
         "roofline": roof,

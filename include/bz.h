@@ -134,7 +134,11 @@ typedef struct {
     int64_t *status;
 } bz_bins;
 
-/* Forward state kept for the reverse pass.
+/* Forward state kept for the reverse pass (blend state).  The render calls
+ * take a NULL state instead: the forward then writes only the image and the
+ * reverse pass recomputes the state tile by tile (one extra front-to-back
+ * sweep without colour, no per-pixel memory).  Both calls of one step must
+ * agree: a NULL-state forward is followed by a NULL-state backward.
  * t_final, n_last: [height][width]; n_last is the number of tile-list entries up
  *   to and including the pixel's last contributor.
  * n_contrib (optional, may be NULL): contributors per pixel, [height][width].
@@ -205,7 +209,7 @@ bz_status bz_bin(const bz_gaussians *g, const bz_opts *opts, bz_bins *b, hipStre
  * alpha = min(alpha_max, o (G - g_min)_+/(1 - g_min)) with
  * G = exp(-1/2 d^T Q d) (Eq. rasterization2), C += alpha T c, T *= 1 - alpha,
  * stop after T < t_min, then C += T bg.  image: [3][H][W]; state: per-pixel
- * t_final, n_last (and optionally n_contrib) for bz_render_bwd. */
+ * t_final, n_last (and optionally n_contrib) for bz_render_bwd, or NULL. */
 bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *opts,
                         float *image, bz_pixstate *state, hipStream_t stream);
 
@@ -215,7 +219,9 @@ bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *
  * gradients into grads->d_gauss.  Stage 2, per curve, chains them through the
  * sampling of Sec. 3.3 to control points, widths, colours and opacities.
  * d_image: dL/dimage, [3][H][W].  c, g, b, opts and state must be those of the
- * forward pass.  Requires alpha_max < 1 (the division recovering T).
+ * forward pass; with state NULL the per-pixel state is recomputed per tile
+ * (same results, one more sweep of the tile lists).  Requires alpha_max < 1
+ * (the division recovering T).
  * Per-Gaussian sums use float atomics, so d_gauss and the curve gradients
  * vary in the last bits from run to run. */
 bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins *b,

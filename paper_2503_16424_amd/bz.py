@@ -182,10 +182,15 @@ class Rasterizer:
     ``color``, ``opacity``) that an optimiser may update in place; gradients
     land in ``d_ctrl``, ``d_width``, ``d_color``, ``d_opacity`` after
     :meth:`backward`.
+
+    ``blend_state="stored"`` keeps the forward pass's per-pixel state (T after
+    the last contributor, its list position) and per-batch contribution masks
+    for the backward; ``"recompute"`` keeps none of it and the backward
+    recomputes it tile by tile (one more sweep of the tile lists).
     """
 
     def __init__(self, scene, opts: RenderOptions | None = None, device: str = "cuda",
-                 cap_pairs: int | None = None):
+                 cap_pairs: int | None = None, blend_state: str = "stored"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libbz needs a GPU; none is visible")
@@ -194,6 +199,9 @@ class Rasterizer:
         self.dev = torch.device(device)
         self.scene = scene
         self.ro = opts or RenderOptions()
+        if blend_state not in ("stored", "recompute"):
+            raise ValueError("blend_state is 'stored' or 'recompute'")
+        self.recompute = blend_state == "recompute"
         self.W, self.H = scene.width, scene.height
         self.opts = make_opts(self.W, self.H, scene.bg, self.ro)
         order, goff, mg, mk = layout_host(scene)
@@ -233,11 +241,15 @@ class Rasterizer:
         # image and state
         HW = self.W * self.H
         self.image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
-        self.t_final = torch.empty((self.H, self.W), dtype=f32, device=self.dev)
-        self.n_last = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
-        self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
-        self.state = PixState(_ptr(self.t_final).value, _ptr(self.n_last).value,
-                              _ptr(self.n_contrib).value, None, 0)
+        if self.recompute:         # no per-pixel state: the backward recomputes it per tile
+            self.t_final = self.n_last = self.n_contrib = None
+            self.state = None
+        else:
+            self.t_final = torch.empty((self.H, self.W), dtype=f32, device=self.dev)
+            self.n_last = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
+            self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
+            self.state = PixState(_ptr(self.t_final).value, _ptr(self.n_last).value,
+                                  _ptr(self.n_contrib).value, None, 0)
         self._alloc_pairs(cap_pairs if cap_pairs is not None else max(4 * self.n_gauss, 1 << 16))
         # gradients
         self.d_image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
@@ -266,6 +278,8 @@ class Rasterizer:
         aligned = (base + 255) & ~255
         self.bins = Bins(cap, _ptr(self.ids).value, _ptr(self.ranges).value, aligned,
                          int(wsb.value), _ptr(self.status).value)
+        if self.state is None:
+            return
         vw = C.c_int64(0)
         _check("bz_visit_words", self.lib.bz_visit_words(C.byref(self.opts), cap, C.byref(vw)))
         self.visit = torch.empty(int(vw.value), dtype=torch.int64, device=self.dev)
@@ -302,6 +316,9 @@ class Rasterizer:
             dst.copy_(src.detach().reshape(dst.shape))
 
     # -- library calls ---------------------------------------------------------
+    def _state_arg(self):
+        return None if self.state is None else C.byref(self.state)
+
     def sample(self):
         _check("bz_sample", self.lib.bz_sample(C.byref(self.curves), C.byref(self.opts),
                                                C.byref(self.gauss), _stream()))
@@ -313,14 +330,14 @@ class Rasterizer:
     def forward(self):
         _check("bz_render_fwd", self.lib.bz_render_fwd(C.byref(self.gauss), C.byref(self.bins),
                                                        C.byref(self.opts), _ptr(self.image),
-                                                       C.byref(self.state), _stream()))
+                                                       self._state_arg(), _stream()))
         return self.image
 
     def backward(self, d_image=None):
         d = self.d_image if d_image is None else d_image
         _check("bz_render_bwd", self.lib.bz_render_bwd(C.byref(self.curves), C.byref(self.gauss),
                                                        C.byref(self.bins), C.byref(self.opts),
-                                                       _ptr(d), C.byref(self.state),
+                                                       _ptr(d), self._state_arg(),
                                                        C.byref(self.grads), _stream()))
 
     def backward_gauss(self, d_image=None):
@@ -328,7 +345,7 @@ class Rasterizer:
         d = self.d_image if d_image is None else d_image
         _check("bz_render_bwd_gauss", self.lib.bz_render_bwd_gauss(
             C.byref(self.gauss), C.byref(self.bins), C.byref(self.opts), _ptr(d),
-            C.byref(self.state), _ptr(self.d_gauss), _stream()))
+            self._state_arg(), _ptr(self.d_gauss), _stream()))
 
     def backward_curves(self):
         """Stage 2 only: ``d_gauss`` -> per-curve gradients."""

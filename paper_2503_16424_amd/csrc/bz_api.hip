@@ -170,16 +170,24 @@ bz_status bz_bin(const bz_gaussians *g, const bz_opts *o, bz_bins *b, hipStream_
     return launched(launch_bin(g->rec, g->n, *o, *b, s));
 }
 
+// Blend state: absent (recomputed by the backward), or complete and large enough.
+static bz_status check_state(const bz_pixstate *state, const bz_opts *o, const bz_bins *b) {
+    if (!state) return BZ_OK;
+    if (!state->t_final || !state->n_last || !state->visit) return BZ_ERR_ARG;
+    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
+    return BZ_OK;
+}
+
 bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *o, float *image,
                         bz_pixstate *state, hipStream_t s) {
     bz_status st = check_opts(o);
     if (st != BZ_OK) return st;
     if (!g || g->n < 0 || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
     if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
-    if (!image || !state || !state->t_final || !state->n_last || !state->visit) return BZ_ERR_ARG;
-    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
+    if (!image) return BZ_ERR_ARG;
+    if ((st = check_state(state, o, b)) != BZ_OK) return st;
     (void)hipGetLastError();
-    return launched(launch_fwd(g->rec, *b, *o, image, *state, s));
+    return launched(launch_fwd(g->rec, *b, *o, image, state, s));
 }
 
 bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_opts *o,
@@ -189,12 +197,11 @@ bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_
     if (st != BZ_OK) return st;
     if (!g || g->n < 0 || (g->n > 0 && (!g->rec || !d_gauss))) return BZ_ERR_ARG;
     if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
-    if (!d_image || !state || !state->t_final || !state->n_last || !state->visit)
-        return BZ_ERR_ARG;
-    if (state->visit_words < visit_words(*o, b->cap_pairs)) return BZ_ERR_CAPACITY;
+    if (!d_image) return BZ_ERR_ARG;
+    if ((st = check_state(state, o, b)) != BZ_OK) return st;
     if (!(o->alpha_max < 1.f)) return BZ_ERR_UNSUPPORTED;
     (void)hipGetLastError();
-    return launched(launch_bwd_gauss(g->rec, g->n, *b, *o, d_image, *state, d_gauss, s));
+    return launched(launch_bwd_gauss(g->rec, g->n, *b, *o, d_image, state, d_gauss, s));
 }
 
 bz_status bz_render_bwd_curves(const bz_curves *c, const bz_opts *o, const float *d_gauss,

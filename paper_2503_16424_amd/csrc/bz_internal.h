@@ -47,10 +47,12 @@ struct Status {
 hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipStream_t s);
 hipError_t launch_bin(const float *rec, int64_t n_gauss, const bz_opts &o, const bz_bins &b,
                       hipStream_t s);
+// st == nullptr: the forward writes only the image; the backward recomputes
+// the blend state per tile.
 hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
-                      const bz_pixstate &st, hipStream_t s);
+                      const bz_pixstate *st, hipStream_t s);
 hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
-                            const bz_opts &o, const float *d_image, const bz_pixstate &st,
+                            const bz_opts &o, const float *d_image, const bz_pixstate *st,
                             float *d_gauss, hipStream_t s);
 hipError_t launch_bwd_curves(const bz_curves &c, const bz_opts &o, const float *d_gauss,
                              const bz_grads &gr, hipStream_t s);

@@ -114,7 +114,74 @@ __device__ inline int64_t visit_word(uint32_t start, int tile) {
     return (int64_t)(start >> 6) + tile;
 }
 
-template <bool kCount>
+// Result of a front-to-back sweep for one pixel.
+struct Sweep {
+    float T, C0, C1, C2;   // transmittance after the last contributor, colour sum
+    uint32_t last;         // 1 + list position of the last contributor (0: none)
+    uint32_t cnt;          // contributors (kCount only)
+};
+
+// Front-to-back blend (Sec. 3.4) of one wave's 8x8 quad over tile-list
+// positions [start, end): per batch of 64 entries, every lane stages one entry
+// into the wave's LDS slice and box-tests it against the quad; the wave then
+// visits the hits in list order.  Per pixel and hit: alpha = min(alpha_max,
+// o (G - g_min) / (1 - g_min)) when G > g_min, colour += alpha T c, T *= 1 - alpha;
+// a pixel stops after the first contributor that takes T below t_min, and the
+// wave leaves when all its pixels have stopped.  sink(k, bits) receives, for
+// batch k, the entries that changed at least one pixel of the quad.
+template <bool kColor, bool kCount, typename Sink>
+__device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start, uint32_t end,
+                                  float px, float py, float qx0, float qy0, bool valid, int lane,
+                                  Sink sink) {
+    Sweep r = {1.f, 0.f, 0.f, 0.f, 0u, 0u};
+    bool done = !valid;
+    const float g_min = a.g_min, amax = a.alpha_max, tmin = a.t_min;
+    uint32_t k = 0;
+    for (uint32_t base = start; base < end; base += 64, ++k) {
+        const uint32_t j = base + lane;
+        bool hit = false;
+        if (j < end) {
+            Staged st;
+            hit = stage_entry(a, a.ids[j], qx0, qy0, st);
+            my[lane] = st;
+        }
+        uint64_t mask = __ballot(hit);
+        uint64_t vbits = 0;
+        wave_lds_sync();
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const Staged st = my[b];
+            const float dx = (px - st.m.x) - st.m.z;
+            const float dy = (py - st.m.y) - st.m.w;
+            const float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
+            const float G = __builtin_amdgcn_exp2f(-p2);
+            const bool c = !done && G > g_min;
+            const float araw = fmaf(st.q.w, G, -st.c.w);
+            const float al = c ? (araw < amax ? araw : amax) : 0.f;
+            if (kColor) {
+                const float wgt = al * r.T;
+                r.C0 = fmaf(wgt, st.c.x, r.C0);
+                r.C1 = fmaf(wgt, st.c.y, r.C1);
+                r.C2 = fmaf(wgt, st.c.z, r.C2);
+            }
+            r.T = fmaf(-al, r.T, r.T);
+            r.last = c ? k * 64 + b + 1 : r.last;
+            if (kCount) r.cnt += c ? 1u : 0u;
+            done = done || r.T < tmin;
+            if (__ballot(c)) vbits |= 1ull << b;
+        }
+        sink(k, vbits);
+        if (__ballot(!done) == 0) break;
+        wave_lds_sync();
+    }
+    return r;
+}
+
+// Forward pass.  With kState the blend state the backward reads is written:
+// T after the last contributor, its position, and per (quad, batch) the mask
+// of entries that contributed; without it only the image.
+template <bool kState, bool kCount>
 __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
     extern __shared__ Staged s_stage[];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
@@ -139,63 +206,30 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
             a.image[pix] = nan;
             a.image[plane + pix] = nan;
             a.image[2 * plane + pix] = nan;
-            a.t_final[pix] = nan;
-            a.n_last[pix] = 0;
-            if (a.n_contrib) a.n_contrib[pix] = 0;
+            if (kState) {
+                a.t_final[pix] = nan;
+                a.n_last[pix] = 0;
+                if (kCount) a.n_contrib[pix] = 0;
+            }
         }
         return;
     }
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    uint64_t *vis = a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0, cnt = 0;
-    bool done = !valid;
-    const float g_min = a.g_min, amax = a.alpha_max, tmin = a.t_min;
-
-    uint32_t k = 0;
-    for (uint32_t base = start; base < end; base += 64, ++k) {
-        const uint32_t j = base + lane;
-        bool hit = false;
-        if (j < end) {
-            Staged st;
-            hit = stage_entry(a, a.ids[j], qx0, qy0, st);
-            my[lane] = st;
-        }
-        uint64_t mask = __ballot(hit);
-        uint64_t vbits = 0;
-        wave_lds_sync();
-        while (mask) {
-            const int b = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const Staged st = my[b];
-            const float dx = (px - st.m.x) - st.m.z;
-            const float dy = (py - st.m.y) - st.m.w;
-            const float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
-            const float G = __builtin_amdgcn_exp2f(-p2);
-            const bool c = !done && G > g_min;
-            const float araw = fmaf(st.q.w, G, -st.c.w);
-            const float al = c ? (araw < amax ? araw : amax) : 0.f;
-            const float wgt = al * T;
-            C0 = fmaf(wgt, st.c.x, C0);
-            C1 = fmaf(wgt, st.c.y, C1);
-            C2 = fmaf(wgt, st.c.z, C2);
-            T = fmaf(-al, T, T);
-            last = c ? k * 64 + b + 1 : last;
-            if (kCount) cnt += c ? 1u : 0u;
-            done = done || T < tmin;
-            if (__ballot(c)) vbits |= 1ull << b;
-        }
-        if (lane == 0) vis[k] = vbits;
-        if (__ballot(!done) == 0) break;
-        wave_lds_sync();
-    }
+    uint64_t *vis = kState ? a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile)
+                           : nullptr;
+    const Sweep r = fwd_sweep<true, kCount>(a, my, start, end, px, py, qx0, qy0, valid, lane,
+                                            [&](uint32_t k, uint64_t bits) {
+                                                if (kState && lane == 0) vis[k] = bits;
+                                            });
     if (valid) {
-        a.image[pix] = fmaf(T, a.bg0, C0);
-        a.image[plane + pix] = fmaf(T, a.bg1, C1);
-        a.image[2 * plane + pix] = fmaf(T, a.bg2, C2);
-        a.t_final[pix] = T;
-        a.n_last[pix] = last;
-        if (a.n_contrib) a.n_contrib[pix] = cnt;
+        a.image[pix] = fmaf(r.T, a.bg0, r.C0);
+        a.image[plane + pix] = fmaf(r.T, a.bg1, r.C1);
+        a.image[2 * plane + pix] = fmaf(r.T, a.bg2, r.C2);
+        if (kState) {
+            a.t_final[pix] = r.T;
+            a.n_last[pix] = r.last;
+            if (kCount) a.n_contrib[pix] = r.cnt;
+        }
     }
 }
 
@@ -290,9 +324,21 @@ constexpr int kTableCap = 640;   // tile-list positions pooled in LDS by the bac
 // dy^2/2).  The nine per-lane values of seven Gaussians are summed over the
 // wave in one transposed reduction and added to the per-Gaussian planes with
 // one 63-lane atomic instruction.
+//
+// kRecompute: the blend state (T after the last contributor, its position and
+// the per-batch contribution masks) is not read from memory but recomputed by
+// a front-to-back sweep of the same quad (colour omitted), with the
+// instruction sequence of the forward pass, so T and the positions are those
+// the forward pass had.  The masks of the first kVisCap batches stay in LDS;
+// later batches are staged whole and box-tested again (a superset of the
+// contributors: the others add exact zeros).
+constexpr int kVisCap = 128;
+
+template <bool kRecompute>
 __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
-    extern __shared__ Staged s_stage[];   // [waves][64] staged records, then the sum table
-    __shared__ uint32_t s_ids[16][64];
+    // dynamic LDS: [waves][64] staged records, [waves][64] their ids, the sum
+    // table, and (kRecompute) [waves][kVisCap] batch masks
+    extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_top[16];
     const int tile = xcd_tile(blockIdx.x, a.per_xcd);
     if (tile >= a.n_tiles) return;                       // whole block
@@ -307,24 +353,41 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
     const bool valid = wave_on && x < a.W && y < a.H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
-    uint32_t *my_ids = s_ids[w];
+    uint32_t *my_ids = reinterpret_cast<uint32_t *>(s_stage + nwaves * 64) + w * 64;
     // Per-tile sums, plane-major [9][tab_cap], indexed by tile-list position:
     // the quads of a tile share most of their Gaussians, so their sums meet
     // here and leave the block with one global atomic per (Gaussian, plane).
     const int tab_cap = a.tab_cap;
-    float *table = reinterpret_cast<float *>(s_stage + nwaves * 64);
+    float *table = reinterpret_cast<float *>(reinterpret_cast<uint32_t *>(s_stage + nwaves * 64) +
+                                             nwaves * 64);
+    // kRecompute: per-wave batch masks after the table
+    uint64_t *s_vis = reinterpret_cast<uint64_t *>(table + 9 * tab_cap) + w * kVisCap;
 
     const uint32_t start = a.ranges[2 * tile];
     const uint32_t len = a.ranges[2 * tile + 1] - start;
-    const uint64_t *vis = a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
+    const uint64_t *vis =
+        kRecompute ? nullptr : a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
     const int64_t pix = (int64_t)y * a.W + x;
     const int64_t plane = (int64_t)a.W * a.H;
     uint32_t nl = 0;
     float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    if (valid) {
+    if (kRecompute) {
+        if (wave_on) {
+            const Sweep r = fwd_sweep<false, false>(a, my, start, start + len, px, py, qx0, qy0,
+                                                    valid, lane, [&](uint32_t k, uint64_t bits) {
+                                                        if (lane == 0 && k < kVisCap) s_vis[k] = bits;
+                                                    });
+            nl = valid ? r.last : 0u;
+            T = valid ? r.T : 0.f;
+        }
+        wave_lds_sync();
+    } else if (valid) {
         nl = a.n_last[pix];
         T = a.t_final[pix];
+    }
+    if (valid) {
         g0 = a.d_image[pix];
         g1 = a.d_image[plane + pix];
         g2 = a.d_image[2 * plane + pix];
@@ -374,21 +437,37 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
             if (s == filled) {
                 while (mask == 0 && k > 0) {
                     --k;
-                    const uint64_t vraw = vis[k];
                     lo = (uint32_t)k * 64;
                     // only entries of this tile's list can be visited
                     const uint32_t avail = len - lo;
-                    const uint64_t vm = uniform_u64(vraw) & (avail >= 64 ? ~0ull : ((1ull << avail) - 1ull));
-                    if (vm != 0) {
+                    const uint64_t in_list = avail >= 64 ? ~0ull : ((1ull << avail) - 1ull);
+                    uint64_t vm;
+                    if (!kRecompute || k < kVisCap) {
+                        const uint64_t vraw = kRecompute ? s_vis[k] : vis[k];
+                        vm = uniform_u64(vraw) & in_list;
+                        if (vm != 0) {
+                            wave_lds_sync();
+                            if ((vm >> lane) & 1ull) {
+                                const uint32_t id = a.ids[start + lo + lane];
+                                Staged st;
+                                float4 q;
+                                stage_record(a, id, st, q);
+                                my[lane] = st;
+                                my_ids[lane] = id;
+                            }
+                            wave_lds_sync();
+                        }
+                    } else {
                         wave_lds_sync();
-                        if ((vm >> lane) & 1ull) {
+                        bool hit = false;
+                        if ((uint32_t)lane < avail) {
                             const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
-                            float4 q;
-                            stage_record(a, id, st, q);
+                            hit = stage_entry(a, id, qx0, qy0, st);
                             my[lane] = st;
                             my_ids[lane] = id;
                         }
+                        vm = __ballot(hit) & in_list;
                         wave_lds_sync();
                     }
                     mask = vm;
@@ -754,24 +833,29 @@ TileArgs tile_args(const float *rec, const bz_bins &b, const bz_opts &o) {
 }  // namespace
 
 hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
-                      const bz_pixstate &st, hipStream_t s) {
+                      const bz_pixstate *st, hipStream_t s) {
     TileArgs a = tile_args(rec, b, o);
     a.image = image;
-    a.t_final = st.t_final;
-    a.n_last = st.n_last;
-    a.n_contrib = st.n_contrib;
-    a.visit = st.visit;
     int threads = o.tile_w * o.tile_h;
     size_t lds = sizeof(Staged) * (size_t)threads;
-    if (st.n_contrib)
-        hipLaunchKernelGGL(k_fwd<true>, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    dim3 grid(8 * a.per_xcd);
+    if (!st) {
+        hipLaunchKernelGGL((k_fwd<false, false>), grid, dim3(threads), lds, s, a);
+        return hipGetLastError();
+    }
+    a.t_final = st->t_final;
+    a.n_last = st->n_last;
+    a.n_contrib = st->n_contrib;
+    a.visit = st->visit;
+    if (st->n_contrib)
+        hipLaunchKernelGGL((k_fwd<true, true>), grid, dim3(threads), lds, s, a);
     else
-        hipLaunchKernelGGL(k_fwd<false>, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_fwd<true, false>), grid, dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
-                            const bz_opts &o, const float *d_image, const bz_pixstate &st,
+                            const bz_opts &o, const float *d_image, const bz_pixstate *st,
                             float *d_gauss, hipStream_t s) {
     int64_t nz = (int64_t)kGradPlanes * n_gauss;
     if (nz > 0) {
@@ -780,16 +864,23 @@ hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
         hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, d_gauss, nz);
     }
     TileArgs a = tile_args(rec, b, o);
-    a.t_final = st.t_final;
-    a.n_last = st.n_last;
-    a.visit = st.visit;
     a.d_image = d_image;
     a.d_gauss = d_gauss;
     a.n_gauss = n_gauss;
     int threads = o.tile_w * o.tile_h;
     a.tab_cap = kTableCap;
-    size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * 9 * (size_t)kTableCap;
-    hipLaunchKernelGGL(k_bwd_tiles, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    size_t lds = (sizeof(Staged) + sizeof(uint32_t)) * (size_t)threads +
+                 sizeof(float) * 9 * (size_t)kTableCap;
+    dim3 grid(8 * a.per_xcd);
+    if (st) {
+        a.t_final = st->t_final;
+        a.n_last = st->n_last;
+        a.visit = st->visit;
+        hipLaunchKernelGGL(k_bwd_tiles<false>, grid, dim3(threads), lds, s, a);
+    } else {
+        lds += sizeof(uint64_t) * kVisCap * (size_t)(threads / 64);
+        hipLaunchKernelGGL(k_bwd_tiles<true>, grid, dim3(threads), lds, s, a);
+    }
     return hipGetLastError();
 }
 

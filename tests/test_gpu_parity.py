@@ -151,16 +151,18 @@ def test_forward_bitwise_across_tile_shapes_and_runs(torch_cuda):
         assert np.array_equal(im.view(np.uint32), ref.view(np.uint32)), f"tile {tile} differs"
 
 
-@pytest.mark.parametrize("name", list(SCENES))
-def test_backward_matches_oracle(torch_cuda, name):
+@pytest.mark.parametrize("state", ["stored", "recompute"])
+@pytest.mark.parametrize("name", list(SCENES) + ["dense_tile"])
+def test_backward_matches_oracle(torch_cuda, name, state):
     import torch
-    sc = SCENES[name]()
-    _note(f"backward parity {name} n_gauss={sc.n_gauss}")
+    sc = SCENES[name]() if name in SCENES else _dense_tile_scene()
+    _note(f"backward parity {name} n_gauss={sc.n_gauss} blend state {state}")
     o0 = oracle.forward_backward(sc)
     dimg = _upstream(sc, o0["image"])
     o = oracle.forward_backward(sc, dimg.astype(np.float64))
-    r = _rast(sc)
-    r.render()
+    r = _rast(sc, blend_state=state)
+    img = r.render().cpu().numpy()
+    assert np.abs(img - o0["image"]).max() <= IMG_TOL
     r.backward(torch.as_tensor(dimg, device="cuda"))
     torch.cuda.synchronize()
     got = dict(d_ctrl=r.d_ctrl.cpu().numpy(), d_width=r.d_width.cpu().numpy(),
@@ -178,6 +180,57 @@ def test_backward_matches_oracle(torch_cuda, name):
     for j, label in enumerate(["mu_x", "mu_y", "Qxx", "Qxy", "Qyy", "o", "r", "g", "b"]):
         e = rel_l2(dg[:, j], o["d_gauss"][:, j])
         assert e <= GRAD_TOL, label
+
+
+@pytest.mark.parametrize("state", ["stored", "recompute"])
+def test_backward_across_tile_shapes(torch_cuda, state):
+    """Tile shape is a tuning choice: every allowed shape gives the oracle's
+    gradients (1 to 16 waves per workgroup)."""
+    import torch
+    sc = SCENES["mixed_small_b"]()
+    o0 = oracle.forward_backward(sc)
+    dimg = _upstream(sc, o0["image"])
+    o = oracle.forward_backward(sc, dimg.astype(np.float64))
+    for tile in [(8, 8), (32, 8), (8, 32), (16, 32), (32, 32)]:
+        _note(f"  tile {tile} blend state {state}")
+        r = _rast(sc, tile, blend_state=state)
+        r.render()
+        r.backward(torch.as_tensor(dimg, device="cuda"))
+        torch.cuda.synchronize()
+        for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
+            assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= GRAD_TOL, (tile, k)
+
+
+def _dense_tile_scene():
+    """12,800 faint Gaussians over a 32x32 canvas: every tile list is longer
+    than the 8,192 entries whose contribution masks the recomputing backward
+    keeps on chip, and no pixel terminates."""
+    sc = scenes.uniform_open(21, 32, 32, 400, 32)
+    sc.ctrl = (np.float32(10.0) + sc.ctrl * np.float32(12.0 / 32.0)).astype(np.float32)
+    sc.opacity = np.random.default_rng(22).uniform(2e-4, 8e-4, sc.opacity.shape).astype(np.float32)
+    return sc
+
+
+def test_recomputed_blend_state_gives_the_stored_state_results(torch_cuda):
+    """Same image bits, and per-Gaussian gradients equal up to the order of
+    the float atomics, with and without stored blend state."""
+    import torch
+    for name in ("mixed_R20", "dense_tile"):
+        sc = SCENES[name]() if name in SCENES else _dense_tile_scene()
+        dimg = torch.as_tensor(_upstream(sc, oracle.forward_backward(sc)["image"]), device="cuda")
+        out = {}
+        for state in ("stored", "recompute"):
+            r = _rast(sc, blend_state=state)
+            img = r.render().clone()
+            r.backward(dimg)
+            torch.cuda.synchronize()
+            out[state] = (img, r.d_gauss[: 9 * sc.n_gauss].clone(), r.d_ctrl.clone())
+        a, b = out["stored"], out["recompute"]
+        assert torch.equal(a[0].view(torch.int32), b[0].view(torch.int32)), name
+        e = rel_l2(b[1].cpu().numpy(), a[1].cpu().numpy())
+        _note(f"  {name}: per-Gaussian gradients rel L2 {e:.2e}")
+        assert e <= 1e-5, name
+        assert rel_l2(b[2].cpu().numpy(), a[2].cpu().numpy()) <= 1e-5, name
 
 
 def test_step_with_l2_kernel_matches_oracle_gradient(torch_cuda):

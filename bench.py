@@ -47,7 +47,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_2048", choices=["paper_2048", "open_512",
-                                                                 "tiny_128"])
+                                                                 "tiny_128", "batched_64"])
+    ap.add_argument("--persistent", action="store_true",
+                    help="persistent blend launches (tiles from a counter)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched_64: pick tile shape and launch form by measurement first")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--blend-state", default="stored", choices=["stored", "recompute"],
                     help="keep the forward's per-pixel blend state for the backward, or "
@@ -111,12 +115,94 @@ def cpu_baseline(sc, target, rows):
                 seconds=t4 - t0)
 
 
+def bench_batched(a):
+    """64 canvases of uneven size (sides log-uniform 128..1024 px, 256..8192
+    open curves, K 16..32): the batched step (one tile space, every stage one
+    launch, the whole step one graph replay) against the same 64 canvases run
+    one after the other, each with its own launches."""
+    import torch
+
+    from paper_2503_16424_amd import bz, scenes
+    from paper_2503_16424_amd.autotune import autotune, time_graph
+    from paper_2503_16424_amd.graph import StepGraph
+    parts = scenes.batched(0)
+    ng = sum(p.n_gauss for p in parts)
+    npx = sum(p.width * p.height for p in parts)
+    print(f"# batched: {len(parts)} canvases, {ng} Gaussians, {npx} px", file=sys.stderr,
+          flush=True)
+    tgt_np = [scenes.target_noise(1000 + c, p.width, p.height) for c, p in enumerate(parts)]
+    import numpy as np
+    flat = torch.as_tensor(np.concatenate([t.reshape(-1) for t in tgt_np]), device="cuda")
+    tw, th = (int(v) for v in a.tile.split("x"))
+    ro = bz.RenderOptions(tile_w=tw, tile_h=th, persistent=a.persistent)
+    table = None
+    if a.autotune:
+        print("# autotuning tile shape and launch form", file=sys.stderr, flush=True)
+        ro, table = autotune(parts, flat, reps=5,
+                             log=lambda m: print("#" + m, file=sys.stderr, flush=True))
+    r = bz.Rasterizer(parts, ro)
+    g = StepGraph(r, flat, warmup=a.warmup)
+    for _ in range(a.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_graph_events = time_graph(g, a.steps)
+    wall_batched = (time.perf_counter() - t0) * 1000.0 / (a.steps + 1)
+    if g.replay(check=True):
+        raise RuntimeError("pair buffer overflowed during the timed steps")
+    del g, r
+    torch.cuda.empty_cache()
+    # the same canvases, one after the other, eager launches
+    seq_ro = bz.RenderOptions(tile_w=16, tile_h=16)
+    rs = [bz.Rasterizer(p, seq_ro) for p in parts]
+    ts = [torch.as_tensor(t, device="cuda") for t in tgt_np]
+    for rr in rs:
+        rr.render()
+        need = rr.pairs_required()
+        if need * 1.25 > rr.cap_pairs:
+            rr._alloc_pairs(int(need * 1.25) + 1024)
+    for _ in range(a.warmup):
+        for rr, t in zip(rs, ts):
+            rr.step(t)
+    torch.cuda.synchronize()
+    seq_steps = max(1, a.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(seq_steps):
+        for rr, t in zip(rs, ts):
+            rr.step(t)
+    torch.cuda.synchronize()
+    wall_seq = (time.perf_counter() - t0) * 1000.0 / seq_steps
+    out = {
+        "metric": "fwd+bwd steps/s, 64 canvases in one batch (step = every canvas once)",
+        "value": 1000.0 / wall_batched,
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": wall_batched,
+        "ms_per_step_events": ms_graph_events,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched-64-canvases", "canvases": len(parts), "gaussians": ng,
+                   "pixels": npx, "tile": [ro.tile_w, ro.tile_h],
+                   "persistent": bool(ro.persistent), "graph": True,
+                   "parallelism": "single GPU"},
+        "sequential": {"ms_per_step": wall_seq, "steps_per_s": 1000.0 / wall_seq,
+                       "launch": "64 canvases one after the other, 16x16 tiles, eager"},
+        "speedup_vs_sequential": wall_seq / wall_batched,
+    }
+    if table:
+        out["autotune"] = [dict(c, ms=round(ms, 4)) for c, ms in table]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         return 2
+    if a.workload == "batched_64":
+        return bench_batched(a)
     import numpy as np
     import torch
 
@@ -134,7 +220,7 @@ def main():
         sc, target = scenes.tiny_128(0), scenes.tiny_128_target(0)
     print(f"# workload {sc.name}: {sc.n_curves} curves, {sc.n_gauss} Gaussians", file=sys.stderr,
           flush=True)
-    ro = bz.RenderOptions(tile_w=tw, tile_h=th)
+    ro = bz.RenderOptions(tile_w=tw, tile_h=th, persistent=a.persistent)
     r = bz.Rasterizer(sc, ro, device="cuda:0")
     tgt = torch.as_tensor(target, device=dev)
     r.render()                                    # sizes the pair buffer (synchronises)
@@ -231,6 +317,7 @@ def main():
         "config": {"workload": sc.name, "canvas": [sc.width, sc.height],
                    "curves": sc.n_curves, "gaussians": sc.n_gauss, "seed": 0,
                    "tile": [tw, th], "blend_state": a.blend_state,
+                   "persistent": bool(a.persistent),
                    "parallelism": "single GPU"},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs": {"tile_pairs": need, "contributing": n_alg},

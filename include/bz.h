@@ -51,6 +51,31 @@ typedef enum {
 #define BZ_OPEN 0     /* stroke: S cubic segments, 3S+1 control points, a width */
 #define BZ_CLOSED 1   /* paired boundaries A, B sharing endpoints: 6S points, filled */
 
+/* One canvas of a batch: many canvases of different sizes share one tile
+ * space, one tile-list sort and one launch per stage.  Filled on the host by
+ * bz_batch_layout and copied to the device by the caller.
+ *   tile_off  : first global tile of the canvas (its tiles are row-major)
+ *   pix_off   : first pixel: the canvas's image is image + 3*pix_off, planar
+ *               [3][height][width]; per-pixel state starts at pix_off
+ *   gauss_off : first Gaussian; the canvas's curves are consecutive in draw
+ *               order, so its Gaussians are [gauss_off, next gauss_off). */
+typedef struct {
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int64_t tile_off, pix_off, gauss_off;
+    float bg[3];
+    int32_t reserved;
+} bz_canvas;
+
+/* A batch of canvases.  canvas: device array of n_canvas + 1 records, the last
+ * one holding the totals (tile_off = n_tiles, pix_off = n_pixels, gauss_off =
+ * n_gauss).  n_tiles, n_pixels, n_gauss: host copies of the totals. */
+typedef struct {
+    int32_t n_canvas;
+    int64_t n_tiles, n_pixels, n_gauss;
+    const bz_canvas *canvas;
+} bz_batch;
+
 /* Rendering options (host struct, passed by pointer, read during the call). */
 typedef struct {
     int32_t width, height;   /* canvas in pixels, 1..32768 each */
@@ -65,6 +90,14 @@ typedef struct {
                                 transmittance below t_min, [0, 1); 1e-6 */
     int32_t tile_w, tile_h;  /* binning tile: multiples of 8, product 64..1024.
                                 Results do not depend on the tile shape. */
+    int32_t persistent;      /* tuning: 0 = one workgroup per tile; 1 = the blend
+                                kernels run as many workgroups as fit on the GPU at
+                                once, each taking tiles from a counter in
+                                bz_bins.workspace.  Results do not depend on it. */
+    int32_t reserved;
+    const bz_batch *batch;   /* NULL: one canvas of width x height with bg.  Else
+                                the canvases of the batch (host struct; width,
+                                height and bg above are then unused). */
 } bz_opts;
 
 /* Curve set, structure of arrays on the device.
@@ -184,8 +217,21 @@ bz_status bz_layout_host(int32_t n_curves, const int32_t *kind, const int32_t *n
 bz_status bz_workspace_size(const bz_opts *opts, int64_t n_gauss, int64_t cap_pairs,
                             int64_t *bytes);
 
-/* Host: number of tiles of the canvas for the options' tile shape. */
+/* Host: number of tiles of the canvas (or of all canvases of opts->batch)
+ * for the options' tile shape. */
 bz_status bz_num_tiles(const bz_opts *opts, int64_t *n_tiles);
+
+/* Host: lay out a batch of n_canvas canvases for the tile shape of opts.
+ * size: [n_canvas][2] width, height (1..32768); bg: [n_canvas][3] or NULL (all
+ * opts->bg); gauss_off: [n_canvas + 1] first Gaussian of every canvas and the
+ * total, non-decreasing from 0.  Writes canvas[0 .. n_canvas] (n_canvas + 1
+ * records, all HOST memory) and batch->n_canvas, n_tiles, n_pixels, n_gauss
+ * (batch->canvas is left for the caller to point at a device copy of the
+ * records).
+ * Tiles and pixels are numbered canvas by canvas. */
+bz_status bz_batch_layout(const bz_opts *opts, int32_t n_canvas, const int32_t *size,
+                          const float *bg, const int64_t *gauss_off, bz_canvas *canvas,
+                          bz_batch *batch);
 
 /* Host: 64-bit words of bz_pixstate.visit for tile lists of cap_pairs entries. */
 bz_status bz_visit_words(const bz_opts *opts, int64_t cap_pairs, int64_t *words);

@@ -22,11 +22,23 @@ STATUS_OVERFLOW = 1
 STATUS_NONFINITE = 2
 
 
+class Canvas(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tiles_x", C.c_int32),
+                ("tiles_y", C.c_int32), ("tile_off", C.c_int64), ("pix_off", C.c_int64),
+                ("gauss_off", C.c_int64), ("bg", C.c_float * 3), ("reserved", C.c_int32)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_canvas", C.c_int32), ("n_tiles", C.c_int64), ("n_pixels", C.c_int64),
+                ("n_gauss", C.c_int64), ("canvas", C.c_void_p)]
+
+
 class Opts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bg", C.c_float * 3),
                 ("rho", C.c_float), ("sigma0_sq", C.c_float), ("g_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32)]
+                ("tile_h", C.c_int32), ("persistent", C.c_int32), ("reserved", C.c_int32),
+                ("batch", C.c_void_p)]
 
 
 class Curves(C.Structure):
@@ -59,8 +71,8 @@ class Grads(C.Structure):
                 ("d_opacity", C.c_void_p), ("d_gauss", C.c_void_p)]
 
 
-EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_visit_words", "bz_sample",
-           "bz_bin",
+EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_batch_layout",
+           "bz_visit_words", "bz_sample", "bz_bin",
            "bz_render_fwd", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
            "bz_l2_grad", "bz_status_str")
 
@@ -85,6 +97,9 @@ def load_library(path: str = LIB_PATH):
     lib.bz_workspace_size.argtypes = [P(Opts), C.c_int64, C.c_int64, P(C.c_int64)]
     lib.bz_num_tiles.restype = C.c_int
     lib.bz_num_tiles.argtypes = [P(Opts), P(C.c_int64)]
+    lib.bz_batch_layout.restype = C.c_int
+    lib.bz_batch_layout.argtypes = [P(Opts), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, P(Batch)]
     lib.bz_visit_words.restype = C.c_int
     lib.bz_visit_words.argtypes = [P(Opts), C.c_int64, P(C.c_int64)]
     lib.bz_sample.restype = C.c_int
@@ -130,6 +145,7 @@ class RenderOptions:
     t_min: float = 1e-6
     tile_w: int = 16
     tile_h: int = 16
+    persistent: bool = False
 
     def as_dict(self):
         return dict(rho=self.rho, sigma0_sq=self.sigma0_sq, g_min=self.g_min,
@@ -144,6 +160,8 @@ def make_opts(width, height, bg, ro: RenderOptions) -> Opts:
     o.rho, o.sigma0_sq, o.g_min = ro.rho, ro.sigma0_sq, ro.g_min
     o.alpha_max, o.t_min = ro.alpha_max, ro.t_min
     o.tile_w, o.tile_h = int(ro.tile_w), int(ro.tile_h)
+    o.persistent = int(bool(ro.persistent))
+    o.batch = None
     return o
 
 
@@ -197,16 +215,40 @@ class Rasterizer:
         self.lib = load_library()
         self.torch = torch
         self.dev = torch.device(device)
-        self.scene = scene
         self.ro = opts or RenderOptions()
         if blend_state not in ("stored", "recompute"):
             raise ValueError("blend_state is 'stored' or 'recompute'")
         self.recompute = blend_state == "recompute"
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
+        self.canvases = None
+        if isinstance(scene, (list, tuple)):             # a batch of canvases
+            from .scenes import concat
+            self.canvases = list(scene)
+            scene = concat(self.canvases)
+        self.scene = scene
         self.W, self.H = scene.width, scene.height
         self.opts = make_opts(self.W, self.H, scene.bg, self.ro)
         order, goff, mg, mk = layout_host(scene)
         self.n_gauss = int(goff[-1])
-        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
+        self.n_pixels = self.W * self.H
+        if self.canvases is not None:
+            n = len(self.canvases)
+            curve_off = np.concatenate([[0], np.cumsum([c.n_curves for c in self.canvases])])
+            size = np.array([[c.width, c.height] for c in self.canvases], np.int32)
+            bg = np.array([np.asarray(c.bg, np.float32) for c in self.canvases], np.float32)
+            cgoff = np.ascontiguousarray(goff[curve_off], np.int64)
+            recs = (Canvas * (n + 1))()
+            self.batch = Batch()
+            p = lambda x: x.ctypes.data_as(C.c_void_p)
+            _check("bz_batch_layout", self.lib.bz_batch_layout(
+                C.byref(self.opts), n, p(size), p(bg), p(cgoff), C.addressof(recs),
+                C.byref(self.batch)))
+            raw = np.frombuffer(bytes(recs), np.uint8)
+            self.canvas_table = t(raw, torch.uint8)
+            self.batch.canvas = self.canvas_table.data_ptr()
+            self.opts.batch = C.addressof(self.batch)
+            self.canvas_host = [(r.width, r.height, r.pix_off) for r in recs[:n]]
+            self.n_pixels = int(self.batch.n_pixels)
         i32, f32 = torch.int32, torch.float32
         self.kind = t(scene.kind, i32)
         self.nseg = t(scene.nseg, i32)
@@ -238,21 +280,23 @@ class Rasterizer:
         self.n_tiles = int(nt.value)
         self.ranges = torch.zeros(2 * self.n_tiles, dtype=torch.int32, device=self.dev)
         self.status = torch.zeros(4, dtype=torch.int64, device=self.dev)
-        # image and state
-        HW = self.W * self.H
-        self.image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
+        # image and state: [3][H][W] and [H][W], or flat over the canvases of a batch
+        HW = self.n_pixels
+        ishape = (3 * HW,) if self.canvases is not None else (3, self.H, self.W)
+        pshape = (HW,) if self.canvases is not None else (self.H, self.W)
+        self.image = torch.empty(ishape, dtype=f32, device=self.dev)
         if self.recompute:         # no per-pixel state: the backward recomputes it per tile
             self.t_final = self.n_last = self.n_contrib = None
             self.state = None
         else:
-            self.t_final = torch.empty((self.H, self.W), dtype=f32, device=self.dev)
-            self.n_last = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
-            self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=self.dev)
+            self.t_final = torch.empty(pshape, dtype=f32, device=self.dev)
+            self.n_last = torch.empty(pshape, dtype=torch.int32, device=self.dev)
+            self.n_contrib = torch.empty(pshape, dtype=torch.int32, device=self.dev)
             self.state = PixState(_ptr(self.t_final).value, _ptr(self.n_last).value,
                                   _ptr(self.n_contrib).value, None, 0)
         self._alloc_pairs(cap_pairs if cap_pairs is not None else max(4 * self.n_gauss, 1 << 16))
         # gradients
-        self.d_image = torch.empty((3, self.H, self.W), dtype=f32, device=self.dev)
+        self.d_image = torch.empty(ishape, dtype=f32, device=self.dev)
         self.d_ctrl = torch.empty_like(self.ctrl)
         self.d_width = torch.empty_like(self.stroke_w)
         self.d_color = torch.empty_like(self.color)
@@ -300,6 +344,19 @@ class Rasterizer:
             self._alloc_pairs(int(math.ceil(self.pairs_required() * slack)) + 1024)
             return True
         return False
+
+    # -- batches -----------------------------------------------------------------
+    def canvas_view(self, t, c: int):
+        """Canvas c's [3, H, W] block of a flat batch image (or [H, W] block of
+        a flat per-pixel array)."""
+        W, H, off = self.canvas_host[c]
+        if t.numel() == 3 * self.n_pixels:
+            return t.view(-1)[3 * off: 3 * off + 3 * W * H].view(3, H, W)
+        return t.view(-1)[off: off + W * H].view(H, W)
+
+    def flat_images(self, imgs):
+        """Concatenate per-canvas [3, H, W] arrays into the flat batch layout."""
+        return np.concatenate([np.asarray(a, np.float32).reshape(-1) for a in imgs])
 
     # -- parameters --------------------------------------------------------------
     def set_params(self, ctrl=None, stroke_w=None, color=None, opacity=None):

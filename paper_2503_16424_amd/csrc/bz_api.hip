@@ -29,8 +29,14 @@ bz_status check_opts(const bz_opts *o) {
     if (!(o->t_min >= 0.f && o->t_min < 1.f)) return BZ_ERR_ARG;
     for (int c = 0; c < 3; ++c)
         if (!isfinite(o->bg[c])) return BZ_ERR_ARG;
-    int64_t nt = tiles_x(*o) * tiles_y(*o);
-    if (nt > (int64_t(1) << 24)) return BZ_ERR_UNSUPPORTED;
+    if (o->persistent != 0 && o->persistent != 1) return BZ_ERR_ARG;
+    if (o->batch) {
+        const bz_batch *bt = o->batch;
+        if (bt->n_canvas < 1 || !bt->canvas || bt->n_tiles < bt->n_canvas || bt->n_pixels < 1 ||
+            bt->n_gauss < 0)
+            return BZ_ERR_ARG;
+    }
+    if (num_tiles(*o) > (int64_t(1) << 24)) return BZ_ERR_UNSUPPORTED;
     return BZ_OK;
 }
 
@@ -58,6 +64,15 @@ bz_status check_bins(const bz_bins *b, const bz_opts *o, int64_t n_gauss, bool n
 }
 
 bz_status launched(hipError_t e) { return e == hipSuccess ? BZ_OK : BZ_ERR_HIP; }
+
+// The blend calls of a persistent launch keep their tile counters at the start
+// of the bin workspace.
+bz_status check_persistent(const bz_bins *b, const bz_opts *o) {
+    if (!o->persistent) return BZ_OK;
+    if (!b->workspace || ((uintptr_t)b->workspace & 255) || b->workspace_bytes < 256)
+        return BZ_ERR_ARG;
+    return BZ_OK;
+}
 
 int64_t stage2_lds(const bz_curves *c) {
     return stage2_lds_bytes(c->max_k, c->max_gauss_per_curve);
@@ -126,7 +141,46 @@ bz_status bz_num_tiles(const bz_opts *o, int64_t *n_tiles) {
     bz_status st = check_opts(o);
     if (st != BZ_OK) return st;
     if (!n_tiles) return BZ_ERR_ARG;
-    *n_tiles = tiles_x(*o) * tiles_y(*o);
+    *n_tiles = num_tiles(*o);
+    return BZ_OK;
+}
+
+bz_status bz_batch_layout(const bz_opts *o, int32_t n, const int32_t *size, const float *bg,
+                          const int64_t *gauss_off, bz_canvas *canvas, bz_batch *batch) {
+    if (!o || n < 1 || !size || !gauss_off || !canvas || !batch) return BZ_ERR_ARG;
+    if (o->tile_w < 8 || o->tile_h < 8 || o->tile_w % 8 || o->tile_h % 8) return BZ_ERR_ARG;
+    if (gauss_off[0] != 0) return BZ_ERR_ARG;
+    int64_t tile = 0, pix = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        const int32_t W = size[2 * c], H = size[2 * c + 1];
+        if (W < 1 || H < 1 || W > 32768 || H > 32768) return BZ_ERR_ARG;
+        if (gauss_off[c + 1] < gauss_off[c]) return BZ_ERR_ARG;
+        bz_canvas &r = canvas[c];
+        memset(&r, 0, sizeof(r));
+        r.width = W;
+        r.height = H;
+        r.tiles_x = (W + o->tile_w - 1) / o->tile_w;
+        r.tiles_y = (H + o->tile_h - 1) / o->tile_h;
+        r.tile_off = tile;
+        r.pix_off = pix;
+        r.gauss_off = gauss_off[c];
+        for (int k = 0; k < 3; ++k) {
+            r.bg[k] = bg ? bg[3 * c + k] : o->bg[k];
+            if (!isfinite(r.bg[k])) return BZ_ERR_ARG;
+        }
+        tile += (int64_t)r.tiles_x * r.tiles_y;
+        pix += (int64_t)W * H;
+    }
+    bz_canvas &end = canvas[n];
+    memset(&end, 0, sizeof(end));
+    end.tile_off = tile;
+    end.pix_off = pix;
+    end.gauss_off = gauss_off[n];
+    batch->n_canvas = n;
+    batch->n_tiles = tile;
+    batch->n_pixels = pix;
+    batch->n_gauss = gauss_off[n];
+    if (tile > (int64_t(1) << 24)) return BZ_ERR_UNSUPPORTED;
     return BZ_OK;
 }
 
@@ -165,6 +219,7 @@ bz_status bz_bin(const bz_gaussians *g, const bz_opts *o, bz_bins *b, hipStream_
     if (st != BZ_OK) return st;
     if (!g || g->n < 0 || g->n > g->cap || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
     if (g->n >= (int64_t(1) << 32)) return BZ_ERR_UNSUPPORTED;
+    if (o->batch && o->batch->n_gauss != g->n) return BZ_ERR_ARG;
     if ((st = check_bins(b, o, g->n, true)) != BZ_OK) return st;
     (void)hipGetLastError();
     return launched(launch_bin(g->rec, g->n, *o, *b, s));
@@ -186,6 +241,7 @@ bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *
     if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
     if (!image) return BZ_ERR_ARG;
     if ((st = check_state(state, o, b)) != BZ_OK) return st;
+    if ((st = check_persistent(b, o)) != BZ_OK) return st;
     (void)hipGetLastError();
     return launched(launch_fwd(g->rec, *b, *o, image, state, s));
 }
@@ -199,6 +255,7 @@ bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_
     if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
     if (!d_image) return BZ_ERR_ARG;
     if ((st = check_state(state, o, b)) != BZ_OK) return st;
+    if ((st = check_persistent(b, o)) != BZ_OK) return st;
     if (!(o->alpha_max < 1.f)) return BZ_ERR_UNSUPPORTED;
     (void)hipGetLastError();
     return launched(launch_bwd_gauss(g->rec, g->n, *b, *o, d_image, state, d_gauss, s));

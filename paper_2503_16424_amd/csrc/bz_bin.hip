@@ -63,12 +63,27 @@ __global__ void k_reset(int64_t *status) {
     }
 }
 
+// canvas (W x H) of Gaussian g: the single canvas, or its batch canvas
+__device__ inline void gauss_canvas(const bz_canvas *cv, int n_canvas, int64_t g, int &W, int &H,
+                                    int &tiles_x, uint32_t &tile_base) {
+    if (!cv) return;
+    const int c = batch_find(cv, n_canvas, g, [](const bz_canvas &r) { return r.gauss_off; });
+    W = cv[c].width;
+    H = cv[c].height;
+    tiles_x = cv[c].tiles_x;
+    tile_base = (uint32_t)cv[c].tile_off;
+}
+
 __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, int64_t n, int W,
                                                int H, int tw, int th, float two_p,
+                                               const bz_canvas *__restrict__ cv, int n_canvas,
                                                uint32_t *__restrict__ counts,
                                                ushort4 *__restrict__ rects, int64_t *status) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
+    int tiles_x_unused;
+    uint32_t base_unused;
+    gauss_canvas(cv, n_canvas, g, W, H, tiles_x_unused, base_unused);
     float4 m = rec[3 * g], q = rec[3 * g + 1];
     float mx = m.x + m.z, my = m.y + m.w;
     float det = q.x * q.z - q.y * q.y;
@@ -201,15 +216,19 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
                                               const ushort4 *__restrict__ rects, int64_t n,
-                                              int tiles_x, uint32_t *__restrict__ keys,
+                                              int tiles_x, const bz_canvas *__restrict__ cv,
+                                              int n_canvas, uint32_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals,
                                               const int64_t *status) {
     // The 256 Gaussians of a block own one contiguous output range (their
     // scan offsets are consecutive), so the block writes that range with
     // consecutive threads on consecutive positions; each position finds its
-    // Gaussian by binary search over the block's offsets in LDS.
+    // Gaussian by binary search over the block's offsets in LDS.  In a batch
+    // the key is the global tile: the canvas's first tile + its local tile.
     __shared__ uint32_t s_off[257];
     __shared__ ushort4 s_rect[256];
+    __shared__ uint32_t s_base[256];
+    __shared__ int s_tx[256];
     if (status[1] & Status::kOverflow) return;
     const int64_t g0 = (int64_t)blockIdx.x * 256;
     const int nb = (int)(n - g0 < 256 ? n - g0 : 256);
@@ -217,6 +236,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
     if (t < nb) {
         s_off[t] = offs[g0 + t];
         s_rect[t] = rects[g0 + t];
+        int W = 0, H = 0, tx = tiles_x;
+        uint32_t base = 0;
+        gauss_canvas(cv, n_canvas, g0 + t, W, H, tx, base);
+        s_base[t] = base;
+        s_tx[t] = tx;
     }
     __syncthreads();
     if (t == 0) {
@@ -239,7 +263,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
         const uint32_t w = (uint32_t)(rc.z - rc.x + 1);
         const uint32_t li = o - s_off[lo];
         const uint32_t ty = rc.y + li / w, tx = rc.x + li % w;
-        keys[o] = ty * (uint32_t)tiles_x + tx;
+        keys[o] = s_base[lo] + ty * (uint32_t)s_tx[lo] + tx;
         vals[o] = (uint32_t)(g0 + lo);
     }
 }
@@ -381,7 +405,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ key
 
 BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
     BinLayout L;
-    L.n_tiles = tiles_x(o) * tiles_y(o);
+    L.n_tiles = num_tiles(o);
     int bits = 0;
     while ((int64_t(1) << bits) < L.n_tiles) ++bits;
     if (bits == 0) bits = 1;
@@ -389,6 +413,8 @@ BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
     L.passes = (bits + 7) / 8;
     L.hist_blocks = cdiv(cap > 0 ? cap : 1, kTile);
     int64_t off = 0;
+    L.off_counters = off;                 // first, so that its place needs no sizes
+    off = align256(off + 4 * 4);
     L.off_counts = off;
     off = align256(off + 4 * (n_gauss > 0 ? n_gauss : 1));
     L.off_rects = off;
@@ -428,15 +454,17 @@ hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_
                        2 * L.n_tiles, 0u);
     if (n > 0) {
         float two_p = 2.0f * (-logf(o.g_min));
+        const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
+        const int ncv = o.batch ? o.batch->n_canvas : 0;
         hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, rec, n, o.width,
-                           o.height, o.tile_w, o.tile_h, two_p, counts, rects, b.status);
+                           o.height, o.tile_w, o.tile_h, two_p, cv, ncv, counts, rects, b.status);
         hipError_t e = scan_u32(counts, counts, n, part, b.status, b.cap_pairs, b.status, s);
         if (e != hipSuccess) return e;
         // The final radix pass must land in (keys_a, ids).
         bool even = (L.passes % 2) == 0;
         uint32_t *k0 = even ? keys_a : keys_b, *v0 = even ? b.ids : vals_b;
         hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 256)), dim3(256), 0, s, counts, rects, n, tx,
-                           k0, v0, (const int64_t *)b.status);
+                           cv, ncv, k0, v0, (const int64_t *)b.status);
         uint32_t *kin = k0, *vin = v0;
         for (int p = 0; p < L.passes; ++p) {
             int shift = 8 * p;

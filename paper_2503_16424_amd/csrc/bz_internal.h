@@ -72,12 +72,30 @@ struct BinLayout {
     int64_t off_vals_b = 0;       // uint32 [cap]
     int64_t off_hist = 0;         // uint32 [radix][hist_blocks]
     int64_t off_part = 0;         // uint64 partial sums of the scans
+    int64_t off_counters = 0;     // uint32 [4] at offset 0: tile counters of the persistent
+                                  // blend kernels ([0] forward, [1] backward)
     int64_t total = 0;
 };
 BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap_pairs);
 
 inline int64_t tiles_x(const bz_opts &o) { return (o.width + o.tile_w - 1) / o.tile_w; }
 inline int64_t tiles_y(const bz_opts &o) { return (o.height + o.tile_h - 1) / o.tile_h; }
+// Tiles of the canvas, or of all canvases of a batch.
+inline int64_t num_tiles(const bz_opts &o) {
+    return o.batch ? o.batch->n_tiles : tiles_x(o) * tiles_y(o);
+}
+
+// Canvas of an index inside a batch: the last c whose offset (read by off)
+// is <= i, over the n_canvas + 1 records (empty canvases are skipped).
+template <typename Off>
+__host__ __device__ inline int batch_find(const bz_canvas *cv, int n_canvas, int64_t i, Off off) {
+    int lo = 0, hi = n_canvas - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off(cv[mid]) <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 // LDS of the per-curve backward: boundary samples (2 x double2 per column),
 // Bernstein weights and segment per column, sample-point gradients and the
@@ -89,7 +107,7 @@ inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
 // Visit masks: one plane per 8x8 quad of a tile; a plane holds, for every tile,
 // ceil(len/64) words starting at word start/64 + tile (see visit_word).
 inline int64_t visit_words_per_plane(const bz_opts &o, int64_t cap_pairs) {
-    return cap_pairs / 64 + tiles_x(o) * tiles_y(o) + 2;
+    return cap_pairs / 64 + num_tiles(o) + 2;
 }
 inline int64_t visit_words(const bz_opts &o, int64_t cap_pairs) {
     return (int64_t)(o.tile_w / 8) * (o.tile_h / 8) * visit_words_per_plane(o, cap_pairs);

@@ -71,6 +71,9 @@ struct TileArgs {
     uint32_t *n_contrib;
     uint64_t *visit;          // per (quad plane, tile batch) contribution masks
     int64_t words_per_plane;
+    const bz_canvas *canvas;  // batch canvases (null: one canvas W x H)
+    int n_canvas;
+    uint32_t *counter;        // persistent launch: next tile (null: one workgroup per tile)
     int tab_cap;              // positions of the backward's per-tile sum table
     // backward
     const float *d_image;
@@ -112,6 +115,62 @@ __device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, fl
 // never overlaps the next tile's range, so every word has one writer.
 __device__ inline int64_t visit_word(uint32_t start, int tile) {
     return (int64_t)(start >> 6) + tile;
+}
+
+// Canvas geometry of a (wave-uniform) global tile.
+struct TileGeo {
+    int W, H;          // canvas size
+    int tx, ty;        // tile coordinates inside the canvas
+    int64_t pix0;      // first pixel of the canvas
+    float bg0, bg1, bg2;
+};
+
+__device__ inline TileGeo tile_geo(const TileArgs &a, int tile) {
+    TileGeo g;
+    if (a.canvas) {
+        const int c = batch_find(a.canvas, a.n_canvas, (int64_t)tile,
+                                 [](const bz_canvas &r) { return r.tile_off; });
+        const bz_canvas &cv = a.canvas[c];
+        const int local = tile - (int)cv.tile_off;
+        g.W = cv.width;
+        g.H = cv.height;
+        g.ty = local / cv.tiles_x;
+        g.tx = local - g.ty * cv.tiles_x;
+        g.pix0 = cv.pix_off;
+        g.bg0 = cv.bg[0];
+        g.bg1 = cv.bg[1];
+        g.bg2 = cv.bg[2];
+    } else {
+        g.W = a.W;
+        g.H = a.H;
+        g.ty = tile / a.tiles_x;
+        g.tx = tile - g.ty * a.tiles_x;
+        g.pix0 = 0;
+        g.bg0 = a.bg0;
+        g.bg1 = a.bg1;
+        g.bg2 = a.bg2;
+    }
+    return g;
+}
+
+// Tile loop of a launch: one tile per workgroup (XCD-contiguous), or, when
+// the launch is persistent, tiles taken from a counter until they run out.
+template <typename Body>
+__device__ inline void for_tiles(const TileArgs &a, Body body) {
+    if (!a.counter) {
+        const int tile = xcd_tile(blockIdx.x, a.per_xcd);
+        if (tile < a.n_tiles) body(tile);
+        return;
+    }
+    __shared__ int s_next;
+    for (;;) {
+        __syncthreads();                        // the previous tile is done with LDS
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int tile = __builtin_amdgcn_readfirstlane(s_next);
+        if (tile >= a.n_tiles) break;
+        body(tile);
+    }
 }
 
 // Result of a front-to-back sweep for one pixel.
@@ -182,30 +241,29 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
 // T after the last contributor, its position, and per (quad, batch) the mask
 // of entries that contributed; without it only the image.
 template <bool kState, bool kCount>
-__global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
+__device__ inline void fwd_tile(const TileArgs &a, int tile) {
     extern __shared__ Staged s_stage[];
-    const int tile = xcd_tile(blockIdx.x, a.per_xcd);
-    if (tile >= a.n_tiles) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const TileGeo tg = tile_geo(a, tile);
     const int qx = w % a.quads_x, qy = w / a.quads_x;
-    const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
-    if (x0 >= a.W || y0 >= a.H) return;
+    const int x0 = tg.tx * a.tile_w + qx * kQuad, y0 = tg.ty * a.tile_h + qy * kQuad;
+    if (x0 >= tg.W || y0 >= tg.H) return;
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
-    const bool valid = x < a.W && y < a.H;
+    const bool valid = x < tg.W && y < tg.H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
 
-    const int64_t pix = (int64_t)y * a.W + x;
-    const int64_t plane = (int64_t)a.W * a.H;
+    const int64_t pix = tg.pix0 + (int64_t)y * tg.W + x;
+    const int64_t plane = (int64_t)tg.W * tg.H;
+    float *img = a.image + 2 * tg.pix0;     // canvas image: 3 planes from 3 * pix0
     if (a.status[1] & Status::kOverflow) {
         if (valid) {
             float nan = __int_as_float(0x7fc00000);
-            a.image[pix] = nan;
-            a.image[plane + pix] = nan;
-            a.image[2 * plane + pix] = nan;
+            img[pix] = nan;
+            img[plane + pix] = nan;
+            img[2 * plane + pix] = nan;
             if (kState) {
                 a.t_final[pix] = nan;
                 a.n_last[pix] = 0;
@@ -222,15 +280,23 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
                                                 if (kState && lane == 0) vis[k] = bits;
                                             });
     if (valid) {
-        a.image[pix] = fmaf(r.T, a.bg0, r.C0);
-        a.image[plane + pix] = fmaf(r.T, a.bg1, r.C1);
-        a.image[2 * plane + pix] = fmaf(r.T, a.bg2, r.C2);
+        img[pix] = fmaf(r.T, tg.bg0, r.C0);
+        img[plane + pix] = fmaf(r.T, tg.bg1, r.C1);
+        img[2 * plane + pix] = fmaf(r.T, tg.bg2, r.C2);
         if (kState) {
             a.t_final[pix] = r.T;
             a.n_last[pix] = r.last;
             if (kCount) a.n_contrib[pix] = r.cnt;
         }
     }
+}
+
+// Forward pass.  With kState the blend state the backward reads is written:
+// T after the last contributor, its position, and per (quad, batch) the mask
+// of entries that contributed; without it only the image.
+template <bool kState, bool kCount>
+__global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
+    for_tiles(a, [&](int tile) { fwd_tile<kState, kCount>(a, tile); });
 }
 
 // Broadcast lane 0's 64-bit value as a wave-uniform (scalar) value.  The
@@ -335,23 +401,20 @@ constexpr int kTableCap = 640;   // tile-list positions pooled in LDS by the bac
 constexpr int kVisCap = 128;
 
 template <bool kRecompute>
-__global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
+__device__ inline void bwd_tile(const TileArgs &a, int tile) {
     // dynamic LDS: [waves][64] staged records, [waves][64] their ids, the sum
     // table, and (kRecompute) [waves][kVisCap] batch masks
     extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_top[16];
-    const int tile = xcd_tile(blockIdx.x, a.per_xcd);
-    if (tile >= a.n_tiles) return;                       // whole block
-    if (a.status[1] & Status::kOverflow) return;         // whole block
     const int nwaves = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const TileGeo tg = tile_geo(a, tile);
     const int qx = w % a.quads_x, qy = w / a.quads_x;
-    const int x0 = tx * a.tile_w + qx * kQuad, y0 = ty * a.tile_h + qy * kQuad;
-    const bool wave_on = x0 < a.W && y0 < a.H;           // quad inside the canvas
+    const int x0 = tg.tx * a.tile_w + qx * kQuad, y0 = tg.ty * a.tile_h + qy * kQuad;
+    const bool wave_on = x0 < tg.W && y0 < tg.H;         // quad inside the canvas
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
-    const bool valid = wave_on && x < a.W && y < a.H;
+    const bool valid = wave_on && x < tg.W && y < tg.H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
@@ -369,8 +432,9 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
     const uint32_t len = a.ranges[2 * tile + 1] - start;
     const uint64_t *vis =
         kRecompute ? nullptr : a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile);
-    const int64_t pix = (int64_t)y * a.W + x;
-    const int64_t plane = (int64_t)a.W * a.H;
+    const int64_t pix = tg.pix0 + (int64_t)y * tg.W + x;
+    const int64_t plane = (int64_t)tg.W * tg.H;
+    const float *dimg = a.d_image + 2 * tg.pix0;   // canvas planes from 3 * pix0
     uint32_t nl = 0;
     float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
     if (kRecompute) {
@@ -388,11 +452,11 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
         T = a.t_final[pix];
     }
     if (valid) {
-        g0 = a.d_image[pix];
-        g1 = a.d_image[plane + pix];
-        g2 = a.d_image[2 * plane + pix];
+        g0 = dimg[pix];
+        g1 = dimg[plane + pix];
+        g2 = dimg[2 * plane + pix];
     }
-    float A0 = a.bg0, A1 = a.bg1, A2 = a.bg2;
+    float A0 = tg.bg0, A1 = tg.bg1, A2 = tg.bg2;
     uint32_t top = nl;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
@@ -534,6 +598,12 @@ __global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
         const float val = table[v * tab_cap + p];
         if (val != 0.f) atomicAdd(a.d_gauss + (int64_t)v * ng + a.ids[start + p], val);
     }
+}
+
+template <bool kRecompute>
+__global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
+    if (a.status[1] & Status::kOverflow) return;         // whole grid
+    for_tiles(a, [&](int tile) { bwd_tile<kRecompute>(a, tile); });
 }
 
 __global__ void k_zero(float *p, int64_t n) {
@@ -804,6 +874,43 @@ __global__ __launch_bounds__(256) void k_l2(const float *__restrict__ img,
     }
 }
 
+__global__ void k_counter_reset(uint32_t *counter) {
+    if (threadIdx.x == 0) counter[0] = 0u;
+}
+
+// Workgroups of a persistent launch: as many as are resident on the device at
+// once (occupancy of this kernel and block shape x compute units), at most
+// one per tile.  Host queries only (nothing is enqueued), so the launch can be
+// captured in a graph.
+int persistent_grid(const void *kernel, int threads, size_t lds, int n_tiles) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
+        return n_tiles;
+    const int64_t blocks = (int64_t)(cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+    return blocks < n_tiles ? (int)blocks : n_tiles;
+}
+
+// Launch a blend kernel over all tiles: one workgroup per tile, or persistent
+// workgroups behind a counter that is cleared first (by a kernel, so that the
+// sequence can be captured in a graph).
+template <typename K>
+void launch_tiles(K kernel, TileArgs &a, const bz_bins &b, const bz_opts &o, int which,
+                  int threads, size_t lds, hipStream_t s) {
+    if (o.persistent && a.n_tiles > 0) {
+        uint32_t *counters = (uint32_t *)b.workspace;     // BinLayout::off_counters == 0
+        a.counter = counters + which;
+        hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, s, a.counter);
+        int grid = persistent_grid(reinterpret_cast<const void *>(kernel), threads, lds,
+                                   a.n_tiles);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a);
+    } else {
+        a.counter = nullptr;
+        hipLaunchKernelGGL(kernel, dim3(8 * a.per_xcd), dim3(threads), lds, s, a);
+    }
+}
+
 TileArgs tile_args(const float *rec, const bz_bins &b, const bz_opts &o) {
     TileArgs a = {};
     a.rec = (const float4 *)rec;
@@ -812,10 +919,14 @@ TileArgs tile_args(const float *rec, const bz_bins &b, const bz_opts &o) {
     a.status = b.status;
     a.W = o.width;
     a.H = o.height;
+    if (o.batch) {
+        a.canvas = o.batch->canvas;
+        a.n_canvas = o.batch->n_canvas;
+    }
     a.tile_w = o.tile_w;
     a.tile_h = o.tile_h;
     a.tiles_x = (int)tiles_x(o);
-    a.n_tiles = (int)(tiles_x(o) * tiles_y(o));
+    a.n_tiles = (int)num_tiles(o);
     a.per_xcd = (int)cdiv(a.n_tiles, 8);
     a.quads_x = o.tile_w / kQuad;
     a.bg0 = o.bg[0];
@@ -838,9 +949,8 @@ hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, floa
     a.image = image;
     int threads = o.tile_w * o.tile_h;
     size_t lds = sizeof(Staged) * (size_t)threads;
-    dim3 grid(8 * a.per_xcd);
     if (!st) {
-        hipLaunchKernelGGL((k_fwd<false, false>), grid, dim3(threads), lds, s, a);
+        launch_tiles(k_fwd<false, false>, a, b, o, 0, threads, lds, s);
         return hipGetLastError();
     }
     a.t_final = st->t_final;
@@ -848,9 +958,9 @@ hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, floa
     a.n_contrib = st->n_contrib;
     a.visit = st->visit;
     if (st->n_contrib)
-        hipLaunchKernelGGL((k_fwd<true, true>), grid, dim3(threads), lds, s, a);
+        launch_tiles(k_fwd<true, true>, a, b, o, 0, threads, lds, s);
     else
-        hipLaunchKernelGGL((k_fwd<true, false>), grid, dim3(threads), lds, s, a);
+        launch_tiles(k_fwd<true, false>, a, b, o, 0, threads, lds, s);
     return hipGetLastError();
 }
 
@@ -871,15 +981,14 @@ hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
     a.tab_cap = kTableCap;
     size_t lds = (sizeof(Staged) + sizeof(uint32_t)) * (size_t)threads +
                  sizeof(float) * 9 * (size_t)kTableCap;
-    dim3 grid(8 * a.per_xcd);
     if (st) {
         a.t_final = st->t_final;
         a.n_last = st->n_last;
         a.visit = st->visit;
-        hipLaunchKernelGGL(k_bwd_tiles<false>, grid, dim3(threads), lds, s, a);
+        launch_tiles(k_bwd_tiles<false>, a, b, o, 1, threads, lds, s);
     } else {
         lds += sizeof(uint64_t) * kVisCap * (size_t)(threads / 64);
-        hipLaunchKernelGGL(k_bwd_tiles<true>, grid, dim3(threads), lds, s, a);
+        launch_tiles(k_bwd_tiles<true>, a, b, o, 1, threads, lds, s);
     }
     return hipGetLastError();
 }

@@ -260,6 +260,38 @@ def paper_analog(seed: int = 0, closed: bool = False) -> Scene:
     return mixed(seed, 2040, 1344, 0, 2048, K=24, S_open=3, name="open-2040x1344-2048c")
 
 
+def batched(seed: int = 0, n_canvas: int = 64, side=(128, 1024), curves=(256, 8192),
+            k_range=(16, 32)) -> list:
+    """Many canvases of uneven size and curve count (open single-segment curves).
+
+    Per canvas: width and height independently log-uniform over ``side`` px,
+    floor(log-uniform over ``curves``) curves, K per curve uniform over the
+    integers of ``k_range``.  Draw order of the generator: all widths, all
+    heights, all curve counts, one child seed per canvas; each canvas then
+    draws control points (uniform over its area), widths U[1,4], colours
+    U[0,1]^3, opacities U[0.3,1] and the K values from its child seed.
+    """
+    rng = np.random.default_rng(seed)
+    lo, hi = math.log(side[0]), math.log(side[1])
+    Ws = np.clip(np.floor(np.exp(rng.uniform(lo, hi, n_canvas))), side[0], side[1]).astype(int)
+    Hs = np.clip(np.floor(np.exp(rng.uniform(lo, hi, n_canvas))), side[0], side[1]).astype(int)
+    ncs = np.floor(np.exp(rng.uniform(math.log(curves[0]), math.log(curves[1]), n_canvas)))
+    ncs = np.clip(ncs, curves[0], curves[1]).astype(int)
+    child = rng.integers(0, 2 ** 31 - 1, n_canvas)
+    out = []
+    for c in range(n_canvas):
+        W, H, n = int(Ws[c]), int(Hs[c]), int(ncs[c])
+        r = np.random.default_rng(int(child[c]))
+        ctrl = r.uniform(0.0, 1.0, (n, 4, 2)) * np.array([W, H], np.float64)
+        widths = r.uniform(1.0, 4.0, n)
+        colors = r.uniform(0.0, 1.0, (n, 3))
+        opas = r.uniform(0.3, 1.0, (n, 1))
+        ks = r.integers(k_range[0], k_range[1] + 1, n)
+        out.append(_assemble(W, H, [OPEN] * n, [1] * n, ks, [0] * n, list(ctrl), widths, colors,
+                             list(opas), np.arange(n), name=f"canvas{c}-{W}x{H}-{n}c"))
+    return out
+
+
 def small_mixed(seed: int, W: int = 48, H: int = 40, n_closed: int = 3, n_open: int = 4,
                 K: int = 8, R: int = 3, extent=(6.0, 30.0)) -> Scene:
     """Small mixed scenes for finite-difference and parity tests."""
@@ -277,3 +309,34 @@ WORKLOADS = {
 def gaussian_noise(seed: int, shape, sigma: float) -> np.ndarray:
     """Additive N(0, sigma^2) noise of the given shape (float64), seeded."""
     return np.random.default_rng(seed).normal(0.0, sigma, shape)
+
+
+def concat(parts) -> Scene:
+    """One curve set holding the curves of several canvases, canvas by canvas:
+    the draw order of canvas c follows every curve of canvases before it.
+    Width and height are the largest of the parts (a batch's canvases keep
+    their own sizes and backgrounds in the batch layout)."""
+    kinds, nsegs, ks, rs, ctrl, taus, ws, cols, opas, ranks = ([] for _ in range(10))
+    ctrl_off, tau_off, opa_off = [0], [0], [0]
+    base = 0
+    for sc in parts:
+        n = sc.n_curves
+        kinds.append(sc.kind); nsegs.append(sc.nseg); ks.append(sc.k_samples)
+        rs.append(sc.r_interior); ctrl.append(np.asarray(sc.ctrl).reshape(-1, 2))
+        taus.append(np.asarray(sc.tau).reshape(-1)); ws.append(sc.stroke_w)
+        cols.append(np.asarray(sc.color).reshape(-1, 3)); opas.append(np.asarray(sc.opacity).reshape(-1))
+        ranks.append(np.asarray(sc.rank) + base)
+        ctrl_off.extend((np.asarray(sc.ctrl_off[1:]) + ctrl_off[-1]).tolist())
+        tau_off.extend((np.asarray(sc.tau_off[1:]) + tau_off[-1]).tolist())
+        opa_off.extend((np.asarray(sc.opa_off[1:]) + opa_off[-1]).tolist())
+        base += n
+    cat = lambda xs, dt: np.ascontiguousarray(np.concatenate(xs), dt)
+    return Scene(width=max(sc.width for sc in parts), height=max(sc.height for sc in parts),
+                 bg=np.asarray(parts[0].bg, np.float32), kind=cat(kinds, np.int32),
+                 nseg=cat(nsegs, np.int32), k_samples=cat(ks, np.int32),
+                 r_interior=cat(rs, np.int32), ctrl=cat(ctrl, np.float32),
+                 ctrl_off=np.asarray(ctrl_off, np.int32), tau=cat(taus, np.float32),
+                 tau_off=np.asarray(tau_off, np.int32), stroke_w=cat(ws, np.float32),
+                 color=cat(cols, np.float32), opacity=cat(opas, np.float32),
+                 opa_off=np.asarray(opa_off, np.int32), rank=cat(ranks, np.int32),
+                 name=f"batch-{len(parts)}", meta={})

@@ -145,3 +145,73 @@ def test_sample_rejects_small_capacity_on_host():
         setattr(cv, f, 4096)                               # never dereferenced on the host
     g = bz.Gaussians(8, 0, 4096)
     assert lib.bz_sample(C.byref(cv), C.byref(o), C.byref(g), None) == bz.BZ_ERR_CAPACITY
+
+
+def _batch_layout(sizes, goff, bg=None, tile=(16, 16)):
+    lib = bz.load_library()
+    o = bz.make_opts(1, 1, (1.0, 1.0, 1.0), bz.RenderOptions(tile_w=tile[0], tile_h=tile[1]))
+    n = len(sizes)
+    size = np.ascontiguousarray(sizes, np.int32)
+    g = np.ascontiguousarray(goff, np.int64)
+    bgp = None if bg is None else np.ascontiguousarray(bg, np.float32).ctypes.data_as(C.c_void_p)
+    recs = (bz.Canvas * (n + 1))()
+    batch = bz.Batch()
+    st = lib.bz_batch_layout(C.byref(o), n, size.ctypes.data_as(C.c_void_p), bgp,
+                             g.ctypes.data_as(C.c_void_p), C.addressof(recs), C.byref(batch))
+    return st, recs, batch
+
+
+def test_batch_records_have_the_c_layout():
+    assert C.sizeof(bz.Canvas) == 56
+    assert C.sizeof(bz.Batch) == 40
+    assert bz.Opts.batch.offset == 56 and C.sizeof(bz.Opts) == 64
+    assert bz.Canvas.bg.offset == 40
+
+
+def test_batch_layout_numbers_tiles_and_pixels_canvas_by_canvas():
+    sizes = [(17, 9), (1, 1), (128, 40), (33, 200)]
+    goff = [0, 10, 10, 500, 777]
+    st, recs, batch = _batch_layout(sizes, goff, bg=[[0.1, 0.2, 0.3]] * 4, tile=(32, 8))
+    assert st == bz.BZ_OK
+    tiles = [((W + 31) // 32) * ((H + 7) // 8) for W, H in sizes]
+    pix = [W * H for W, H in sizes]
+    for c, (W, H) in enumerate(sizes):
+        r = recs[c]
+        assert (r.width, r.height) == (W, H)
+        assert (r.tiles_x, r.tiles_y) == ((W + 31) // 32, (H + 7) // 8)
+        assert r.tile_off == sum(tiles[:c]) and r.pix_off == sum(pix[:c])
+        assert r.gauss_off == goff[c]
+        assert abs(r.bg[2] - 0.3) < 1e-7
+    end = recs[len(sizes)]
+    assert (end.tile_off, end.pix_off, end.gauss_off) == (sum(tiles), sum(pix), 777)
+    assert (batch.n_canvas, batch.n_tiles, batch.n_pixels, batch.n_gauss) == \
+        (4, sum(tiles), sum(pix), 777)
+
+
+@pytest.mark.parametrize("sizes,goff", [
+    ([], [0]),                                  # no canvas
+    ([(0, 5)], [0, 3]),                         # empty canvas side
+    ([(5, 40000)], [0, 3]),                     # side beyond the limit
+    ([(5, 5), (5, 5)], [0, 4, 2]),              # Gaussian offsets decrease
+    ([(5, 5)], [1, 4]),                         # offsets not from 0
+])
+def test_batch_layout_rejects_bad_batches(sizes, goff):
+    if not sizes:
+        lib = bz.load_library()
+        o = bz.make_opts(1, 1, (1, 1, 1), bz.RenderOptions())
+        assert lib.bz_batch_layout(C.byref(o), 0, None, None, None, None,
+                                   C.byref(bz.Batch())) == bz.BZ_ERR_ARG
+        return
+    st, _, _ = _batch_layout(sizes, goff)
+    assert st == bz.BZ_ERR_ARG
+
+
+def test_concatenated_scene_keeps_each_canvas_in_draw_order():
+    parts = [scenes.small_mixed(1, n_closed=2, n_open=3), scenes.uniform_open(2, 40, 30, 5, 8)]
+    sc = scenes.concat(parts)
+    assert sc.n_curves == 10 and sc.n_gauss == parts[0].n_gauss + parts[1].n_gauss
+    order, goff, _, _ = bz.layout_host(sc)
+    # every curve of the first canvas is drawn before every curve of the second
+    assert set(order[:5]) == set(range(5)) and set(order[5:]) == set(range(5, 10))
+    assert goff[5] == parts[0].n_gauss
+    assert np.array_equal(sc.ctrl[sc.ctrl_off[5]:], parts[1].ctrl.reshape(-1, 2))

@@ -243,7 +243,7 @@ class Rasterizer:
             _check("bz_batch_layout", self.lib.bz_batch_layout(
                 C.byref(self.opts), n, p(size), p(bg), p(cgoff), C.addressof(recs),
                 C.byref(self.batch)))
-            raw = np.frombuffer(bytes(recs), np.uint8)
+            raw = np.frombuffer(bytes(recs), np.uint8).copy()
             self.canvas_table = t(raw, torch.uint8)
             self.batch.canvas = self.canvas_table.data_ptr()
             self.opts.batch = C.addressof(self.batch)

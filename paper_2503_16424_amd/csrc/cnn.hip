@@ -1,0 +1,426 @@
+// cnn.hip -- BF16 implicit-GEMM convolutions on the gfx950 matrix cores.
+//
+// All three passes of a convolution are one GEMM C[m][n] = sum_k A[m][k] B[k][n]
+// whose operands are gathered on the fly (no im2col buffer):
+//
+//   forward      m = output pixel, n = output channel, k = (dy, dx, in channel)
+//                A = shifted input pixels, B = filters
+//   input grad   m = input pixel,  n = in channel,     k = (dy, dx, out channel)
+//                A = the output gradients that pixel fed, B = filters
+//   filter grad  m = out channel,  n = (dy, dx, in channel), k = output pixel
+//                A = output gradients, B = shifted input pixels
+//
+// A workgroup (4 waves) computes a 64 x 64 tile of C in steps of 32 along k:
+// the 256 threads gather the A and B slices (8 consecutive k per thread) into
+// LDS with k contiguous, then each wave runs 2 x 2 v_mfma_f32_16x16x32_bf16 on
+// its 32 x 32 quarter.  For that instruction lane l supplies row (l mod 16)
+// of A and column (l mod 16) of B, each with the 8 k values 8 (l / 16) ..
+// 8 (l / 16) + 7, and receives rows 4 (l / 16) .. 4 (l / 16) + 3 of column
+// (l mod 16) of the 16 x 16 result.  The filter gradient splits its long k
+// (all output pixels) over workgroups and adds the partial tiles with float
+// atomics.
+#include "bz_internal.h"
+#include "../../include/bz_cnn.h"
+
+namespace bz {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+constexpr int kLdsK = kBK + 8;          // row pitch in bf16 (80 bytes) against bank conflicts
+constexpr int kSplitRows = 1024;        // filter gradient: output pixels per workgroup
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ inline __bf16 bf_bits(uint16_t u) { return __builtin_bit_cast(__bf16, u); }
+__device__ inline float bf_to_f(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+
+// float -> bfloat16 bits, round to nearest even (finite inputs; NaN stays NaN)
+__device__ inline uint16_t f_to_bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct Shape {
+    int n, h, w, c, k, r, s, p, ho, wo;
+};
+
+// Input pixel read by output pixel m through filter tap `tap`, or -1 (padding).
+__device__ inline int64_t in_pixel(const Shape &S, int64_t m, int tap) {
+    const int64_t hw = (int64_t)S.ho * S.wo;
+    const int64_t b = m / hw;
+    const int rem = (int)(m - b * hw);
+    const int oy = rem / S.wo, ox = rem - (rem / S.wo) * S.wo;
+    const int ky = tap / S.r, kx = tap - (tap / S.r) * S.r;
+    const int iy = oy * S.s - S.p + ky, ix = ox * S.s - S.p + kx;
+    if (iy < 0 || ix < 0 || iy >= S.h || ix >= S.w) return -1;
+    return (b * S.h + iy) * S.w + ix;
+}
+
+// Output pixel that input pixel m feeds through tap `tap`, or -1.
+__device__ inline int64_t out_pixel(const Shape &S, int64_t m, int tap) {
+    const int64_t hw = (int64_t)S.h * S.w;
+    const int64_t b = m / hw;
+    const int rem = (int)(m - b * hw);
+    const int iy = rem / S.w, ix = rem - (rem / S.w) * S.w;
+    const int ky = tap / S.r, kx = tap - (tap / S.r) * S.r;
+    const int ty = iy + S.p - ky, tx = ix + S.p - kx;
+    if (ty < 0 || tx < 0 || ty % S.s || tx % S.s) return -1;
+    const int oy = ty / S.s, ox = tx / S.s;
+    if (oy >= S.ho || ox >= S.wo) return -1;
+    return (b * S.ho + oy) * S.wo + ox;
+}
+
+enum Mode { kFwd = 0, kBwdData = 1, kBwdWeight = 2 };
+
+struct GemmArgs {
+    Shape S;
+    int64_t M, N, K;          // GEMM sizes
+    const uint16_t *x;        // input activations (bf16)
+    const uint16_t *w;        // filters (bf16)
+    const float *dy;          // output gradients (f32)
+    const float *bias;
+    const uint16_t *mask;     // bwd data: zero where the layer input is <= 0
+    int relu;
+    float *out_f;             // fwd y, bwd-data dx, bwd-weight dw
+    uint16_t *out_b;          // fwd y in bf16
+    int64_t k_chunk;          // bwd weight: k range per workgroup
+};
+
+// A[m][k .. k+7] and B[k .. k+7][n] for each mode (zeros outside the GEMM).
+template <int MODE>
+__device__ inline void gather_a(const GemmArgs &g, int64_t m, int64_t k0, int64_t kend,
+                                uint16_t (&v)[8]) {
+    const Shape &S = g.S;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t k = k0 + j;
+        uint16_t u = 0;
+        if (m < g.M && k < kend) {
+            if (MODE == kFwd) {
+                const int tap = (int)(k / S.c), ci = (int)(k - (int64_t)tap * S.c);
+                const int64_t px = in_pixel(S, m, tap);
+                if (px >= 0) u = g.x[px * S.c + ci];
+            } else if (MODE == kBwdData) {
+                const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
+                const int64_t px = out_pixel(S, m, tap);
+                if (px >= 0) u = f_to_bf(g.dy[px * S.k + co]);
+            } else {   // m = out channel, k = output pixel
+                u = f_to_bf(g.dy[k * S.k + m]);
+            }
+        }
+        v[j] = u;
+    }
+}
+
+template <int MODE>
+__device__ inline void gather_b(const GemmArgs &g, int64_t n, int64_t k0, int64_t kend,
+                                uint16_t (&v)[8]) {
+    const Shape &S = g.S;
+    const int64_t kf = (int64_t)S.r * S.r * S.c;     // filter length per output channel
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t k = k0 + j;
+        uint16_t u = 0;
+        if (n < g.N && k < kend) {
+            if (MODE == kFwd) {
+                u = g.w[n * kf + k];
+            } else if (MODE == kBwdData) {        // n = in channel, k = (tap, out channel)
+                const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
+                u = g.w[(int64_t)co * kf + (int64_t)tap * S.c + n];
+            } else {                              // n = (tap, in channel), k = output pixel
+                const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
+                const int64_t px = in_pixel(S, k, tap);
+                if (px >= 0) u = g.x[px * S.c + ci];
+            }
+        }
+        v[j] = u;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_igemm(GemmArgs g) {
+    __shared__ __align__(16) uint16_t sA[kBM][kLdsK];
+    __shared__ __align__(16) uint16_t sB[kBN][kLdsK];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * kBN;
+    int64_t kbeg = 0, kend = g.K;
+    if (MODE == kBwdWeight) {
+        kbeg = (int64_t)blockIdx.z * g.k_chunk;
+        kend = kbeg + g.k_chunk < g.K ? kbeg + g.k_chunk : g.K;
+    }
+    const int wm = wave >> 1, wn = wave & 1;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int lrow = t >> 2, lk = (t & 3) * 8;        // this thread's gather slot
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+        uint16_t va[8], vb[8];
+        gather_a<MODE>(g, m0 + lrow, k0 + lk, kend, va);
+        gather_b<MODE>(g, n0 + lrow, k0 + lk, kend, vb);
+        __syncthreads();                              // previous step's reads are done
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sA[lrow][lk + j] = va[j];
+            sB[lrow][lk + j] = vb[j];
+        }
+        __syncthreads();
+        const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            bf16x8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = bf_bits(sA[wm * 32 + i * 16 + r16][kq + j]);
+#pragma unroll
+            for (int jn = 0; jn < 2; ++jn) {
+                bf16x8 b;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[j] = bf_bits(sB[wn * 32 + jn * 16 + r16][kq + j]);
+                acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][jn], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: lane holds rows 4 (lane / 16) + e, column lane mod 16 of each block
+    const int col = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jn = 0; jn < 2; ++jn)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t m = m0 + wm * 32 + i * 16 + rq + e;
+                const int64_t n = n0 + wn * 32 + jn * 16 + col;
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][jn][e];
+                if (MODE == kFwd) {
+                    if (g.bias) v += g.bias[n];
+                    if (g.relu) v = fmaxf(v, 0.f);
+                    if (g.out_f) g.out_f[m * g.N + n] = v;
+                    if (g.out_b) g.out_b[m * g.N + n] = f_to_bf(v);
+                } else if (MODE == kBwdData) {
+                    if (g.mask && !(bf_to_f(g.mask[m * g.N + n]) > 0.f)) v = 0.f;
+                    g.out_f[m * g.N + n] = v;
+                } else {
+                    atomicAdd(&g.out_f[m * g.N + n], v);
+                }
+            }
+}
+
+__global__ void k_fill0(float *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.f;
+}
+
+// db[o] = sum over output pixels of dy[.][o]: one workgroup per channel block.
+__global__ __launch_bounds__(256) void k_bias_grad(const float *dy, int64_t rows, int k,
+                                                   float *db) {
+    const int o = blockIdx.x;
+    float s = 0.f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) s += dy[r * k + o];
+    __shared__ float part[256];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) part[threadIdx.x] += part[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] = part[0];
+}
+
+__global__ void k_to_bf16(const float *src, uint16_t *dst, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = f_to_bf(src[i]);
+}
+
+__global__ void k_patches(const float *img, int W, int H, const int32_t *xy, int np, int side,
+                          float fill, uint16_t *out) {
+    const int64_t per = (int64_t)side * side * 3;
+    const int64_t total = per * np;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const int p = (int)(i / per);
+        const int rem = (int)(i - (int64_t)p * per);
+        const int ch = rem % 3, pix = rem / 3;
+        const int x = xy[2 * p] + pix % side, y = xy[2 * p + 1] + pix / side;
+        float v = fill;
+        if (x >= 0 && y >= 0 && x < W && y < H) v = img[((int64_t)ch * H + y) * W + x];
+        out[i] = f_to_bf(v);
+    }
+}
+
+Shape shape_of(const bz_conv &c) {
+    return Shape{c.n, c.h, c.w, c.c, c.k, c.r, c.stride, c.pad, c.ho, c.wo};
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_conv_fwd(const bz_conv &c, const uint16_t *x, const uint16_t *w,
+                           const float *bias, int relu, float *y, uint16_t *yb, hipStream_t s) {
+    GemmArgs g = {};
+    g.S = shape_of(c);
+    g.M = (int64_t)c.n * c.ho * c.wo;
+    g.N = c.k;
+    g.K = (int64_t)c.r * c.r * c.c;
+    g.x = x;
+    g.w = w;
+    g.bias = bias;
+    g.relu = relu;
+    g.out_f = y;
+    g.out_b = yb;
+    dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), 1);
+    hipLaunchKernelGGL(k_igemm<kFwd>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_bwd_data(const bz_conv &c, const float *dy, const uint16_t *w,
+                                const uint16_t *mask, float *dx, hipStream_t s) {
+    GemmArgs g = {};
+    g.S = shape_of(c);
+    g.M = (int64_t)c.n * c.h * c.w;
+    g.N = c.c;
+    g.K = (int64_t)c.r * c.r * c.k;
+    g.dy = dy;
+    g.w = w;
+    g.mask = mask;
+    g.out_f = dx;
+    dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), 1);
+    hipLaunchKernelGGL(k_igemm<kBwdData>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_bwd_weight(const bz_conv &c, const float *dy, const uint16_t *x,
+                                  float *dw, float *db, hipStream_t s) {
+    GemmArgs g = {};
+    g.S = shape_of(c);
+    g.M = c.k;
+    g.N = (int64_t)c.r * c.r * c.c;
+    g.K = (int64_t)c.n * c.ho * c.wo;
+    g.dy = dy;
+    g.x = x;
+    g.out_f = dw;
+    g.k_chunk = kSplitRows;
+    const int64_t nz = g.M * g.N;
+    hipLaunchKernelGGL(k_fill0, dim3((unsigned)cdiv(nz, 256) < 4096 ? (unsigned)cdiv(nz, 256) : 4096),
+                       dim3(256), 0, s, dw, nz);
+    dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), (unsigned)cdiv(g.K, g.k_chunk));
+    hipLaunchKernelGGL(k_igemm<kBwdWeight>, grid, dim3(256), 0, s, g);
+    if (db) hipLaunchKernelGGL(k_bias_grad, dim3(c.k), dim3(256), 0, s, dy, g.K, c.k, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s) {
+    if (n > 0) {
+        int64_t b = cdiv(n, 256);
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, src,
+                           dst, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_patches(const float *img, int W, int H, const int32_t *xy, int np, int side,
+                          float fill, uint16_t *out, hipStream_t s) {
+    int64_t total = (int64_t)side * side * 3 * np;
+    if (total > 0) {
+        int64_t b = cdiv(total, 256);
+        hipLaunchKernelGGL(k_patches, dim3((unsigned)(b < 8192 ? b : 8192)), dim3(256), 0, s, img,
+                           W, H, xy, np, side, fill, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bz
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace bz;
+
+extern "C" {
+
+bz_status bz_conv_shape(bz_conv *cv) {
+    if (!cv) return BZ_ERR_ARG;
+    if (cv->n < 1 || cv->h < 1 || cv->w < 1 || cv->c < 1 || cv->k < 1) return BZ_ERR_ARG;
+    if (cv->r != 1 && cv->r != 3) return BZ_ERR_ARG;
+    if (cv->stride < 1 || cv->stride > 4 || cv->pad < 0 || cv->pad >= cv->r) return BZ_ERR_ARG;
+    const int64_t ho = ((int64_t)cv->h + 2 * cv->pad - cv->r) / cv->stride + 1;
+    const int64_t wo = ((int64_t)cv->w + 2 * cv->pad - cv->r) / cv->stride + 1;
+    if ((int64_t)cv->h + 2 * cv->pad < cv->r || (int64_t)cv->w + 2 * cv->pad < cv->r || ho < 1 ||
+        wo < 1)
+        return BZ_ERR_ARG;
+    const int64_t lim = int64_t(1) << 31;
+    if ((int64_t)cv->n * cv->h * cv->w * cv->c >= lim || (int64_t)cv->n * ho * wo * cv->k >= lim ||
+        (int64_t)cv->k * cv->r * cv->r * cv->c >= lim)
+        return BZ_ERR_UNSUPPORTED;
+    cv->ho = (int32_t)ho;
+    cv->wo = (int32_t)wo;
+    return BZ_OK;
+}
+
+static bz_status check_conv(const bz_conv *cv) {
+    if (!cv) return BZ_ERR_ARG;
+    bz_conv c = *cv;
+    bz_status st = bz_conv_shape(&c);
+    if (st != BZ_OK) return st;
+    if (c.ho != cv->ho || c.wo != cv->wo) return BZ_ERR_ARG;
+    return BZ_OK;
+}
+
+static bz_status done(hipError_t e) { return e == hipSuccess ? BZ_OK : BZ_ERR_HIP; }
+
+bz_status bz_conv_fwd(const bz_conv *cv, const uint16_t *x, const uint16_t *w, const float *bias,
+                      int32_t relu, float *y, uint16_t *y_bf16, hipStream_t s) {
+    bz_status st = check_conv(cv);
+    if (st != BZ_OK) return st;
+    if (!x || !w || (!y && !y_bf16) || (relu != 0 && relu != 1)) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return done(launch_conv_fwd(*cv, x, w, bias, relu, y, y_bf16, s));
+}
+
+bz_status bz_conv_bwd_data(const bz_conv *cv, const float *dy, const uint16_t *w,
+                           const uint16_t *x_mask, float *dx, hipStream_t s) {
+    bz_status st = check_conv(cv);
+    if (st != BZ_OK) return st;
+    if (!dy || !w || !dx) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return done(launch_conv_bwd_data(*cv, dy, w, x_mask, dx, s));
+}
+
+bz_status bz_conv_bwd_weight(const bz_conv *cv, const float *dy, const uint16_t *x, float *dw,
+                             float *db, hipStream_t s) {
+    bz_status st = check_conv(cv);
+    if (st != BZ_OK) return st;
+    if (!dy || !x || !dw) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return done(launch_conv_bwd_weight(*cv, dy, x, dw, db, s));
+}
+
+bz_status bz_f32_to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s) {
+    if (n < 0 || (n > 0 && (!src || !dst))) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return done(launch_to_bf16(src, dst, n, s));
+}
+
+bz_status bz_extract_patches(const float *image, int32_t width, int32_t height, const int32_t *xy,
+                             int32_t n_patch, int32_t side, float fill, uint16_t *out,
+                             hipStream_t s) {
+    if (width < 1 || height < 1 || n_patch < 0 || side < 1 || side > 4096) return BZ_ERR_ARG;
+    if (n_patch > 0 && (!image || !xy || !out)) return BZ_ERR_ARG;
+    if ((int64_t)side * side * 3 * n_patch >= (int64_t(1) << 40)) return BZ_ERR_UNSUPPORTED;
+    (void)hipGetLastError();
+    return done(launch_patches(image, width, height, xy, n_patch, side, fill, out, s));
+}
+
+}  // extern "C"

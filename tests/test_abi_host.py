@@ -12,18 +12,24 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "bz.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bz_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(bz_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
+    from paper_2503_16424_amd import cnn
     lib = bz.load_library()
     names = _declared_functions()
-    assert len(names) >= 9
+    assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
-    assert set(names) == set(bz.EXPORTS)
+    assert set(names) == set(bz.EXPORTS) | set(cnn.EXPORTS)
 
 
 def test_status_strings():
@@ -215,3 +221,20 @@ def test_concatenated_scene_keeps_each_canvas_in_draw_order():
     assert set(order[:5]) == set(range(5)) and set(order[5:]) == set(range(5, 10))
     assert goff[5] == parts[0].n_gauss
     assert np.array_equal(sc.ctrl[sc.ctrl_off[5]:], parts[1].ctrl.reshape(-1, 2))
+
+
+def test_conv_shape_validation():
+    from paper_2503_16424_amd import cnn
+    d = cnn.conv_desc(2, 32, 32, 3, 64, 3, 2, 1)
+    assert (d.ho, d.wo) == (16, 16)
+    lib = cnn.lib()
+    for bad in [(0, 8, 8, 3, 4, 3, 1, 1), (1, 8, 8, 3, 4, 2, 1, 0), (1, 8, 8, 3, 4, 3, 1, 3),
+                (1, 1, 1, 3, 4, 3, 1, 0), (1, 8, 8, 3, 4, 3, 0, 1)]:
+        assert lib.bz_conv_shape(C.byref(cnn.ConvDesc(*bad, 0, 0))) == bz.BZ_ERR_ARG, bad
+    big = cnn.ConvDesc(1 << 15, 256, 256, 64, 64, 3, 1, 1, 0, 0)
+    assert lib.bz_conv_shape(C.byref(big)) == bz.BZ_ERR_UNSUPPORTED
+    # a descriptor whose output size was not set by bz_conv_shape is rejected
+    d2 = cnn.ConvDesc(2, 32, 32, 3, 64, 3, 2, 1, 15, 16)
+    assert lib.bz_conv_fwd(C.byref(d2), 1, 1, None, 0, 1, None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_conv_fwd(C.byref(d), None, 1, None, 0, 1, None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_conv_fwd(C.byref(d), 1, 1, None, 2, 1, None, None) == bz.BZ_ERR_ARG

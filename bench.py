@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the timed steps, copy a MIB-sized buffer once (a known-size "
                          "kernel to scale hardware byte counters against)")
+    ap.add_argument("--no-learned-init", action="store_true",
+                    help="skip the steps-to-PSNR measurement of the learned initialiser")
     ap.add_argument("--cpu-rows", type=int, default=128,
                     help="rows of the frame the CPU oracle renders for its baseline")
     return ap.parse_args()
@@ -113,6 +115,32 @@ def cpu_baseline(sc, target, rows):
                         f"({rows} of {H}, {t3 - t2:.2f} s) scaled by {H / rows:.0f}; "
                         f"host {platform.processor() or platform.machine()}"),
                 seconds=t4 - t0)
+
+
+def learned_init_figure(size=1024, steps=1000, seed=77):
+    """Second half of the metric: steps the learned start needs to reach the
+    PSNR the uniform random start has after `steps` Adam steps (learning rates
+    of Sec. 4.1), on one synthetic 1024x1024 target."""
+    import numpy as np
+
+    from paper_2503_16424_amd import cnn, learned_init
+    from paper_2503_16424_amd.optim import PAPER_LR
+    if not os.path.exists(learned_init.WEIGHTS):
+        return None
+    print("# learned initialiser: steps-to-PSNR at 1024x1024", file=sys.stderr, flush=True)
+    net = cnn.CurveNet()
+    with np.load(learned_init.WEIGHTS, allow_pickle=False) as f:
+        net.load_state_dict({k: f[k] for k in f.files})
+    o = learned_init.evaluate(net, size, steps, seed, sets={"paper_lr": dict(PAPER_LR)})
+    e = o["paper_lr"]
+    return {"metric": "steps to the random start's PSNR after 1000 steps", "size": size,
+            "steps": steps, "target_seed": seed, "lr": "Sec. 4.1 (control points 2e-4)",
+            "random_psnr_1000": e["random"]["psnr_final"],
+            "learned_psnr_initial": e["learned"]["psnr_initial"],
+            "learned_psnr_1000": e["learned"]["psnr_final"],
+            "learned_steps": e["learned"]["steps_to_random_final"],
+            "fraction_of_steps": e["learned"]["fraction_of_steps"],
+            "propose_ms": o["propose_ms"]}
 
 
 def bench_batched(a):
@@ -323,6 +351,8 @@ def main():
         "pairs": {"tile_pairs": need, "contributing": n_alg},
         "roofline": roof,
     }
+    if not a.no_learned_init and a.workload == "paper_2048":
+        out["learned_init"] = learned_init_figure()
     if not a.no_cpu_baseline:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, target.astype(np.float64), a.cpu_rows)

@@ -71,6 +71,11 @@ class FitConfig:
     check_every: int = 10       # pair-buffer overflow checks (each one synchronises)
 
 
+# Learning rates of Sec. 4.1 (control points 2e-4 in the normalised
+# coordinates, colours 1e-2, opacities 1e-1; the width's is not stated).
+PAPER_LR = dict(lr_ctrl=2e-4, lr_color=1e-2, lr_opacity=1e-1, lr_width=1e-2)
+
+
 @dataclass
 class FitResult:
     psnr: list = field(default_factory=list)        # (step, PSNR of that step's render)

@@ -292,6 +292,56 @@ def batched(seed: int = 0, n_canvas: int = 64, side=(128, 1024), curves=(256, 81
     return out
 
 
+def patch_origins(W: int, H: int, side: int = 32) -> np.ndarray:
+    """Top-left corners [n, 2] (px) of the side x side patches tiling a canvas, row-major."""
+    ys, xs = np.mgrid[0:H:side, 0:W:side]
+    return np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
+
+
+def open_curves(W: int, H: int, ctrl, widths, colors, opacities, K: int, name: str = "") -> Scene:
+    """Open single-segment curves from arrays: ctrl [n, 4, 2] px, widths [n],
+    colours [n, 3], opacities [n]; identity draw order."""
+    ctrl = np.asarray(ctrl, np.float64).reshape(-1, 4, 2)
+    n = ctrl.shape[0]
+    return _assemble(W, H, [OPEN] * n, [1] * n, [K] * n, [0] * n, list(ctrl),
+                     np.asarray(widths).reshape(n), np.asarray(colors).reshape(n, 3),
+                     list(np.asarray(opacities).reshape(n, 1)), np.arange(n), name=name)
+
+
+def grid_init(W: int, H: int, side: int = 32, per: int = 8, K: int = 16) -> Scene:
+    """Deterministic per-patch initialisation: the patch is cut into per cells
+    (4 columns x per/4 rows); slot j's curve is a straight horizontal stroke
+    across cell j (control points at 1/8, 3/8, 5/8, 7/8 of its width, at its
+    mid height), width 2 px, grey, opacity 0.5."""
+    org = patch_origins(W, H, side).astype(np.float64)
+    cols, rows = 4, per // 4
+    cw, ch = side / cols, side / rows
+    ctrl = []
+    for j in range(per):
+        cx0, cy = (j % cols) * cw, (j // cols) * ch + ch / 2
+        ctrl.append([[cx0 + cw * f, cy] for f in (0.125, 0.375, 0.625, 0.875)])
+    ctrl = np.asarray(ctrl)[None] + org[:, None, None, :]
+    n = ctrl.shape[0] * per
+    return open_curves(W, H, ctrl.reshape(n, 4, 2), np.full(n, 2.0), np.full((n, 3), 0.5),
+                       np.full(n, 0.5), K, name=f"grid-init-{W}x{H}")
+
+
+def random_init(seed: int, W: int, H: int, side: int = 32, per: int = 8, K: int = 16) -> Scene:
+    """Uniform random initialisation, per curves per patch (the same count and
+    density as the learned one): control points uniform over the curve's
+    patch, widths U[1,4], colours U[0,1]^3, opacities U[0.3,1].  Drawn in that
+    order for all curves at once."""
+    rng = np.random.default_rng(seed)
+    org = patch_origins(W, H, side).astype(np.float64)
+    n = org.shape[0] * per
+    ctrl = rng.uniform(0.0, side, (org.shape[0], per, 4, 2)) + org[:, None, None, :]
+    widths = rng.uniform(1.0, 4.0, n)
+    colors = rng.uniform(0.0, 1.0, (n, 3))
+    opas = rng.uniform(0.3, 1.0, n)
+    return open_curves(W, H, ctrl.reshape(n, 4, 2), widths, colors, opas, K,
+                       name=f"random-init-{W}x{H}")
+
+
 def small_mixed(seed: int, W: int = 48, H: int = 40, n_closed: int = 3, n_open: int = 4,
                 K: int = 8, R: int = 3, extent=(6.0, 30.0)) -> Scene:
     """Small mixed scenes for finite-difference and parity tests."""

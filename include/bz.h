@@ -289,6 +289,35 @@ bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_
 bz_status bz_render_bwd_curves(const bz_curves *c, const bz_opts *opts, const float *d_gauss,
                                bz_grads *grads, hipStream_t stream);
 
+/* Per-curve area (Sec. 3.3: depth follows curve area).  Closed curve: the
+ * area of the polygon of its boundary samples A_0..A_{K-1}, B_{K-2}..B_1 (the
+ * region between its two boundaries).  Open stroke: polyline length of its K
+ * samples times its width.  area: float [n_curves], by curve index. */
+bz_status bz_curve_area(const bz_curves *c, float *area, hipStream_t stream);
+
+/* Host: workspace bytes of bz_area_order for n_curves curves. */
+bz_status bz_area_order_workspace(int32_t n_curves, int64_t *bytes);
+
+/* Draw order by area (Sec. 3.3): curves sorted by bz_curve_area, smallest in
+ * front (position 0), equal areas by curve index.  Writes area [n_curves],
+ * order [n_curves] (the curve at each position) and gauss_off [n_curves + 1]
+ * (first Gaussian of every position), the fields bz_layout_host would fill
+ * for that rank; order and gauss_off may be c->order and c->gauss_off
+ * themselves (they are not read).  workspace: device, 256-byte aligned, of
+ * bz_area_order_workspace bytes.  Runs entirely on the device. */
+bz_status bz_area_order(const bz_curves *c, float *area, int32_t *order, int64_t *gauss_off,
+                        void *workspace, int64_t workspace_bytes, hipStream_t stream);
+
+/* Xing loss (Sec. 3.5, the convexity term the paper takes from LIVE) of the
+ * closed curves' boundary segments: per cubic segment P0..P3,
+ * D1 = [cross(P1-P0, P2-P1) >= 0], D2 = cross(P1-P0, P3-P2)/(|P1-P0||P3-P2|),
+ * cost D1 max(0, -D2) + (1 - D1) max(0, D2).  loss[0] (device, may be NULL) =
+ * weight * sum of costs (overwritten); weight * d(sum)/d(control points) is
+ * ADDED to d_ctrl ([n_ctrl][2], e.g. after bz_render_bwd).  Segments with a
+ * zero-length first or last control edge cost 0. */
+bz_status bz_xing_loss(const bz_curves *c, float weight, float *loss, float *d_ctrl,
+                       hipStream_t stream);
+
 /* Mean squared error loss of Sec. 3.5 (the L2 term): d_image = scale*(image - target)
  * elementwise over n floats, and loss[0] = sum (image - target)^2 accumulated
  * (loss is zeroed by the call; may be NULL). */

@@ -74,6 +74,7 @@ class Grads(C.Structure):
 EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_batch_layout",
            "bz_visit_words", "bz_sample", "bz_bin",
            "bz_render_fwd", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
+           "bz_curve_area", "bz_area_order_workspace", "bz_area_order", "bz_xing_loss",
            "bz_l2_grad", "bz_status_str")
 
 _lib = None
@@ -117,6 +118,15 @@ def load_library(path: str = LIB_PATH):
                                         C.c_void_p, C.c_void_p]
     lib.bz_render_bwd_curves.restype = C.c_int
     lib.bz_render_bwd_curves.argtypes = [P(Curves), P(Opts), C.c_void_p, P(Grads), C.c_void_p]
+    lib.bz_curve_area.restype = C.c_int
+    lib.bz_curve_area.argtypes = [P(Curves), C.c_void_p, C.c_void_p]
+    lib.bz_area_order_workspace.restype = C.c_int
+    lib.bz_area_order_workspace.argtypes = [C.c_int32, P(C.c_int64)]
+    lib.bz_area_order.restype = C.c_int
+    lib.bz_area_order.argtypes = [P(Curves), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int64, C.c_void_p]
+    lib.bz_xing_loss.restype = C.c_int
+    lib.bz_xing_loss.argtypes = [P(Curves), C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.bz_l2_grad.restype = C.c_int
     lib.bz_l2_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p,
                                C.c_void_p, C.c_void_p]
@@ -208,7 +218,8 @@ class Rasterizer:
     """
 
     def __init__(self, scene, opts: RenderOptions | None = None, device: str = "cuda",
-                 cap_pairs: int | None = None, blend_state: str = "stored"):
+                 cap_pairs: int | None = None, blend_state: str = "stored",
+                 draw_order: str = "rank"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libbz needs a GPU; none is visible")
@@ -218,6 +229,9 @@ class Rasterizer:
         self.ro = opts or RenderOptions()
         if blend_state not in ("stored", "recompute"):
             raise ValueError("blend_state is 'stored' or 'recompute'")
+        if draw_order not in ("rank", "area"):
+            raise ValueError("draw_order is 'rank' (the scene's) or 'area' (Sec. 3.3)")
+        self.draw_order = draw_order
         self.recompute = blend_state == "recompute"
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
         self.canvases = None
@@ -306,7 +320,16 @@ class Rasterizer:
                            _ptr(self.d_color).value, _ptr(self.d_opacity).value,
                            _ptr(self.d_gauss).value)
         self.loss = torch.zeros(1, dtype=f32, device=self.dev)
+        self.xing_value = torch.zeros(1, dtype=f32, device=self.dev)
         self._hw = HW
+        self.area = torch.zeros(max(scene.n_curves, 1), dtype=f32, device=self.dev)
+        if draw_order == "area":
+            wb = C.c_int64(0)
+            _check("bz_area_order_workspace",
+                   self.lib.bz_area_order_workspace(scene.n_curves, C.byref(wb)))
+            self.order_ws = torch.empty(int(wb.value) + 256, dtype=torch.uint8, device=self.dev)
+            self._order_ws_ptr = (self.order_ws.data_ptr() + 255) & ~255
+            self._order_ws_bytes = int(wb.value)
 
     # -- capacity ------------------------------------------------------------
     def _alloc_pairs(self, cap: int):
@@ -376,7 +399,30 @@ class Rasterizer:
     def _state_arg(self):
         return None if self.state is None else C.byref(self.state)
 
+    def curve_area(self):
+        """Per-curve areas (by curve index) into ``area``."""
+        _check("bz_curve_area", self.lib.bz_curve_area(C.byref(self.curves), _ptr(self.area),
+                                                       _stream()))
+        return self.area
+
+    def reorder(self):
+        """Draw order by area (smallest in front), on the device, into the
+        ``order`` / ``gauss_off`` the curve set points at."""
+        _check("bz_area_order", self.lib.bz_area_order(
+            C.byref(self.curves), _ptr(self.area), _ptr(self.order), _ptr(self.gauss_off),
+            C.c_void_p(self._order_ws_ptr), self._order_ws_bytes, _stream()))
+
+    def xing(self, weight: float):
+        """Xing loss of the closed curves into ``xing_value``; weight times its
+        gradient is added to ``d_ctrl``."""
+        _check("bz_xing_loss", self.lib.bz_xing_loss(C.byref(self.curves), C.c_float(weight),
+                                                     _ptr(self.xing_value), _ptr(self.d_ctrl),
+                                                     _stream()))
+        return self.xing_value
+
     def sample(self):
+        if self.draw_order == "area":
+            self.reorder()
         _check("bz_sample", self.lib.bz_sample(C.byref(self.curves), C.byref(self.opts),
                                                C.byref(self.gauss), _stream()))
 

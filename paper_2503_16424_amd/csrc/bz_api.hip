@@ -287,6 +287,40 @@ bz_status bz_render_bwd(const bz_curves *c, const bz_gaussians *g, const bz_bins
     return bz_render_bwd_curves(c, o, gr->d_gauss, gr, s);
 }
 
+bz_status bz_curve_area(const bz_curves *c, float *area, hipStream_t s) {
+    bz_status st = check_curves(c);
+    if (st != BZ_OK) return st;
+    if (c->n_curves > 0 && !area) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return launched(launch_area(*c, area, s));
+}
+
+bz_status bz_area_order_workspace(int32_t n, int64_t *bytes) {
+    if (n < 0 || !bytes) return BZ_ERR_ARG;
+    *bytes = order_workspace_bytes(n);
+    return BZ_OK;
+}
+
+bz_status bz_area_order(const bz_curves *c, float *area, int32_t *order, int64_t *gauss_off,
+                        void *ws, int64_t ws_bytes, hipStream_t s) {
+    bz_status st = check_curves(c);
+    if (st != BZ_OK) return st;
+    if (c->n_curves > 0 && (!area || !order || !gauss_off || !ws)) return BZ_ERR_ARG;
+    if (c->n_curves > 0 && ((uintptr_t)ws & 255)) return BZ_ERR_ARG;
+    if (ws_bytes < order_workspace_bytes(c->n_curves)) return BZ_ERR_CAPACITY;
+    (void)hipGetLastError();
+    return launched(launch_area_order(*c, area, order, gauss_off, ws, s));
+}
+
+bz_status bz_xing_loss(const bz_curves *c, float weight, float *loss, float *d_ctrl,
+                       hipStream_t s) {
+    bz_status st = check_curves(c);
+    if (st != BZ_OK) return st;
+    if (!isfinite(weight) || (c->n_curves > 0 && !d_ctrl)) return BZ_ERR_ARG;
+    (void)hipGetLastError();
+    return launched(launch_xing(*c, weight, loss, d_ctrl, s));
+}
+
 bz_status bz_l2_grad(const float *image, const float *target, int64_t n, float scale,
                      float *d_image, float *loss, hipStream_t s) {
     if (n < 0 || (n > 0 && (!image || !target || !d_image))) return BZ_ERR_ARG;

@@ -401,7 +401,54 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ key
     if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
 }
 
+__global__ void k_set_count(int64_t *status, int64_t n) {
+    if (threadIdx.x == 0) {
+        status[0] = n;
+        status[1] = 0;
+    }
+}
+
 }  // namespace
+
+int64_t sort_hist_blocks(int64_t n) { return cdiv(n > 0 ? n : 1, kTile); }
+int64_t sort_part_elems(int64_t n) {
+    const int64_t a = cdiv(n > 0 ? n : 1, kTile);
+    const int64_t b = cdiv(kRadix * sort_hist_blocks(n), kTile);
+    return a > b ? a : b;
+}
+
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part,
+                              int64_t *total_out, int64_t *status, hipStream_t s) {
+    // cap = 2^62: the overflow test of the pair count never fires here
+    return scan_u32(in, out, n, part, total_out, int64_t(1) << 62, status, s);
+}
+
+hipError_t sort_pairs_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
+                          int64_t n, int key_bits, uint32_t *hist, uint64_t *part, int64_t *status,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (key_bits < 16 || key_bits > 32 || key_bits % 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, s, status, n);
+    const int64_t hb = sort_hist_blocks(n);
+    const int passes = (key_bits + 7) / 8;
+    uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
+        hipLaunchKernelGGL(k_radix_hist, dim3(hb), dim3(kBlk), 0, s, kin, (const int64_t *)status,
+                           shift, nbits, hist, hb);
+        hipError_t e = scan_u32(hist, hist, kRadix * hb, part, nullptr, 0, status, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(hb), dim3(kBlk), 0, s, kin, vin, kout, vout,
+                           (const uint32_t *)hist, hb, (const int64_t *)status, shift, nbits);
+        uint32_t *tk = kin, *tv = vin;
+        kin = kout;
+        vin = vout;
+        kout = tk;
+        vout = tv;
+    }
+    return hipGetLastError();
+}
 
 BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
     BinLayout L;

@@ -42,6 +42,23 @@ __device__ inline CurveView load_curve_view(const bz_curves &c, int p) {
     return v;
 }
 
+// View of curve i by its index (draw position unknown: g0 = 0).
+__device__ inline CurveView load_curve_by_id(const bz_curves &c, int i) {
+    CurveView v;
+    v.id = i;
+    v.kind = c.kind[i];
+    v.S = c.nseg[i];
+    v.K = c.k_samples[i];
+    v.R = v.kind == BZ_CLOSED ? c.r_interior[i] : 0;
+    v.rows = v.kind == BZ_CLOSED ? v.R + 2 : 1;
+    v.nopa = c.opa_off[i + 1] - c.opa_off[i];
+    v.g0 = 0;
+    v.P = c.ctrl + 2 * (int64_t)c.ctrl_off[i];
+    v.tau = c.tau + c.tau_off[i];
+    v.width = c.stroke_w[i];
+    return v;
+}
+
 // Column k of a row: segment s = min(floor(kS/(K-1)), S-1) in integers and the
 // local parameter t in [0, 1] of that segment.
 __device__ inline void column_param(int k, int K, int S, int &s, double &t) {
@@ -96,6 +113,21 @@ __device__ inline void boundary_samples(const CurveView &v, double2 *XA, double2
         XA[k] = make_double2(ax, ay);
         if (v.kind == BZ_CLOSED) XB[k] = make_double2(bx, by);
     }
+}
+
+// Sample k of boundary A (or B) evaluated directly (no LDS).
+__device__ inline double2 boundary_point(const CurveView &v, bool boundary_b, int k) {
+    int s;
+    double t, B[4];
+    column_param(k, v.K, v.S, s, t);
+    bernstein3(t, B);
+    double x = 0.0, y = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        const double2 p = ctrl_point(v, boundary_b, 3 * s + j);
+        x += B[j] * p.x;
+        y += B[j] * p.y;
+    }
+    return make_double2(x, y);
 }
 
 // Sample point X_{r,k}.

@@ -58,6 +58,26 @@ hipError_t launch_bwd_curves(const bz_curves &c, const bz_opts &o, const float *
                              const bz_grads &gr, hipStream_t s);
 hipError_t launch_l2(const float *image, const float *target, int64_t n, float scale,
                      float *d_image, float *loss, hipStream_t s);
+hipError_t launch_area(const bz_curves &c, float *area, hipStream_t s);
+hipError_t launch_area_order(const bz_curves &c, float *area, int32_t *order, int64_t *gauss_off,
+                             void *ws, hipStream_t s);
+hipError_t launch_xing(const bz_curves &c, float weight, float *loss, float *d_ctrl,
+                       hipStream_t s);
+int64_t order_workspace_bytes(int64_t n_curves);
+
+// Sorting helpers of bz_bin.hip, reused by the draw-order pipeline.
+// sort_pairs_u32: stable LSD radix sort of n (key, value) pairs on the low
+// key_bits bits (16 or 32: an even number of 8-bit passes, so the result
+// ends in keys/vals);
+// hist: uint32 [256 * sort_hist_blocks(n)], part: uint64 [sort_part_elems(n)],
+// status: int64 [2] scratch.
+int64_t sort_hist_blocks(int64_t n);
+int64_t sort_part_elems(int64_t n);
+hipError_t sort_pairs_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
+                          int64_t n, int key_bits, uint32_t *hist, uint64_t *part, int64_t *status,
+                          hipStream_t s);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part,
+                              int64_t *total_out, int64_t *status, hipStream_t s);
 
 // Workspace layout of bz_bin (bytes); shared by bz_workspace_size and the launcher.
 struct BinLayout {

@@ -69,6 +69,7 @@ class FitConfig:
     min_width: float = 0.5      # px
     log_every: int = 50         # PSNR / timing samples
     check_every: int = 10       # pair-buffer overflow checks (each one synchronises)
+    xing_weight: float = 0.0    # weight of the Xing loss (Sec. 3.5) on closed curves
 
 
 # Learning rates of Sec. 4.1 (control points 2e-4 in the normalised
@@ -168,6 +169,8 @@ def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=No
             ev[1].record()
         rast.l2_grad(target)
         rast.backward()
+        if cfg.xing_weight > 0.0:
+            rast.xing(cfg.xing_weight)          # L = mean squared error + weight * Xing
         if logged:
             ev[2].record()
         f.update()

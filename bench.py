@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_2048", choices=["paper_2048", "open_512",
-                                                                 "tiny_128", "batched_64"])
+                                                                 "tiny_128", "batched_64",
+                                                                 "curvenet"])
+    ap.add_argument("--batch", type=int, default=256, help="curvenet: patches per step")
     ap.add_argument("--persistent", action="store_true",
                     help="persistent blend launches (tiles from a counter)")
     ap.add_argument("--autotune", action="store_true",
@@ -143,6 +145,81 @@ def learned_init_figure(size=1024, steps=1000, seed=77):
             "propose_ms": o["propose_ms"]}
 
 
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+
+
+def bench_curvenet(a):
+    """One training step of the curve-proposal network (forward, filter and
+    input gradients of every layer) on a batch of 32x32 patches, per kernel,
+    against the dense BF16 matrix-core peak."""
+    import numpy as np
+    import torch
+
+    from paper_2503_16424_amd import cnn
+    net = cnn.CurveNet(seed=0)
+    net.sync_weights()
+    rng = np.random.default_rng(0)
+    x = torch.as_tensor(rng.uniform(0, 1, (a.batch, 32, 32, 3)).astype(np.float32),
+                        device="cuda").to(torch.bfloat16).view(torch.int16)
+    dz = torch.as_tensor(rng.standard_normal((a.batch, cnn.OUT)).astype(np.float32),
+                         device="cuda")
+    for _ in range(a.warmup):
+        net.forward(x)
+        net.backward(dz)
+    torch.cuda.synchronize()
+    ds = net._shapes(a.batch)
+    rows = []
+    for i, d in enumerate(ds):
+        M = d.n * d.ho * d.wo
+        flops = 2.0 * M * d.k * d.r * d.r * d.c
+        acts = net._acts
+        y = torch.empty((d.n, d.ho, d.wo, d.k), dtype=torch.int16, device="cuda")
+        dy = torch.randn((d.n, d.ho, d.wo, d.k), device="cuda")
+        dw = torch.empty(net.params[i][0].shape, device="cuda")
+        dx = torch.empty(acts[i].shape, device="cuda")
+        w = net._bf[i]
+        calls = {"fwd": lambda: cnn.conv_fwd(d, acts[i], w, net.params[i][1], True, y_bf16=y),
+                 "bwd_weight": lambda: cnn.conv_bwd_weight(d, dy, acts[i], dw),
+                 "bwd_data": lambda: cnn.conv_bwd_data(d, dy, w, dx, x_mask=acts[i])}
+        for name, fn in calls.items():
+            if name == "bwd_data" and i == 0:
+                continue
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fn()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(a.steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / a.steps
+            rows.append({"layer": i, "pass": name, "gemm_mnk": [M, d.k, d.r * d.r * d.c]
+                         if name == "fwd" else None, "ms": ms, "tflops": flops / ms / 1e9})
+    t0 = time.perf_counter()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        net.forward(x)
+        net.backward(dz)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / a.steps
+    dom = max(rows, key=lambda r: r["ms"])
+    out = {"metric": "curve-proposal network training steps/s (forward + backward)",
+           "value": 1000.0 / step_ms, "unit": "steps/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": step_ms, "higher_is_better": True,
+           "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+           "config": {"workload": "curvenet-32x32-patches", "batch": a.batch},
+           "roofline": {"kernel": f"k_igemm layer {dom['layer']} {dom['pass']}", "bound": "mfma",
+                        "achieved": dom["tflops"], "peak": PEAK_BF16_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": dom["tflops"] / PEAK_BF16_MFMA_TFLOPS,
+                        "traffic": None},
+           "kernels": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_batched(a):
     """64 canvases of uneven size (sides log-uniform 128..1024 px, 256..8192
     open curves, K 16..32): the batched step (one tile space, every stage one
@@ -231,6 +308,8 @@ def main():
         return 2
     if a.workload == "batched_64":
         return bench_batched(a)
+    if a.workload == "curvenet":
+        return bench_curvenet(a)
     import numpy as np
     import torch
 

@@ -143,7 +143,96 @@ __device__ inline void gather_b(const GemmArgs &g, int64_t n, int64_t k0, int64_
     }
 }
 
-template <int MODE>
+// 8 bf16 from a 16-byte aligned address, or zeros.
+__device__ inline void load8_bf16(const uint16_t *p, bool ok, uint16_t (&v)[8]) {
+    uint4 q = make_uint4(0, 0, 0, 0);
+    if (ok) q = *reinterpret_cast<const uint4 *>(p);
+    v[0] = (uint16_t)q.x; v[1] = (uint16_t)(q.x >> 16);
+    v[2] = (uint16_t)q.y; v[3] = (uint16_t)(q.y >> 16);
+    v[4] = (uint16_t)q.z; v[5] = (uint16_t)(q.z >> 16);
+    v[6] = (uint16_t)q.w; v[7] = (uint16_t)(q.w >> 16);
+}
+
+// 8 floats from a 32-byte aligned address rounded to bf16, or zeros.
+__device__ inline void load8_f32(const float *p, bool ok, uint16_t (&v)[8]) {
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+    if (ok) {
+        a = reinterpret_cast<const float4 *>(p)[0];
+        b = reinterpret_cast<const float4 *>(p)[1];
+    }
+    v[0] = f_to_bf(a.x); v[1] = f_to_bf(a.y); v[2] = f_to_bf(a.z); v[3] = f_to_bf(a.w);
+    v[4] = f_to_bf(b.x); v[5] = f_to_bf(b.y); v[6] = f_to_bf(b.z); v[7] = f_to_bf(b.w);
+}
+
+// Operand slices of one k step into LDS (k contiguous in sA[m][.], sB[n][.]).
+// VA / VB: the operand's contiguous dimension holds whole groups of 8, so a
+// thread moves 8 neighbours with one vector load: along k for operands stored
+// k-contiguous (forward input and filters, input-gradient output gradients),
+// along m or n otherwise (written transposed).  Else the element gather.
+template <int MODE, bool VA, bool VB>
+__device__ inline void load_tiles(const GemmArgs &g, int64_t m0, int64_t n0, int64_t k0,
+                                  int64_t kend, uint16_t (*sA)[kLdsK], uint16_t (*sB)[kLdsK]) {
+    const Shape &S = g.S;
+    const int t = threadIdx.x;
+    const int lrow = t >> 2, lk = (t & 3) * 8;          // k-major slot: row, 8 k
+    const int tk = t >> 3, tc = (t & 7) * 8;            // mn-major slot: k, 8 rows
+    const int64_t kf = (int64_t)S.r * S.r * S.c;
+    uint16_t v[8];
+    // ---- A ----
+    if (MODE == kFwd && VA) {
+        const int64_t m = m0 + lrow, k = k0 + lk;
+        const int tap = (int)(k / S.c), ci = (int)(k - (int64_t)tap * S.c);
+        const int64_t px = (m < g.M && k < kend) ? in_pixel(S, m, tap) : -1;
+        load8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+    } else if (MODE == kBwdData && VA) {
+        const int64_t m = m0 + lrow, k = k0 + lk;
+        const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
+        const int64_t px = (m < g.M && k < kend) ? out_pixel(S, m, tap) : -1;
+        load8_f32(g.dy + (px >= 0 ? px * S.k + co : 0), px >= 0, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+    } else if (MODE == kBwdWeight && VA) {              // A[co][pixel] = dy[pixel][co]
+        const int64_t k = k0 + tk, m = m0 + tc;
+        const bool ok = k < kend && m < g.M;
+        load8_f32(g.dy + (ok ? k * S.k + m : 0), ok, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[tc + j][tk] = v[j];
+    } else {
+        gather_a<MODE>(g, m0 + lrow, k0 + lk, kend, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+    }
+    // ---- B ----
+    if (MODE == kFwd && VB) {
+        const int64_t n = n0 + lrow, k = k0 + lk;
+        const bool ok = n < g.N && k < kend;
+        load8_bf16(g.w + (ok ? n * kf + k : 0), ok, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
+    } else if (MODE == kBwdData && VB) {                // B[(tap, co)][ci] = w[co][tap][ci]
+        const int64_t k = k0 + tk, n = n0 + tc;
+        const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
+        const bool ok = k < kend && n < g.N;
+        load8_bf16(g.w + (ok ? (int64_t)co * kf + (int64_t)tap * S.c + n : 0), ok, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sB[tc + j][tk] = v[j];
+    } else if (MODE == kBwdWeight && VB) {              // B[pixel][(tap, ci)] = x[shifted pixel][ci]
+        const int64_t k = k0 + tk, n = n0 + tc;
+        const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
+        const int64_t px = (k < kend && n < g.N) ? in_pixel(S, k, tap) : -1;
+        load8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sB[tc + j][tk] = v[j];
+    } else {
+        gather_b<MODE>(g, n0 + lrow, k0 + lk, kend, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
+    }
+}
+
+template <int MODE, bool VA, bool VB>
 __global__ __launch_bounds__(256) void k_igemm(GemmArgs g) {
     __shared__ __align__(16) uint16_t sA[kBM][kLdsK];
     __shared__ __align__(16) uint16_t sB[kBN][kLdsK];
@@ -160,17 +249,9 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int lrow = t >> 2, lk = (t & 3) * 8;        // this thread's gather slot
     for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
-        uint16_t va[8], vb[8];
-        gather_a<MODE>(g, m0 + lrow, k0 + lk, kend, va);
-        gather_b<MODE>(g, n0 + lrow, k0 + lk, kend, vb);
         __syncthreads();                              // previous step's reads are done
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            sA[lrow][lk + j] = va[j];
-            sB[lrow][lk + j] = vb[j];
-        }
+        load_tiles<MODE, VA, VB>(g, m0, n0, k0, kend, sA, sB);
         __syncthreads();
         const int r16 = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
@@ -211,6 +292,19 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs g) {
                     atomicAdd(&g.out_f[m * g.N + n], v);
                 }
             }
+}
+
+// Dispatch on which operands can move 8 at a time.
+template <int MODE>
+void launch_igemm(const GemmArgs &g, bool va, bool vb, dim3 grid, hipStream_t s) {
+    if (va && vb)
+        hipLaunchKernelGGL((k_igemm<MODE, true, true>), grid, dim3(256), 0, s, g);
+    else if (va)
+        hipLaunchKernelGGL((k_igemm<MODE, true, false>), grid, dim3(256), 0, s, g);
+    else if (vb)
+        hipLaunchKernelGGL((k_igemm<MODE, false, true>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_igemm<MODE, false, false>), grid, dim3(256), 0, s, g);
 }
 
 __global__ void k_fill0(float *p, int64_t n) {
@@ -281,7 +375,8 @@ hipError_t launch_conv_fwd(const bz_conv &c, const uint16_t *x, const uint16_t *
     g.out_f = y;
     g.out_b = yb;
     dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), 1);
-    hipLaunchKernelGGL(k_igemm<kFwd>, grid, dim3(256), 0, s, g);
+    // A: 8 input channels per load (c % 8); B: 8 filter taps-channels per load (K % 8)
+    launch_igemm<kFwd>(g, c.c % 8 == 0, g.K % 8 == 0 && c.c % 8 == 0, grid, s);
     return hipGetLastError();
 }
 
@@ -297,7 +392,8 @@ hipError_t launch_conv_bwd_data(const bz_conv &c, const float *dy, const uint16_
     g.mask = mask;
     g.out_f = dx;
     dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), 1);
-    hipLaunchKernelGGL(k_igemm<kBwdData>, grid, dim3(256), 0, s, g);
+    // A: 8 output channels of dy (k % 8); B: 8 input channels of a filter row (c % 8)
+    launch_igemm<kBwdData>(g, c.k % 8 == 0, c.c % 8 == 0, grid, s);
     return hipGetLastError();
 }
 
@@ -316,7 +412,8 @@ hipError_t launch_conv_bwd_weight(const bz_conv &c, const float *dy, const uint1
     hipLaunchKernelGGL(k_fill0, dim3((unsigned)cdiv(nz, 256) < 4096 ? (unsigned)cdiv(nz, 256) : 4096),
                        dim3(256), 0, s, dw, nz);
     dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), (unsigned)cdiv(g.K, g.k_chunk));
-    hipLaunchKernelGGL(k_igemm<kBwdWeight>, grid, dim3(256), 0, s, g);
+    // A: 8 output channels of dy (k % 8); B: 8 input channels of a shifted pixel (c % 8)
+    launch_igemm<kBwdWeight>(g, c.k % 8 == 0, c.c % 8 == 0, grid, s);
     if (db) hipLaunchKernelGGL(k_bias_grad, dim3(c.k), dim3(256), 0, s, dy, g.K, c.k, db);
     return hipGetLastError();
 }

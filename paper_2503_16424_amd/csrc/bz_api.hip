@@ -13,7 +13,7 @@ namespace {
 // Per-curve limits of the per-curve kernels (LDS sizes).
 constexpr int kMaxK = 1024;
 constexpr int kMaxR = 254;
-constexpr int64_t kMaxLdsBytes = 64 * 1024;
+constexpr int64_t kMaxLdsBytes = 152 * 1024;   // dynamic LDS of the per-curve kernels (160 KB per CU on gfx950, static use ~2 KB)
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
 

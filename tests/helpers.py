@@ -78,3 +78,23 @@ def rel_l2(a, b):
     b = np.asarray(b, np.float64).ravel()
     den = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def max_size_scene(W=96, H=80):
+    """Curves at the per-curve limits: a 4-segment stroke of K = 1024 samples,
+    a 4-segment closed curve of R = 254 interior rows (K = 8), and a closed
+    curve of K = 60, R = 30 (together at the per-curve kernels' LDS budget:
+    the widest curve and the curve with most Gaussians share it)."""
+    import numpy as np
+    from paper_2503_16424_amd import scenes
+    rng = np.random.default_rng(99)
+    stroke = rng.uniform([5, 5], [W - 5, H - 5], (13, 2))
+    def lens(S, c, L, h):
+        A = [c + np.array([(-0.5 + j / (3 * S)) * L, 0.0]) for j in range(3 * S + 1)]
+        B = [c + np.array([(-0.5 + j / (3 * S)) * L, h]) for j in range(1, 3 * S)]
+        A = [a + np.array([0.0, -0.5 * h * np.sin(np.pi * j / (3 * S))]) for j, a in enumerate(A)]
+        return np.array(A + B)
+    ctrl = [stroke, lens(4, np.array([40.0, 40.0]), 60.0, 20.0), lens(1, np.array([60.0, 30.0]), 30.0, 12.0)]
+    return scenes._assemble(W, H, [0, 1, 1], [4, 4, 1], [1024, 8, 60], [0, 254, 30], ctrl,
+                            [2.0, 0.0, 0.0], rng.uniform(0, 1, (3, 3)),
+                            [[0.6, 0.9, 0.4, 0.8], [0.7], [0.5]], [2, 0, 1])

@@ -84,6 +84,23 @@ def test_layout_flags_unsupported_sizes():
     assert e.value.code == bz.BZ_ERR_UNSUPPORTED
 
 
+def test_layout_accepts_the_largest_curves_and_rejects_beyond():
+    # the largest K for a stroke and the largest R for a short closed curve fit the
+    # per-curve kernels' LDS together; R = 254 rows at K = 64 does not
+    ok = _max_size_scene()
+    bz.layout_host(ok)
+    big = _max_size_scene()
+    big.k_samples[1] = 64
+    with pytest.raises(bz.BzError) as e:
+        bz.layout_host(big)
+    assert e.value.code == bz.BZ_ERR_UNSUPPORTED
+
+
+def _max_size_scene():
+    from tests.helpers import max_size_scene
+    return max_size_scene()
+
+
 def _opts(**kw):
     ro = bz.RenderOptions(**{k: v for k, v in kw.items() if k in bz.RenderOptions.__dataclass_fields__})
     return bz.make_opts(kw.get("W", 128), kw.get("H", 96), (1, 1, 1), ro)

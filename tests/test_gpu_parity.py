@@ -348,3 +348,33 @@ def test_split_backward_stages_match_combined_call(torch_cuda):
     for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
         assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= 1e-5, k
     assert rel_l2(dg[: 9 * sc.n_gauss].cpu().numpy(), o["d_gauss"].T.reshape(-1)) <= GRAD_TOL
+
+
+def test_largest_curves_and_empty_scene(torch_cuda):
+    """Per-curve limits (a 4-segment stroke of K = 1024, a closed curve of
+    R = 254 rows, together at the per-curve LDS budget) and a scene with no
+    curves at all."""
+    import torch
+    from tests.helpers import max_size_scene
+    sc = max_size_scene()
+    _note(f"largest curves: n_gauss={sc.n_gauss}")
+    o0 = oracle.forward_backward(sc)
+    dimg = _upstream(sc, o0["image"])
+    o = oracle.forward_backward(sc, dimg.astype(np.float64))
+    r = _rast(sc)
+    r.sample()
+    g = r.gaussians_host()
+    assert np.abs(g["mu"] - o0["gauss"]["mu"]).max() < 1e-6
+    img = r.render().cpu().numpy()
+    assert np.abs(img - o0["image"]).max() <= IMG_TOL
+    r.backward(torch.as_tensor(dimg, device="cuda"))
+    torch.cuda.synchronize()
+    for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
+        assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= GRAD_TOL, k
+    empty = scenes.uniform_open(3, 40, 24, 0, 8)
+    empty.bg = np.array([0.1, 0.2, 0.3], np.float32)
+    r = _rast(empty)
+    img = r.render().cpu().numpy()
+    assert np.all(img == empty.bg[:, None, None]) and r.pairs_required() == 0
+    r.backward(torch.zeros((3, 24, 40), device="cuda"))
+    torch.cuda.synchronize()

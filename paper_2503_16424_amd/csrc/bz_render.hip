@@ -320,19 +320,37 @@ __device__ inline float dpp_f(float v) {
                                                                  CTRL, 0xF, 0xF, false));
 }
 
-// Exchange lanes 32..63 of x with lanes 0..31 of y (v_permlane32_swap), and
-// the odd 16-lane rows of x with the even rows of y (v_permlane16_swap).  Both
-// registers are outputs of the instruction; the compiler builtins of this
-// toolchain return the first one twice, so the instruction is written here
-// with both operands read-write.  s_nop 1 gives the two wait states a swap
-// needs after a VALU write of its operands.
-__device__ inline void swap32(float &x, float &y) {
-    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(x), "+v"(y));
-}
+// Exchange lanes 32..63 of x[i] with lanes 0..31 of y[i] (v_permlane32_swap),
+// or the odd 16-lane rows of x[i] with the even rows of y[i]
+// (v_permlane16_swap), for 8 register pairs.  Both registers of a pair are
+// outputs of the instruction; the compiler builtins of this toolchain return
+// the first one twice, so the instructions are written here with both
+// operands read-write.  One s_nop 1 gives the two wait states a swap needs
+// after a VALU write of its operands; the 8 swaps of a group do not depend on
+// each other.
+#define BZ_SWAP8(OP, x, y, o)                                                           \
+    asm volatile("s_nop 1\n\t" OP " %0, %8\n\t" OP " %1, %9\n\t" OP " %2, %10\n\t" OP    \
+                 " %3, %11\n\t" OP " %4, %12\n\t" OP " %5, %13\n\t" OP " %6, %14\n\t" OP \
+                 " %7, %15"                                                             \
+                 : "+v"(x[o + 0]), "+v"(x[o + 1]), "+v"(x[o + 2]), "+v"(x[o + 3]),       \
+                   "+v"(x[o + 4]), "+v"(x[o + 5]), "+v"(x[o + 6]), "+v"(x[o + 7]),       \
+                   "+v"(y[o + 0]), "+v"(y[o + 1]), "+v"(y[o + 2]), "+v"(y[o + 3]),       \
+                   "+v"(y[o + 4]), "+v"(y[o + 5]), "+v"(y[o + 6]), "+v"(y[o + 7]))
 
-__device__ inline void swap16(float &x, float &y) {
-    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(x), "+v"(y));
-}
+// d[i] on the lanes of the banks in MASK (4-lane groups of a 16-lane row) =
+// s[i] + s[i] read from the DPP partner lane (row_ror:8: lane ^ 8;
+// row_half_mirror: lane ^ 7 inside 8 lanes), for 4 registers; lanes of the
+// other banks keep d (OUT "+v") or are left undefined (OUT "=&v", early
+// clobber: the block reads its inputs after writing outputs).  The wait
+// states before the first DPP read of a freshly written register come first.
+#define BZ_DPPADD4(OUT, CTRL, MASK, d, s, od, os)                                        \
+    asm volatile("s_nop 1\n\t"                                                          \
+                 "v_add_f32_dpp %0, %4, %4 " CTRL " row_mask:0xf bank_mask:" MASK "\n\t"  \
+                 "v_add_f32_dpp %1, %5, %5 " CTRL " row_mask:0xf bank_mask:" MASK "\n\t"  \
+                 "v_add_f32_dpp %2, %6, %6 " CTRL " row_mask:0xf bank_mask:" MASK "\n\t"  \
+                 "v_add_f32_dpp %3, %7, %7 " CTRL " row_mask:0xf bank_mask:" MASK          \
+                 : OUT(d[od + 0]), OUT(d[od + 1]), OUT(d[od + 2]), OUT(d[od + 3])        \
+                 : "v"(s[os + 0]), "v"(s[os + 1]), "v"(s[os + 2]), "v"(s[os + 3]))
 
 // Transposed reduction of 64 per-lane values: on return lane l holds the sum
 // over all 64 lanes of v[l].  Each level halves the values a lane holds by
@@ -340,41 +358,38 @@ __device__ inline void swap16(float &x, float &y) {
 // swap), l^16 (permlane16 swap), l^8 (DPP row rotate by 8), l^7 (DPP half-row
 // mirror), l^3 and l^1 (DPP quad permutes).  Bit b of the lane index decides
 // which half a lane keeps, so after the six levels lane l holds index l.
-// 141 VALU instructions for 64 sums (a butterfly per value would need 384).
+// Lanes l and l^8 differ in bit 1 of their bank, lanes l and l^7 in bit 0, so
+// those two levels are pairs of bank-masked DPP adds (lanes of a bank add
+// the index they keep).  Works in place: v holds partial sums afterwards.
 __device__ inline float reduce_scatter64(float (&v)[64], int lane) {
+    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 0);
+    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 8);
+    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 16);
+    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 24);
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        float x = v[i], y = v[i + 32];
-        swap32(x, y);
-        v[i] = x + y;
-    }
+    for (int i = 0; i < 32; ++i) v[i] += v[i + 32];
+    BZ_SWAP8("v_permlane16_swap_b32", v, (v + 16), 0);
+    BZ_SWAP8("v_permlane16_swap_b32", v, (v + 16), 8);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        float x = v[i], y = v[i + 16];
-        swap16(x, y);
-        v[i] = x + y;
-    }
-    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
-        v[i] = keep + dpp_f<0x128>(send);          // row_ror:8  (lane ^ 8)
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
-        v[i] = keep + dpp_f<0x141>(send);          // row_half_mirror (lane ^ 7)
-    }
+    for (int i = 0; i < 16; ++i) v[i] += v[i + 16];
+    // lane ^ 8: banks 0, 1 keep index i, banks 2, 3 keep i + 8 (written into v[i])
+    float w[8];
+    BZ_DPPADD4("=&v", "row_ror:8", "0x3", w, v, 0, 0);
+    BZ_DPPADD4("=&v", "row_ror:8", "0x3", w, v, 4, 4);
+    BZ_DPPADD4("+v", "row_ror:8", "0xc", w, v, 0, 8);
+    BZ_DPPADD4("+v", "row_ror:8", "0xc", w, v, 4, 12);
+    // lane ^ 7: banks 0, 2 keep index i, banks 1, 3 keep i + 4
+    float u[4];
+    BZ_DPPADD4("=&v", "row_half_mirror", "0x5", u, w, 0, 0);
+    BZ_DPPADD4("+v", "row_half_mirror", "0xa", u, w, 0, 4);
+    const bool b1 = lane & 2, b0 = lane & 1;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
-        v[i] = keep + dpp_f<0x1B>(send);           // quad_perm [3,2,1,0] (lane ^ 3)
+        float keep = b1 ? u[i + 2] : u[i], send = b1 ? u[i] : u[i + 2];
+        u[i] = keep + dpp_f<0x1B>(send);           // quad_perm [3,2,1,0] (lane ^ 3)
     }
-    {
-        float keep = b0 ? v[1] : v[0], send = b0 ? v[0] : v[1];
-        v[0] = keep + dpp_f<0xB1>(send);           // quad_perm [1,0,3,2] (lane ^ 1)
-    }
-    return v[0];
+    float keep = b0 ? u[1] : u[0], send = b0 ? u[0] : u[1];
+    return keep + dpp_f<0xB1>(send);               // quad_perm [1,0,3,2] (lane ^ 1)
 }
 
 constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums

@@ -40,7 +40,9 @@ __device__ inline bool box_hit(float x0, float x1, float y0, float y1, float qa,
                                float qc, float thr) {
     if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
     float best = 3.0e38f;
-    float ia = 1.0f / qa, ic = 1.0f / qc;
+    // hardware reciprocals: an error in the clamped edge point moves the value
+    // of the quadratic form only to second order (the slack on thr covers it)
+    float ia = __builtin_amdgcn_rcpf(qa), ic = __builtin_amdgcn_rcpf(qc);
     // vertical edges: dx fixed, minimise over dy
 #pragma unroll
     for (int e = 0; e < 2; ++e) {

@@ -91,3 +91,16 @@ def test_xing_closed_form_and_invariances():
     # boundary A turns left, then its last edge heads down-right: 1/sqrt(2)
     s_bend = [[10, 10], [40, 10], [40, 40], [70, 10], [30, 30], [50, 30]]
     assert abs(so.xing_loss(_closed([s_bend]), weight=2.0) - 2.0 / math.sqrt(2.0)) < 1e-12
+
+
+def test_many_equal_areas_keep_index_order():
+    lens = [[10, 10], [20, 10], [30, 10], [40, 10], [20, 20], [30, 20]]
+    sc = _closed([lens] * 50, K=6, R=2)
+    a, order, _ = so.area_order(sc)
+    assert np.all(a == a[0]) and list(order) == list(range(50))
+
+
+def test_xing_cost_on_boundary_b():
+    # A is convex; B turns left then heads down-right: 1/sqrt(2) from B alone
+    ctrl = [[10, 10], [30, 0], [60, 0], [70, 10], [40, 10], [40, 40]]
+    assert abs(so.xing_loss(_closed([ctrl])) - 1.0 / math.sqrt(2.0)) < 1e-12

@@ -58,13 +58,15 @@ typedef enum {
  *   pix_off   : first pixel: the canvas's image is image + 3*pix_off, planar
  *               [3][height][width]; per-pixel state starts at pix_off
  *   gauss_off : first Gaussian; the canvas's curves are consecutive in draw
- *               order, so its Gaussians are [gauss_off, next gauss_off). */
+ *               order, so its Gaussians are [gauss_off, next gauss_off).
+ *   curve_off : first curve (by index) of the canvas; its curves are
+ *               consecutive by index too. */
 typedef struct {
     int32_t width, height;
     int32_t tiles_x, tiles_y;
     int64_t tile_off, pix_off, gauss_off;
     float bg[3];
-    int32_t reserved;
+    int32_t curve_off;
 } bz_canvas;
 
 /* A batch of canvases.  canvas: device array of n_canvas + 1 records, the last
@@ -224,14 +226,16 @@ bz_status bz_num_tiles(const bz_opts *opts, int64_t *n_tiles);
 /* Host: lay out a batch of n_canvas canvases for the tile shape of opts.
  * size: [n_canvas][2] width, height (1..32768); bg: [n_canvas][3] or NULL (all
  * opts->bg); gauss_off: [n_canvas + 1] first Gaussian of every canvas and the
- * total, non-decreasing from 0.  Writes canvas[0 .. n_canvas] (n_canvas + 1
+ * total, non-decreasing from 0; curve_off: [n_canvas + 1] first curve (by
+ * index) of every canvas and the total, non-decreasing from 0.  Writes
+ * canvas[0 .. n_canvas] (n_canvas + 1
  * records, all HOST memory) and batch->n_canvas, n_tiles, n_pixels, n_gauss
  * (batch->canvas is left for the caller to point at a device copy of the
  * records).
  * Tiles and pixels are numbered canvas by canvas. */
 bz_status bz_batch_layout(const bz_opts *opts, int32_t n_canvas, const int32_t *size,
-                          const float *bg, const int64_t *gauss_off, bz_canvas *canvas,
-                          bz_batch *batch);
+                          const float *bg, const int64_t *gauss_off, const int32_t *curve_off,
+                          bz_canvas *canvas, bz_batch *batch);
 
 /* Host: 64-bit words of bz_pixstate.visit for tile lists of cap_pairs entries. */
 bz_status bz_visit_words(const bz_opts *opts, int64_t cap_pairs, int64_t *words);
@@ -299,14 +303,17 @@ bz_status bz_curve_area(const bz_curves *c, float *area, hipStream_t stream);
 bz_status bz_area_order_workspace(int32_t n_curves, int64_t *bytes);
 
 /* Draw order by area (Sec. 3.3): curves sorted by bz_curve_area, smallest in
- * front (position 0), equal areas by curve index.  Writes area [n_curves],
+ * front (position 0), equal areas by curve index.  With a batch (opts->batch;
+ * opts may be NULL otherwise) the order is per canvas: canvas by canvas, by
+ * area inside each, so every canvas keeps its range of draw positions.  Writes area [n_curves],
  * order [n_curves] (the curve at each position) and gauss_off [n_curves + 1]
  * (first Gaussian of every position), the fields bz_layout_host would fill
  * for that rank; order and gauss_off may be c->order and c->gauss_off
  * themselves (they are not read).  workspace: device, 256-byte aligned, of
  * bz_area_order_workspace bytes.  Runs entirely on the device. */
-bz_status bz_area_order(const bz_curves *c, float *area, int32_t *order, int64_t *gauss_off,
-                        void *workspace, int64_t workspace_bytes, hipStream_t stream);
+bz_status bz_area_order(const bz_curves *c, const bz_opts *opts, float *area, int32_t *order,
+                        int64_t *gauss_off, void *workspace, int64_t workspace_bytes,
+                        hipStream_t stream);
 
 /* Xing loss (Sec. 3.5, the convexity term the paper takes from LIVE) of the
  * closed curves' boundary segments: per cubic segment P0..P3,

@@ -25,7 +25,7 @@ STATUS_NONFINITE = 2
 class Canvas(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tiles_x", C.c_int32),
                 ("tiles_y", C.c_int32), ("tile_off", C.c_int64), ("pix_off", C.c_int64),
-                ("gauss_off", C.c_int64), ("bg", C.c_float * 3), ("reserved", C.c_int32)]
+                ("gauss_off", C.c_int64), ("bg", C.c_float * 3), ("curve_off", C.c_int32)]
 
 
 class Batch(C.Structure):
@@ -100,7 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.bz_num_tiles.argtypes = [P(Opts), P(C.c_int64)]
     lib.bz_batch_layout.restype = C.c_int
     lib.bz_batch_layout.argtypes = [P(Opts), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, P(Batch)]
+                                    C.c_void_p, C.c_void_p, P(Batch)]
     lib.bz_visit_words.restype = C.c_int
     lib.bz_visit_words.argtypes = [P(Opts), C.c_int64, P(C.c_int64)]
     lib.bz_sample.restype = C.c_int
@@ -123,8 +123,8 @@ def load_library(path: str = LIB_PATH):
     lib.bz_area_order_workspace.restype = C.c_int
     lib.bz_area_order_workspace.argtypes = [C.c_int32, P(C.c_int64)]
     lib.bz_area_order.restype = C.c_int
-    lib.bz_area_order.argtypes = [P(Curves), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                  C.c_int64, C.c_void_p]
+    lib.bz_area_order.argtypes = [P(Curves), P(Opts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int64, C.c_void_p]
     lib.bz_xing_loss.restype = C.c_int
     lib.bz_xing_loss.argtypes = [P(Curves), C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.bz_l2_grad.restype = C.c_int
@@ -248,6 +248,7 @@ class Rasterizer:
         if self.canvases is not None:
             n = len(self.canvases)
             curve_off = np.concatenate([[0], np.cumsum([c.n_curves for c in self.canvases])])
+            coff32 = np.ascontiguousarray(curve_off, np.int32)
             size = np.array([[c.width, c.height] for c in self.canvases], np.int32)
             bg = np.array([np.asarray(c.bg, np.float32) for c in self.canvases], np.float32)
             cgoff = np.ascontiguousarray(goff[curve_off], np.int64)
@@ -255,7 +256,7 @@ class Rasterizer:
             self.batch = Batch()
             p = lambda x: x.ctypes.data_as(C.c_void_p)
             _check("bz_batch_layout", self.lib.bz_batch_layout(
-                C.byref(self.opts), n, p(size), p(bg), p(cgoff), C.addressof(recs),
+                C.byref(self.opts), n, p(size), p(bg), p(cgoff), p(coff32), C.addressof(recs),
                 C.byref(self.batch)))
             raw = np.frombuffer(bytes(recs), np.uint8).copy()
             self.canvas_table = t(raw, torch.uint8)
@@ -409,8 +410,9 @@ class Rasterizer:
         """Draw order by area (smallest in front), on the device, into the
         ``order`` / ``gauss_off`` the curve set points at."""
         _check("bz_area_order", self.lib.bz_area_order(
-            C.byref(self.curves), _ptr(self.area), _ptr(self.order), _ptr(self.gauss_off),
-            C.c_void_p(self._order_ws_ptr), self._order_ws_bytes, _stream()))
+            C.byref(self.curves), C.byref(self.opts), _ptr(self.area), _ptr(self.order),
+            _ptr(self.gauss_off), C.c_void_p(self._order_ws_ptr), self._order_ws_bytes,
+            _stream()))
 
     def xing(self, weight: float):
         """Xing loss of the closed curves into ``xing_value``; weight times its

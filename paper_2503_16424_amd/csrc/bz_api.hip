@@ -146,15 +146,16 @@ bz_status bz_num_tiles(const bz_opts *o, int64_t *n_tiles) {
 }
 
 bz_status bz_batch_layout(const bz_opts *o, int32_t n, const int32_t *size, const float *bg,
-                          const int64_t *gauss_off, bz_canvas *canvas, bz_batch *batch) {
-    if (!o || n < 1 || !size || !gauss_off || !canvas || !batch) return BZ_ERR_ARG;
+                          const int64_t *gauss_off, const int32_t *curve_off, bz_canvas *canvas,
+                          bz_batch *batch) {
+    if (!o || n < 1 || !size || !gauss_off || !curve_off || !canvas || !batch) return BZ_ERR_ARG;
     if (o->tile_w < 8 || o->tile_h < 8 || o->tile_w % 8 || o->tile_h % 8) return BZ_ERR_ARG;
-    if (gauss_off[0] != 0) return BZ_ERR_ARG;
+    if (gauss_off[0] != 0 || curve_off[0] != 0) return BZ_ERR_ARG;
     int64_t tile = 0, pix = 0;
     for (int32_t c = 0; c < n; ++c) {
         const int32_t W = size[2 * c], H = size[2 * c + 1];
         if (W < 1 || H < 1 || W > 32768 || H > 32768) return BZ_ERR_ARG;
-        if (gauss_off[c + 1] < gauss_off[c]) return BZ_ERR_ARG;
+        if (gauss_off[c + 1] < gauss_off[c] || curve_off[c + 1] < curve_off[c]) return BZ_ERR_ARG;
         bz_canvas &r = canvas[c];
         memset(&r, 0, sizeof(r));
         r.width = W;
@@ -164,6 +165,7 @@ bz_status bz_batch_layout(const bz_opts *o, int32_t n, const int32_t *size, cons
         r.tile_off = tile;
         r.pix_off = pix;
         r.gauss_off = gauss_off[c];
+        r.curve_off = curve_off[c];
         for (int k = 0; k < 3; ++k) {
             r.bg[k] = bg ? bg[3 * c + k] : o->bg[k];
             if (!isfinite(r.bg[k])) return BZ_ERR_ARG;
@@ -176,6 +178,7 @@ bz_status bz_batch_layout(const bz_opts *o, int32_t n, const int32_t *size, cons
     end.tile_off = tile;
     end.pix_off = pix;
     end.gauss_off = gauss_off[n];
+    end.curve_off = curve_off[n];
     batch->n_canvas = n;
     batch->n_tiles = tile;
     batch->n_pixels = pix;
@@ -301,15 +304,18 @@ bz_status bz_area_order_workspace(int32_t n, int64_t *bytes) {
     return BZ_OK;
 }
 
-bz_status bz_area_order(const bz_curves *c, float *area, int32_t *order, int64_t *gauss_off,
-                        void *ws, int64_t ws_bytes, hipStream_t s) {
+bz_status bz_area_order(const bz_curves *c, const bz_opts *o, float *area, int32_t *order,
+                        int64_t *gauss_off, void *ws, int64_t ws_bytes, hipStream_t s) {
     bz_status st = check_curves(c);
     if (st != BZ_OK) return st;
+    const bz_batch *batch = o ? o->batch : nullptr;
+    if (batch && (batch->n_canvas < 1 || batch->n_canvas > 65535 || !batch->canvas))
+        return BZ_ERR_ARG;
     if (c->n_curves > 0 && (!area || !order || !gauss_off || !ws)) return BZ_ERR_ARG;
     if (c->n_curves > 0 && ((uintptr_t)ws & 255)) return BZ_ERR_ARG;
     if (ws_bytes < order_workspace_bytes(c->n_curves)) return BZ_ERR_CAPACITY;
     (void)hipGetLastError();
-    return launched(launch_area_order(*c, area, order, gauss_off, ws, s));
+    return launched(launch_area_order(*c, batch, area, order, gauss_off, ws, s));
 }
 
 bz_status bz_xing_loss(const bz_curves *c, float weight, float *loss, float *d_ctrl,

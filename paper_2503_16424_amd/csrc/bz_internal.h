@@ -59,8 +59,8 @@ hipError_t launch_bwd_curves(const bz_curves &c, const bz_opts &o, const float *
 hipError_t launch_l2(const float *image, const float *target, int64_t n, float scale,
                      float *d_image, float *loss, hipStream_t s);
 hipError_t launch_area(const bz_curves &c, float *area, hipStream_t s);
-hipError_t launch_area_order(const bz_curves &c, float *area, int32_t *order, int64_t *gauss_off,
-                             void *ws, hipStream_t s);
+hipError_t launch_area_order(const bz_curves &c, const bz_batch *batch, float *area,
+                             int32_t *order, int64_t *gauss_off, void *ws, hipStream_t s);
 hipError_t launch_xing(const bz_curves &c, float weight, float *loss, float *d_ctrl,
                        hipStream_t s);
 int64_t order_workspace_bytes(int64_t n_curves);

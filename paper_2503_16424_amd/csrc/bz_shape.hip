@@ -9,8 +9,9 @@
 //
 // Draw order.  Curves sorted by area, smallest in front, ties by index (a
 // stable LSD radix sort on the float bits of the non-negative areas, the
-// binning's sort kernels), then the first Gaussian of every draw position by
-// an exclusive scan of the per-curve Gaussian counts.  Everything stays on
+// binning's sort kernels; for a batch a second stable pass on the canvas
+// index keeps every canvas's curves together), then the first Gaussian of
+// every draw position by an exclusive scan of the per-curve Gaussian counts.  Everything stays on
 // the device, so the order can follow the curves every step.
 //
 // Xing loss (Sec. 3.5, the convexity term of LIVE).  Per cubic segment
@@ -67,6 +68,15 @@ __global__ void k_area_keys(const float *area, int n, uint32_t *keys, uint32_t *
     const float a = area[i];
     keys[i] = isnan(a) ? 0xffffffffu : __float_as_uint(fmaxf(a, 0.f));
     vals[i] = (uint32_t)i;
+}
+
+// Second key of a batch's order: the canvas of the curve at each position.
+__global__ void k_canvas_keys(const bz_canvas *cv, int n_canvas, const uint32_t *vals, int n,
+                              uint32_t *keys) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    keys[p] = (uint32_t)batch_find(cv, n_canvas, (int64_t)vals[p],
+                                   [](const bz_canvas &r) { return (int64_t)r.curve_off; });
 }
 
 __global__ void k_order_counts(bz_curves c, const uint32_t *vals, int32_t *order, uint32_t *cnt) {
@@ -176,8 +186,8 @@ hipError_t launch_area(const bz_curves &c, float *area, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_area_order(const bz_curves &c, float *area, int32_t *order, int64_t *gauss_off,
-                             void *ws, hipStream_t s) {
+hipError_t launch_area_order(const bz_curves &c, const bz_batch *batch, float *area,
+                             int32_t *order, int64_t *gauss_off, void *ws, hipStream_t s) {
     const int n = c.n_curves;
     if (n == 0) return hipGetLastError();
     OrderLayout L = order_layout(n);
@@ -192,6 +202,12 @@ hipError_t launch_area_order(const bz_curves &c, float *area, int32_t *order, in
     hipLaunchKernelGGL(k_area_keys, dim3(nb), dim3(256), 0, s, (const float *)area, n, keys, vals);
     hipError_t e = sort_pairs_u32(keys, vals, keys2, vals2, n, 32, hist, part, status, s);
     if (e != hipSuccess) return e;
+    if (batch) {      // stable by canvas on top: canvas-major, area inside each canvas
+        hipLaunchKernelGGL(k_canvas_keys, dim3(nb), dim3(256), 0, s, batch->canvas,
+                           batch->n_canvas, (const uint32_t *)vals, n, keys);
+        e = sort_pairs_u32(keys, vals, keys2, vals2, n, 16, hist, part, status, s);
+        if (e != hipSuccess) return e;
+    }
     // after the sort keys2 / vals2 are free: counts and offsets
     hipLaunchKernelGGL(k_order_counts, dim3(nb), dim3(256), 0, s, c, (const uint32_t *)vals,
                        order, keys2);

@@ -179,8 +179,10 @@ def _batch_layout(sizes, goff, bg=None, tile=(16, 16)):
     bgp = None if bg is None else np.ascontiguousarray(bg, np.float32).ctypes.data_as(C.c_void_p)
     recs = (bz.Canvas * (n + 1))()
     batch = bz.Batch()
+    coff = np.ascontiguousarray(np.arange(n + 1) * 3, np.int32)
     st = lib.bz_batch_layout(C.byref(o), n, size.ctypes.data_as(C.c_void_p), bgp,
-                             g.ctypes.data_as(C.c_void_p), C.addressof(recs), C.byref(batch))
+                             g.ctypes.data_as(C.c_void_p), coff.ctypes.data_as(C.c_void_p),
+                             C.addressof(recs), C.byref(batch))
     return st, recs, batch
 
 
@@ -188,7 +190,7 @@ def test_batch_records_have_the_c_layout():
     assert C.sizeof(bz.Canvas) == 56
     assert C.sizeof(bz.Batch) == 40
     assert bz.Opts.batch.offset == 56 and C.sizeof(bz.Opts) == 64
-    assert bz.Canvas.bg.offset == 40
+    assert bz.Canvas.bg.offset == 40 and bz.Canvas.curve_off.offset == 52
 
 
 def test_batch_layout_numbers_tiles_and_pixels_canvas_by_canvas():
@@ -203,10 +205,11 @@ def test_batch_layout_numbers_tiles_and_pixels_canvas_by_canvas():
         assert (r.width, r.height) == (W, H)
         assert (r.tiles_x, r.tiles_y) == ((W + 31) // 32, (H + 7) // 8)
         assert r.tile_off == sum(tiles[:c]) and r.pix_off == sum(pix[:c])
-        assert r.gauss_off == goff[c]
+        assert r.gauss_off == goff[c] and r.curve_off == 3 * c
         assert abs(r.bg[2] - 0.3) < 1e-7
     end = recs[len(sizes)]
-    assert (end.tile_off, end.pix_off, end.gauss_off) == (sum(tiles), sum(pix), 777)
+    assert (end.tile_off, end.pix_off, end.gauss_off, end.curve_off) == \
+        (sum(tiles), sum(pix), 777, 12)
     assert (batch.n_canvas, batch.n_tiles, batch.n_pixels, batch.n_gauss) == \
         (4, sum(tiles), sum(pix), 777)
 
@@ -222,7 +225,7 @@ def test_batch_layout_rejects_bad_batches(sizes, goff):
     if not sizes:
         lib = bz.load_library()
         o = bz.make_opts(1, 1, (1, 1, 1), bz.RenderOptions())
-        assert lib.bz_batch_layout(C.byref(o), 0, None, None, None, None,
+        assert lib.bz_batch_layout(C.byref(o), 0, None, None, None, None, None,
                                    C.byref(bz.Batch())) == bz.BZ_ERR_ARG
         return
     st, _, _ = _batch_layout(sizes, goff)

@@ -167,3 +167,64 @@ def test_batched_64_canvases_sampled_parity(torch_cuda):
             err = np.abs(got[:, ys, xs].T - p["rgb"]).max()
             assert err <= IMG_TOL, (c, err)
         del r
+
+
+def test_many_tiny_canvases(torch_cuda):
+    """300 canvases of 1..40 px sides (many with no curve): every one renders
+    bit for bit as alone, with both launch forms."""
+    from paper_2503_16424_amd import bz
+    rng = np.random.default_rng(61)
+    parts = []
+    for c in range(300):
+        W, H = int(rng.integers(1, 41)), int(rng.integers(1, 41))
+        n = int(rng.integers(0, 4))
+        parts.append(scenes.uniform_open(1000 + c, W, H, n, int(rng.integers(2, 12))))
+    ref = [bz.Rasterizer(sc).render().cpu().numpy() for sc in parts]
+    for persistent in (False, True):
+        r = _rast(parts, (8, 8), persistent)
+        img = r.render()
+        for c in range(len(parts)):
+            got = r.canvas_view(img, c).cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), ref[c].view(np.uint32)), (c, persistent)
+
+
+def test_step_graph_with_every_option(torch_cuda):
+    """Batch + persistent launches + recomputed blend state + area draw order,
+    recorded as one graph: replays reproduce the eager step, and the
+    gradients match the oracle run on the same draw order."""
+    torch = torch_cuda
+    from paper_2503_16424_amd.graph import StepGraph
+    parts = _small_batch()[:5]
+    r = _rast(parts, (16, 8), True, blend_state="recompute", draw_order="area")
+    tgts = [scenes.target_noise(70 + c, sc.width, sc.height) for c, sc in enumerate(parts)]
+    tgt = torch.as_tensor(r.flat_images(tgts), device="cuda")
+    r.render()
+    r.step(tgt)
+    torch.cuda.synchronize()
+    ref_img, ref_ctrl = r.image.clone(), r.d_ctrl.clone()
+    g = StepGraph(r, tgt)
+    for rep in range(3):
+        r.image.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(r.image.view(torch.int32), ref_img.view(torch.int32)), rep
+        assert rel_l2(r.d_ctrl.cpu().numpy(), ref_ctrl.cpu().numpy()) <= 1e-5, rep
+    # oracle on the concatenated scene in the device's draw order
+    order = r.order.cpu().numpy()
+    sc = scenes.concat(parts)
+    sc.rank = np.empty(sc.n_curves, np.int32)
+    sc.rank[order] = np.arange(sc.n_curves, dtype=np.int32)
+    # per canvas: each canvas's curves keep their relative area order
+    n0 = 0
+    d_ref = []
+    for c, p in enumerate(parts):
+        sub = p.copy()
+        rk = sc.rank[n0: n0 + p.n_curves]
+        sub.rank = np.argsort(np.argsort(rk)).astype(np.int32)
+        o0 = oracle.forward_backward(sub)
+        assert np.abs(r.canvas_view(r.image, c).cpu().numpy() - o0["image"]).max() <= IMG_TOL
+        d = 2.0 * (o0["image"] - tgts[c].astype(np.float64)) / (3.0 * r.n_pixels)
+        d_ref.append(oracle.forward_backward(sub, d)["d_ctrl"])
+        n0 += p.n_curves
+    assert rel_l2(r.d_ctrl.cpu().numpy(), np.concatenate(d_ref)) <= GRAD_TOL

@@ -143,3 +143,32 @@ def test_xing_loss_and_gradient(torch_cuda):
             fd[j, a] = (lp - so.xing_loss(s, w)) / (2 * h)
     assert rel_l2(grad, fd) <= 1e-5
     assert np.all(grad[np.repeat(sc.kind, np.diff(sc.ctrl_off)) == 0] == 0)   # open curves: none
+
+
+def test_area_order_of_a_batch_is_per_canvas(torch_cuda):
+    from paper_2503_16424_amd import bz
+    parts = [SCENES["mixed_small"](), scenes.small_mixed(21, W=60, H=50, n_closed=5, n_open=6),
+             scenes.uniform_open(22, 30, 30, 0, 8), SCENES["mixed_R20"]()]
+    r = bz.Rasterizer(parts, draw_order="area")
+    r.reorder()
+    order = r.order.cpu().numpy()
+    area = r.area.cpu().numpy()
+    goff = r.gauss_off.cpu().numpy()
+    c0 = 0
+    for p in parts:
+        seg = order[c0: c0 + p.n_curves]
+        assert sorted(seg.tolist()) == list(range(c0, c0 + p.n_curves))     # canvas kept together
+        local = p.copy()
+        _check_order(seg - c0, goff[c0: c0 + p.n_curves + 1] - goff[c0], area[c0: c0 + p.n_curves],
+                     local)
+        ref = so.curve_area(p)
+        assert np.all(np.abs(area[c0: c0 + p.n_curves] - ref) <= 2e-7 * np.abs(ref) + 1e-30)
+        c0 += p.n_curves
+    img = r.render()
+    for c, p in enumerate(parts):
+        s2 = p.copy()
+        seg = order[sum(q.n_curves for q in parts[:c]):][: p.n_curves] - sum(q.n_curves for q in parts[:c])
+        s2.rank = np.empty(p.n_curves, np.int32)
+        s2.rank[seg] = np.arange(p.n_curves, dtype=np.int32)
+        o = oracle.forward_backward(s2)
+        assert np.abs(r.canvas_view(img, c).cpu().numpy() - o["image"]).max() <= 1e-5, c

@@ -6,7 +6,11 @@ workload: 2048x2048 canvas, 20,000 curves (12,000 closed with R = 20 interior
 rows and 8,000 open 3-segment strokes, 24 samples per row), 6,528,000
 Gaussians, seeded draw order, uniform-noise target.
 
-Prints one JSON line (see the README for the fields).
+Prints one JSON line (see the README for the fields).  Other workloads:
+--workload batched_64 (64 canvases in one batch, against the canvases one
+after the other), --workload curvenet (the learned initialiser's training
+step), --workload open_512 / tiny_128; --blend-state recompute and
+--persistent select the other launch forms of the 2048x2048 step.
 """
 from __future__ import annotations
 

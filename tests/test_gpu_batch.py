@@ -150,8 +150,9 @@ def test_batched_64_canvases_sampled_parity(torch_cuda):
     from paper_2503_16424_amd import bz
     parts = scenes.batched(0)
     _note(f"64 canvases: {sum(p.n_gauss for p in parts)} Gaussians")
-    for persistent in (False, True):
-        r = _rast(parts, persistent=persistent)
+    # (16, 32) persistent: the configuration the autotuner picks on this workload
+    for tile, persistent in (((16, 16), False), ((16, 16), True), ((16, 32), True)):
+        r = _rast(parts, tile, persistent=persistent)
         img = r.render()
         rng = np.random.default_rng(7)
         for c in rng.choice(len(parts), 6, replace=False):

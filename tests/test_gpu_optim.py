@@ -190,3 +190,33 @@ def test_adam_fit_raises_psnr_and_survives_buffer_growth(torch_cuda):
     assert np.isfinite(res.final_psnr)
     assert res.final_psnr > first + 3.0
     assert all(np.isfinite(p) for _, p in res.psnr)
+
+
+def test_gradient_at_the_512_workload_after_adam_steps(torch_cuda):
+    """The 512x512 fit (2,048 strokes x K = 32) after 20 Adam steps on the GPU:
+    the image and the four gradient groups at the reached parameters match
+    the oracle evaluated at the same parameters."""
+    torch = torch_cuda
+    from paper_2503_16424_amd import bz
+    from paper_2503_16424_amd.optim import FitConfig, fit, noisy_target
+    clean = bz.Rasterizer(scenes.hidden_512(1)).render().cpu().numpy()
+    tgt = noisy_target(clean, 2, 0.02)
+    sc = scenes.open_512(0)
+    r = bz.Rasterizer(sc)
+    fit(r, torch.as_tensor(tgt, device="cuda"), FitConfig(steps=20, log_every=20))
+    s2 = sc.copy()
+    s2.ctrl = r.ctrl.cpu().numpy().astype(np.float32)
+    s2.color = r.color.cpu().numpy().astype(np.float32)
+    s2.opacity = r.opacity.cpu().numpy().astype(np.float32)
+    s2.stroke_w = r.stroke_w.cpu().numpy().astype(np.float32)
+    img = r.render().cpu().numpy()
+    o0 = oracle.forward_backward(s2)
+    assert np.abs(img - o0["image"]).max() <= 1e-5
+    d = 2.0 * (o0["image"] - tgt.astype(np.float64)) / o0["image"].size
+    o = oracle.forward_backward(s2, d)
+    r.backward(torch.as_tensor(d.astype(np.float32), device="cuda"))
+    torch.cuda.synchronize()
+    for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
+        e = rel_l2(getattr(r, k).cpu().numpy(), o[k])
+        _note(f"  512 workload {k}: rel L2 {e:.2e}")
+        assert e <= GRAD_TOL, k

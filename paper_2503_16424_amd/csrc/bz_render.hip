@@ -395,7 +395,11 @@ __device__ inline float reduce_scatter64(float (&v)[64], int lane) {
 }
 
 constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
-constexpr int kTableCap = 640;   // tile-list positions pooled in LDS by the backward
+// Tile-list positions pooled in LDS by the backward.  With 16x16 tiles a
+// block then takes 256 x 52 B of staging + 9 x 512 x 4 B of sums = 31 KiB,
+// so five blocks share a CU's 160 KiB of LDS: five waves per SIMD, the
+// occupancy the kernel's register budget is held to.
+constexpr int kTableCap = 512;
 
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
 // its pixels used down to the first.  Per pixel and contributor (reverse
@@ -617,8 +621,12 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     }
 }
 
+// Held to 96 VGPRs (five waves per SIMD): the 64 in-place reduction registers
+// dominate, and the few spills this costs sit outside the per-Gaussian
+// arithmetic; at four waves per SIMD the stage ran 8% slower.
 template <bool kRecompute>
-__global__ __launch_bounds__(1024) void k_bwd_tiles(TileArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_bwd_tiles(
+    TileArgs a) {
     if (a.status[1] & Status::kOverflow) return;         // whole grid
     for_tiles(a, [&](int tile) { bwd_tile<kRecompute>(a, tile); });
 }

@@ -175,6 +175,14 @@ __device__ inline void for_tiles(const TileArgs &a, Body body) {
     }
 }
 
+// min(x, hi) for finite x and a wave-uniform hi, as one VALU instruction:
+// fminf would canonicalise both operands first (IEEE mode), two more per use.
+__device__ inline float min_amax(float x, float hi) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "s"(hi), "v"(x));
+    return r;
+}
+
 // Result of a front-to-back sweep for one pixel.
 struct Sweep {
     float T, C0, C1, C2;   // transmittance after the last contributor, colour sum
@@ -219,7 +227,8 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
             const float G = __builtin_amdgcn_exp2f(-p2);
             const bool c = !done && G > g_min;
             const float araw = fmaf(st.q.w, G, -st.c.w);
-            const float al = c ? (araw < amax ? araw : amax) : 0.f;
+            const float acl = min_amax(araw, amax);
+            const float al = c ? acl : 0.f;
             if (kColor) {
                 const float wgt = al * r.T;
                 r.C0 = fmaf(wgt, st.c.x, r.C0);
@@ -230,7 +239,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
             r.last = c ? k * 64 + b + 1 : r.last;
             if (kCount) r.cnt += c ? 1u : 0u;
             done = done || r.T < tmin;
-            if (__ballot(c)) vbits |= 1ull << b;
+            if (__builtin_amdgcn_ballot_w64(c)) vbits |= 1ull << b;
         }
         sink(k, vbits);
         if (__ballot(!done) == 0) break;
@@ -395,10 +404,21 @@ __device__ inline float reduce_scatter64(float (&v)[64], int lane) {
 }
 
 constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
+
+// Planes 0-5 are summed without their constant factors, which are applied
+// once to the reduced sums.  With f the alpha gradient, o' the scaled opacity,
+// P = f o' G and p = A dx^2 + B dx dy + C dy^2 the base-2 exponent (G = 2^-p):
+// dL/dmean = ln 2 P (dp/d dx, dp/d dy), dL/dQ = -P (dx^2 / 2, dx dy, dy^2 / 2),
+// dL/do = f (G - g_min) / (1 - g_min).
+__device__ inline float plane_scale(int v, float inv_1mg) {
+    return v < 2 ? 0.69314718056f : v == 3 ? -1.f : (v == 2 || v == 4) ? -0.5f : v == 5 ? inv_1mg : 1.f;
+}
+
 // Tile-list positions pooled in LDS by the backward.  With 16x16 tiles a
-// block then takes 256 x 52 B of staging + 9 x 512 x 4 B of sums = 31 KiB,
+// block then takes 256 x 48 B of staging + 9 x 512 x 4 B of sums = 30 KiB,
 // so five blocks share a CU's 160 KiB of LDS: five waves per SIMD, the
-// occupancy the kernel's register budget is held to.
+// occupancy the kernel's register budget is held to.  (560 entries, 31.7 KiB,
+// measured as four blocks: the allocation is rounded up.)
 constexpr int kTableCap = 512;
 
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
@@ -423,8 +443,8 @@ constexpr int kVisCap = 128;
 
 template <bool kRecompute>
 __device__ inline void bwd_tile(const TileArgs &a, int tile) {
-    // dynamic LDS: [waves][64] staged records, [waves][64] their ids, the sum
-    // table, and (kRecompute) [waves][kVisCap] batch masks
+    // dynamic LDS: [waves][64] staged records, the sum table, and (kRecompute)
+    // [waves][kVisCap] batch masks
     extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_top[16];
     const int nwaves = blockDim.x >> 6;
@@ -439,13 +459,11 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
-    uint32_t *my_ids = reinterpret_cast<uint32_t *>(s_stage + nwaves * 64) + w * 64;
     // Per-tile sums, plane-major [9][tab_cap], indexed by tile-list position:
     // the quads of a tile share most of their Gaussians, so their sums meet
     // here and leave the block with one global atomic per (Gaussian, plane).
     const int tab_cap = a.tab_cap;
-    float *table = reinterpret_cast<float *>(reinterpret_cast<uint32_t *>(s_stage + nwaves * 64) +
-                                             nwaves * 64);
+    float *table = reinterpret_cast<float *>(s_stage + nwaves * 64);
     // kRecompute: per-wave batch masks after the table
     uint64_t *s_vis = reinterpret_cast<uint64_t *>(table + 9 * tab_cap) + w * kVisCap;
 
@@ -495,15 +513,11 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     __syncthreads();
 
     const float g_min = a.g_min, amax = a.alpha_max, inv_1mg = a.inv_1mg;
-    const float ln2 = 0.69314718056f;
     const int64_t ng = a.n_gauss;
     const int my_v = lane % 9, my_s = lane / 9;
-    uint32_t slot_id[kSlots], slot_pos[kSlots];
+    uint32_t slot_pos[kSlots];
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i) {
-        slot_id[i] = 0;
-        slot_pos[i] = 0;
-    }
+    for (int i = 0; i < kSlots; ++i) slot_pos[i] = 0;
 
     // Batches are visited last to first; inside a batch, entries from the
     // highest position down.  Only entries whose bit the forward pass set (at
@@ -538,7 +552,6 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                                 float4 q;
                                 stage_record(a, id, st, q);
                                 my[lane] = st;
-                                my_ids[lane] = id;
                             }
                             wave_lds_sync();
                         }
@@ -550,7 +563,6 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                             Staged st;
                             hit = stage_entry(a, id, qx0, qy0, st);
                             my[lane] = st;
-                            my_ids[lane] = id;
                         }
                         vm = __ballot(hit) & in_list;
                         wave_lds_sync();
@@ -564,13 +576,15 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     const uint32_t pos = lo + (uint32_t)b;
                     const float dx = (px - st.m.x) - st.m.z;
                     const float dy = (py - st.m.y) - st.m.w;
-                    const float t1 = st.q.x * dx + st.q.y * dy;
-                    const float p2 = dx * t1 + st.q.z * dy * dy;
+                    const float u = st.q.z * dy;
+                    const float t1 = fmaf(st.q.x, dx, st.q.y * dy);
+                    const float p2 = fmaf(dx, t1, dy * u);       // A dx^2 + B dx dy + C dy^2
                     const float G = __builtin_amdgcn_exp2f(-p2);
                     const bool c = pos < nl && G > g_min;
                     const float araw = fmaf(st.q.w, G, -st.c.w);
                     const bool shaped = c && araw <= amax;       // alpha not clamped
-                    const float al = c ? (araw < amax ? araw : amax) : 0.f;
+                    const float acl = min_amax(araw, amax);
+                    const float al = c ? acl : 0.f;
                     const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
                     const float wgt = al * Tb;
                     const float e0 = st.c.x - A0, e1 = st.c.y - A1, e2 = st.c.z - A2;
@@ -580,19 +594,19 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     A2 = fmaf(al, e2, A2);
                     T = Tb;
                     const float f = shaped ? abar : 0.f;
-                    const float pbar = -f * st.q.w * G;
-                    const float pl = pbar * ln2;
-                    const float ph = 0.5f * pbar;
-                    acc[9 * s + 0] = -pl * (t1 + st.q.x * dx);
-                    acc[9 * s + 1] = -pl * (st.q.y * dx + 2.f * st.q.z * dy);
-                    acc[9 * s + 2] = ph * dx * dx;
-                    acc[9 * s + 3] = pbar * dx * dy;
-                    acc[9 * s + 4] = ph * dy * dy;
-                    acc[9 * s + 5] = f * (G - g_min) * inv_1mg;
+                    // P = -dL/dp; the planes' constant factors (plane_scale)
+                    // are applied to the sums after the reduction
+                    const float P = f * st.q.w * G;
+                    const float Pdx = P * dx, Pdy = P * dy;
+                    acc[9 * s + 0] = P * fmaf(st.q.x, dx, t1);          // d p2 / d dx
+                    acc[9 * s + 1] = P * fmaf(st.q.y, dx, u + u);       // d p2 / d dy
+                    acc[9 * s + 2] = Pdx * dx;
+                    acc[9 * s + 3] = Pdx * dy;
+                    acc[9 * s + 4] = Pdy * dy;
+                    acc[9 * s + 5] = f * (G - g_min);
                     acc[9 * s + 6] = wgt * g0;
                     acc[9 * s + 7] = wgt * g1;
                     acc[9 * s + 8] = wgt * g2;
-                    slot_id[s] = (uint32_t)__builtin_amdgcn_readfirstlane((int)my_ids[b]);
                     slot_pos[s] = pos;
                     filled = s + 1;
                 }
@@ -600,24 +614,23 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
         }
         if (filled == 0) break;
         const float r = reduce_scatter64(acc, lane);
-        uint32_t my_id = slot_id[0], my_pos = slot_pos[0];
+        uint32_t my_pos = slot_pos[0];
 #pragma unroll
-        for (int i = 1; i < kSlots; ++i) {
-            my_id = my_s == i ? slot_id[i] : my_id;
-            my_pos = my_s == i ? slot_pos[i] : my_pos;
-        }
+        for (int i = 1; i < kSlots; ++i) my_pos = my_s == i ? slot_pos[i] : my_pos;
         if (lane < 9 * filled) {
             if (my_pos < (uint32_t)tab_cap)
                 atomicAdd(&table[my_v * tab_cap + my_pos], r);
             else
-                atomicAdd(a.d_gauss + (int64_t)my_v * ng + my_id, r);
+                atomicAdd(a.d_gauss + (int64_t)my_v * ng + a.ids[start + my_pos],
+                          r * plane_scale(my_v, inv_1mg));
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 9 * tab_n; i += blockDim.x) {
         const int v = i / tab_n, p = i - v * tab_n;
         const float val = table[v * tab_cap + p];
-        if (val != 0.f) atomicAdd(a.d_gauss + (int64_t)v * ng + a.ids[start + p], val);
+        if (val != 0.f)
+            atomicAdd(a.d_gauss + (int64_t)v * ng + a.ids[start + p], val * plane_scale(v, inv_1mg));
     }
 }
 
@@ -1004,8 +1017,7 @@ hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
     a.n_gauss = n_gauss;
     int threads = o.tile_w * o.tile_h;
     a.tab_cap = kTableCap;
-    size_t lds = (sizeof(Staged) + sizeof(uint32_t)) * (size_t)threads +
-                 sizeof(float) * 9 * (size_t)kTableCap;
+    size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * 9 * (size_t)kTableCap;
     if (st) {
         a.t_final = st->t_final;
         a.n_last = st->n_last;

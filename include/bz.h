@@ -174,8 +174,12 @@ typedef struct {
  * reverse pass recomputes the state tile by tile (one extra front-to-back
  * sweep without colour, no per-pixel memory).  Both calls of one step must
  * agree: a NULL-state forward is followed by a NULL-state backward.
- * t_final, n_last: [height][width]; n_last is the number of tile-list entries up
- *   to and including the pixel's last contributor.
+ * t_final, n_last: [height][width].  n_last bounds the tile-list positions of the
+ *   pixel's contributors: for a pixel whose blend stopped (T below t_min) it is
+ *   1 + the position of the contributor that stopped it; otherwise the end of
+ *   the last 64-entry batch that contributed to the pixel's 8x8 block (capped
+ *   at the list length).  Every entry before it with G > g_min contributed to
+ *   the pixel and no entry at or after it did.
  * n_contrib (optional, may be NULL): contributors per pixel, [height][width].
  * visit: per 8x8 pixel block and per 64-entry batch of its tile list, the bit
  *   mask of entries that contributed to at least one pixel of the block; the

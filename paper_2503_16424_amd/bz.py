@@ -212,7 +212,7 @@ class Rasterizer:
     :meth:`backward`.
 
     ``blend_state="stored"`` keeps the forward pass's per-pixel state (T after
-    the last contributor, its list position) and per-batch contribution masks
+    the last contributor, a bound on its list position) and per-batch contribution masks
     for the backward; ``"recompute"`` keeps none of it and the backward
     recomputes it tile by tile (one more sweep of the tile lists).
     """

@@ -269,7 +269,30 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
 }
 
 // --- stable LSD radix sort on tile ids --------------------------------------
+//
+// A block owns kTile consecutive elements; inside it wave w owns the kWaveItems
+// elements [w kWaveItems, (w + 1) kWaveItems) and takes them 64 at a time, in
+// order, lane l holding element 64 j + l of round j.  The lanes of a round that
+// share a digit find each other with one ballot per digit bit; the lowest of
+// them adds the group's size to the wave's count of that digit (an LDS word no
+// other lane of the round touches).  So every element learns its rank among the
+// wave's elements of its digit, in element order, without block barriers.
 
+constexpr int kWaveItems = kItems * 64;
+
+// Lanes of the wave whose digit equals this lane's (valid lanes only).
+__device__ inline uint64_t digit_peers(bool valid, uint32_t d, int nbits) {
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return valid ? peers : 0ull;
+}
+
+// Per-block digit counts (LDS atomics: cheaper here than grouping the lanes of
+// a digit with ballots first, which the scatter needs for its ranks anyway).
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                     const int64_t *status, int shift, int nbits,
                                                     uint32_t *__restrict__ hist,
@@ -277,13 +300,13 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     __shared__ uint32_t h[kRadix];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t n = (status[1] & Status::kOverflow) ? 0 : status[0];
-    int64_t base = (int64_t)blockIdx.x * kTile;
-    uint32_t mask = (1u << nbits) - 1u;
+    const int64_t n = (status[1] & Status::kOverflow) ? 0 : status[0];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const uint32_t mask = (1u << nbits) - 1u;
     if (base < n) {
 #pragma unroll 4
         for (int j = 0; j < kItems; ++j) {
-            int64_t e = base + j * kBlk + threadIdx.x;
+            const int64_t e = base + j * kBlk + threadIdx.x;
             if (e < n) atomicAdd(&h[(keys[e] >> shift) & mask], 1u);
         }
     }
@@ -299,9 +322,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     __shared__ uint32_t s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
     __shared__ uint32_t s_prefix[kRadix];
-    __shared__ uint32_t s_run[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
-    __shared__ uint32_t s_wcnt[kBlk / 64][kRadix];
+    __shared__ uint32_t s_wrun[kBlk / 64][kRadix];   // per-wave digit counts, then bases
     __shared__ uint64_t s_wave[kBlk / 64];
 
     if (status[1] & Status::kOverflow) return;
@@ -312,73 +334,62 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t dmask = (1u << nbits) - 1u;
     const int cnt = (int)(n - base < kTile ? n - base : kTile);
 
-    s_run[tid] = 0;
 #pragma unroll
-    for (int q = 0; q < kBlk / 64; ++q) s_wcnt[q][tid] = 0;
-    __syncthreads();
-
-    uint32_t key[kItems], val[kItems];
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        int li = j * kBlk + tid;
-        if (li < cnt) {
-            key[j] = keys_in[base + li];
-            val[j] = vals_in[base + li];
-            atomicAdd(&s_run[(key[j] >> shift) & dmask], 1u);
-        } else {
-            key[j] = 0;
-            val[j] = 0;
-        }
-    }
-    __syncthreads();
-    {
-        uint64_t tot;
-        uint32_t c = s_run[tid];
-        uint32_t ex = (uint32_t)block_excl_scan(c, s_wave, tot);
-        s_prefix[tid] = ex;
-        s_gbase[tid] = hist_scanned[(int64_t)tid * hist_blocks + blockIdx.x];
-        s_run[tid] = 0;
-    }
+    for (int q = 0; q < kBlk / 64; ++q) s_wrun[q][tid] = 0;
     __syncthreads();
 
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t *run = s_wrun[w];
+    uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        int li = j * kBlk + tid;
-        bool valid = li < cnt;
-        uint32_t d = (key[j] >> shift) & dmask;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < nbits; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
+        const int li = w * kWaveItems + j * 64 + lane;
+        const bool valid = li < cnt;
+        key[j] = valid ? keys_in[base + li] : 0u;
+        val[j] = valid ? vals_in[base + li] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int li = w * kWaveItems + j * 64 + lane;
+        const bool valid = li < cnt;
+        const uint32_t d = (key[j] >> shift) & dmask;
+        const uint64_t peers = digit_peers(valid, d, nbits);
+        // the wave's LDS accesses execute in order: this round reads the
+        // counts the previous round's group leaders wrote
+        const uint32_t before = valid ? run[d] : 0u;
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0) run[d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        // digit tid: bases of the four waves, then the block's prefix
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < kBlk / 64; ++q) {
+            const uint32_t c = s_wrun[q][tid];
+            s_wrun[q][tid] = t;
+            t += c;
         }
-        if (!valid) peers = 0;
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t off = s_run[d] + rank;
-            for (int q = 0; q < w; ++q) off += s_wcnt[q][d];
-            uint32_t slot = s_prefix[d] + off;
+        uint64_t tot;
+        s_prefix[tid] = (uint32_t)block_excl_scan(t, s_wave, tot);
+        s_gbase[tid] = hist_scanned[(int64_t)tid * hist_blocks + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int li = w * kWaveItems + j * 64 + lane;
+        if (li < cnt) {
+            const uint32_t d = (key[j] >> shift) & dmask;
+            const uint32_t slot = s_prefix[d] + run[d] + rank[j];
             s_keys[slot] = key[j];
             s_vals[slot] = val[j];
         }
-        __syncthreads();
-        {
-            uint32_t add = 0;
-#pragma unroll
-            for (int q = 0; q < kBlk / 64; ++q) {
-                add += s_wcnt[q][tid];
-                s_wcnt[q][tid] = 0;
-            }
-            s_run[tid] += add;
-        }
-        __syncthreads();
     }
+    __syncthreads();
     for (int i = tid; i < cnt; i += kBlk) {
-        uint32_t k = s_keys[i];
-        uint32_t d = (k >> shift) & dmask;
-        uint32_t pos = s_gbase[d] + (uint32_t)i - s_prefix[d];
+        const uint32_t k = s_keys[i];
+        const uint32_t d = (k >> shift) & dmask;
+        const uint32_t pos = s_gbase[d] + (uint32_t)i - s_prefix[d];
         keys_out[pos] = k;
         vals_out[pos] = s_vals[i];
     }
@@ -389,16 +400,37 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+// First and one-past-last position of every tile: thread t looks at the
+// kRangeItems keys from kRangeItems t and the key after them.
+constexpr int kRangeItems = 8;
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ keys,
                                                 const int64_t *status, int64_t cap,
                                                 uint32_t *__restrict__ ranges) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (status[1] & Status::kOverflow) return;
-    int64_t n = status[0];
-    if (i >= n || i >= cap) return;
-    uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)i;
-    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+    const int64_t n0 = status[0];
+    const int64_t n = n0 < cap ? n0 : cap;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+    if (i0 >= n) return;
+    uint32_t k[kRangeItems + 1];
+    if (i0 + kRangeItems <= n && (i0 & 3) == 0) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(keys + i0);
+        const uint4 b = *reinterpret_cast<const uint4 *>(keys + i0 + 4);
+        k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+        k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRangeItems; ++j) k[j] = i0 + j < n ? keys[i0 + j] : ~0u;
+    }
+    k[kRangeItems] = i0 + kRangeItems < n ? keys[i0 + kRangeItems] : ~0u;
+    const uint32_t prev = i0 > 0 ? keys[i0 - 1] : ~0u;
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j) {
+        const int64_t i = i0 + j;
+        if (i >= n) break;
+        if ((j == 0 ? prev : k[j - 1]) != k[j]) ranges[2 * (int64_t)k[j]] = (uint32_t)i;
+        if (k[j + 1] != k[j]) ranges[2 * (int64_t)k[j] + 1] = (uint32_t)(i + 1);
+    }
 }
 
 __global__ void k_set_count(int64_t *status, int64_t n) {
@@ -528,8 +560,8 @@ hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_
             kin = kout;
             vin = vout;
         }
-        hipLaunchKernelGGL(k_ranges, dim3(cdiv(b.cap_pairs, 256)), dim3(256), 0, s, kin,
-                           (const int64_t *)b.status, b.cap_pairs, b.ranges);
+        hipLaunchKernelGGL(k_ranges, dim3(cdiv(cdiv(b.cap_pairs, kRangeItems), 256)), dim3(256),
+                           0, s, kin, (const int64_t *)b.status, b.cap_pairs, b.ranges);
     }
     return hipGetLastError();
 }

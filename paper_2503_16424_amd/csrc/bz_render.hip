@@ -83,32 +83,47 @@ struct TileArgs {
     int64_t n_gauss;
 };
 
-// Entry of the wave's LDS slice: mean (hi, lo), log2-scaled half conic and
-// the opacity divided by (1 - g_min), colour and opacity * g_min / (1 - g_min).
+// Entry of the wave's LDS slice: the mean, log2-scaled half conic and the
+// opacity divided by (1 - g_min), colour and opacity * g_min / (1 - g_min).
+// The mean is held one of two ways:
+// - kRel (the front-to-back sweep): relative to the quad's first pixel centre
+//   (qx0, qy0), so a pixel's offset from it is one subtraction from the
+//   pixel's place in the quad (0..7 in x and y).  The record's mean is
+//   hi + lo; hi - qx0 is exact for any Gaussian near the quad, so the relative
+//   mean is rounded once.
+// - otherwise (the reverse pass): hi and lo as stored, the offset taken as
+//   (px - hi) - lo; this keeps the quad origin out of the reverse pass's
+//   registers, which are all in use.
 struct Staged {
-    float4 m;   // hi.x, hi.y, lo.x, lo.y
+    float4 m;   // kRel: mean - (qx0, qy0), 0, 0; else hi.x, hi.y, lo.x, lo.y
     float4 q;   // A, B, C (p*log2e = A dx^2 + B dx dy + C dy^2), o'
     float4 c;   // r, g, b, o' * g_min
 };
 
 // Load a record and compute its LDS constants.
-__device__ inline void stage_record(const TileArgs &a, uint32_t id, Staged &st, float4 &q) {
+template <bool kRel>
+__device__ inline void stage_record(const TileArgs &a, uint32_t id, float qx0, float qy0,
+                                    Staged &st, float4 &q) {
     const float4 m = a.rec[3 * (int64_t)id];
     q = a.rec[3 * (int64_t)id + 1];
     const float4 c = a.rec[3 * (int64_t)id + 2];
     const float op = q.w * a.inv_1mg;
-    st.m = m;
+    st.m = kRel ? make_float4((m.x - qx0) + m.z, (m.y - qy0) + m.w, 0.f, 0.f) : m;
     st.q = make_float4(0.5f * kLog2e * q.x, kLog2e * q.y, 0.5f * kLog2e * q.z, op);
     st.c = make_float4(c.x, c.y, c.z, op * a.g_min);
 }
 
 // Load a tile-list entry, compute its LDS constants and test its support
 // against the wave's 8x8 quad (first pixel centre qx0, qy0).
+template <bool kRel>
 __device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, float qy0,
                                    Staged &st) {
     float4 q;
-    stage_record(a, id, st, q);
-    const float x0 = (qx0 - st.m.x) - st.m.z, y0 = (qy0 - st.m.y) - st.m.w;
+    stage_record<kRel>(a, id, qx0, qy0, st, q);
+    // offsets of the quad's first pixel centre from the mean (the same value
+    // either way: -((hi - qx0) + lo) = (qx0 - hi) - lo under round to nearest)
+    const float x0 = kRel ? -st.m.x : (qx0 - st.m.x) - st.m.z;
+    const float y0 = kRel ? -st.m.y : (qy0 - st.m.y) - st.m.w;
     return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, q.x, q.y, q.z, a.box_thr);
 }
 
@@ -183,10 +198,27 @@ __device__ inline float min_amax(float x, float hi) {
     return r;
 }
 
+// Per lane: bit `lane` of the wave-uniform mask m ? on : off, as one
+// v_cndmask with m in scalar registers (a bool built from m would cost a shift,
+// an and and a compare per lane).
+__device__ inline float select_lanes(uint64_t m, float on, float off) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, %2, %1, %3" : "=v"(r) : "v"(on), "v"(off), "s"(m));
+    return r;
+}
+__device__ inline uint32_t select_lanes_u32(uint64_t m, uint32_t on, uint32_t off) {
+    return __float_as_uint(select_lanes(m, __uint_as_float(on), __uint_as_float(off)));
+}
+
+// A wave-uniform float moved to a scalar register.
+__device__ inline float uniform_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Result of a front-to-back sweep for one pixel.
 struct Sweep {
     float T, C0, C1, C2;   // transmittance after the last contributor, colour sum
-    uint32_t last;         // 1 + list position of the last contributor (0: none)
+    uint32_t last;         // list positions the reverse pass must consider (see below)
     uint32_t cnt;          // contributors (kCount only)
 };
 
@@ -198,20 +230,29 @@ struct Sweep {
 // a pixel stops after the first contributor that takes T below t_min, and the
 // wave leaves when all its pixels have stopped.  sink(k, bits) receives, for
 // batch k, the entries that changed at least one pixel of the quad.
+//
+// A pixel has stopped exactly when T < t_min (T never grows; lanes outside the
+// canvas start at T = -1), so the wave keeps that set as one 64-bit mask.
+// last: for a pixel that stopped, 1 + the list position of the contributor
+// that stopped it; otherwise the end of the last batch that changed a pixel of
+// the quad (capped at the list length).  Either way no entry at or beyond it
+// contributed to the pixel, and every earlier entry with G > g_min did, which
+// is all the reverse pass needs; recording it costs the loop nothing except
+// when a pixel stops.
 template <bool kColor, bool kCount, typename Sink>
 __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start, uint32_t end,
-                                  float px, float py, float qx0, float qy0, bool valid, int lane,
+                                  float lx, float ly, float qx0, float qy0, bool valid, int lane,
                                   Sink sink) {
-    Sweep r = {1.f, 0.f, 0.f, 0.f, 0u, 0u};
-    bool done = !valid;
+    Sweep r = {valid ? 1.f : -1.f, 0.f, 0.f, 0.f, 0u, 0u};
     const float g_min = a.g_min, amax = a.alpha_max, tmin = a.t_min;
-    uint32_t k = 0;
+    uint64_t stopped = __builtin_amdgcn_ballot_w64(r.T < tmin);
+    uint32_t k = 0, k_used = 0;
     for (uint32_t base = start; base < end; base += 64, ++k) {
         const uint32_t j = base + lane;
         bool hit = false;
         if (j < end) {
             Staged st;
-            hit = stage_entry(a, a.ids[j], qx0, qy0, st);
+            hit = stage_entry<true>(a, a.ids[j], qx0, qy0, st);
             my[lane] = st;
         }
         uint64_t mask = __ballot(hit);
@@ -221,35 +262,43 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
             const int b = __builtin_ctzll(mask);
             mask &= mask - 1;
             const Staged st = my[b];
-            const float dx = (px - st.m.x) - st.m.z;
-            const float dy = (py - st.m.y) - st.m.w;
+            const float dx = lx - st.m.x;
+            const float dy = ly - st.m.y;
             const float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
             const float G = __builtin_amdgcn_exp2f(-p2);
-            const bool c = !done && G > g_min;
+            // contributors: inside the support and not stopped, as a lane mask
+            const uint64_t cm = __builtin_amdgcn_ballot_w64(G > g_min) & ~stopped;
             const float araw = fmaf(st.q.w, G, -st.c.w);
-            const float acl = min_amax(araw, amax);
-            const float al = c ? acl : 0.f;
+            const float al = select_lanes(cm, min_amax(araw, amax), 0.f);
+            const float wgt = al * r.T;
             if (kColor) {
-                const float wgt = al * r.T;
                 r.C0 = fmaf(wgt, st.c.x, r.C0);
                 r.C1 = fmaf(wgt, st.c.y, r.C1);
                 r.C2 = fmaf(wgt, st.c.z, r.C2);
             }
-            r.T = fmaf(-al, r.T, r.T);
-            r.last = c ? k * 64 + b + 1 : r.last;
-            if (kCount) r.cnt += c ? 1u : 0u;
-            done = done || r.T < tmin;
-            if (__builtin_amdgcn_ballot_w64(c)) vbits |= 1ull << b;
+            {
+                // T (1 - alpha) as T - wgt, after wgt has used T: no copy of T
+                _Pragma("clang fp contract(off)") r.T = r.T - wgt;
+            }
+            if (kCount) r.cnt = select_lanes_u32(cm, r.cnt + 1u, r.cnt);
+            if (cm) vbits |= 1ull << b;
+            const uint64_t now = __builtin_amdgcn_ballot_w64(r.T < tmin);
+            if (__builtin_expect(now != stopped, 0)) {     // some pixel stopped here
+                r.last = select_lanes_u32(now & ~stopped, k * 64 + b + 1, r.last);
+                stopped = now;
+            }
         }
+        if (vbits) k_used = k + 1;
         sink(k, vbits);
-        if (__ballot(!done) == 0) break;
+        if (stopped == ~0ull) break;
         wave_lds_sync();
     }
+    r.last = select_lanes_u32(stopped, r.last, min(k_used * 64u, end - start));
     return r;
 }
 
 // Forward pass.  With kState the blend state the backward reads is written:
-// T after the last contributor, its position, and per (quad, batch) the mask
+// T after the last contributor, a bound on its position, and per (quad, batch) the mask
 // of entries that contributed; without it only the image.
 template <bool kState, bool kCount>
 __device__ inline void fwd_tile(const TileArgs &a, int tile) {
@@ -262,8 +311,9 @@ __device__ inline void fwd_tile(const TileArgs &a, int tile) {
     if (x0 >= tg.W || y0 >= tg.H) return;
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
     const bool valid = x < tg.W && y < tg.H;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
+    const float lx = (float)(lane & 7), ly = (float)(lane >> 3);   // pixel - first pixel of the quad
+    // wave-uniform: held in scalar registers
+    const float qx0 = uniform_f32((float)x0 + 0.5f), qy0 = uniform_f32((float)y0 + 0.5f);
     Staged *my = s_stage + w * 64;
 
     const int64_t pix = tg.pix0 + (int64_t)y * tg.W + x;
@@ -286,7 +336,7 @@ __device__ inline void fwd_tile(const TileArgs &a, int tile) {
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     uint64_t *vis = kState ? a.visit + (int64_t)w * a.words_per_plane + visit_word(start, tile)
                            : nullptr;
-    const Sweep r = fwd_sweep<true, kCount>(a, my, start, end, px, py, qx0, qy0, valid, lane,
+    const Sweep r = fwd_sweep<true, kCount>(a, my, start, end, lx, ly, qx0, qy0, valid, lane,
                                             [&](uint32_t k, uint64_t bits) {
                                                 if (kState && lane == 0) vis[k] = bits;
                                             });
@@ -303,7 +353,7 @@ __device__ inline void fwd_tile(const TileArgs &a, int tile) {
 }
 
 // Forward pass.  With kState the blend state the backward reads is written:
-// T after the last contributor, its position, and per (quad, batch) the mask
+// T after the last contributor, a bound on its position, and per (quad, batch) the mask
 // of entries that contributed; without it only the image.
 template <bool kState, bool kCount>
 __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
@@ -432,7 +482,7 @@ constexpr int kTableCap = 512;
 // wave in one transposed reduction and added to the per-Gaussian planes with
 // one 63-lane atomic instruction.
 //
-// kRecompute: the blend state (T after the last contributor, its position and
+// kRecompute: the blend state (T after the last contributor, the bound on its position and
 // the per-batch contribution masks) is not read from memory but recomputed by
 // a front-to-back sweep of the same quad (colour omitted), with the
 // instruction sequence of the forward pass, so T and the positions are those
@@ -457,6 +507,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
     const bool valid = wave_on && x < tg.W && y < tg.H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float lx = (float)(lane & 7), ly = (float)(lane >> 3);   // pixel - first pixel of the quad
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
     Staged *my = s_stage + w * 64;
     // Per-tile sums, plane-major [9][tab_cap], indexed by tile-list position:
@@ -478,7 +529,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
     if (kRecompute) {
         if (wave_on) {
-            const Sweep r = fwd_sweep<false, false>(a, my, start, start + len, px, py, qx0, qy0,
+            const Sweep r = fwd_sweep<false, false>(a, my, start, start + len, lx, ly, qx0, qy0,
                                                     valid, lane, [&](uint32_t k, uint64_t bits) {
                                                         if (lane == 0 && k < kVisCap) s_vis[k] = bits;
                                                     });
@@ -550,7 +601,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                                 const uint32_t id = a.ids[start + lo + lane];
                                 Staged st;
                                 float4 q;
-                                stage_record(a, id, st, q);
+                                stage_record<false>(a, id, qx0, qy0, st, q);
                                 my[lane] = st;
                             }
                             wave_lds_sync();
@@ -561,7 +612,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                         if ((uint32_t)lane < avail) {
                             const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
-                            hit = stage_entry(a, id, qx0, qy0, st);
+                            hit = stage_entry<false>(a, id, qx0, qy0, st);
                             my[lane] = st;
                         }
                         vm = __ballot(hit) & in_list;
@@ -613,6 +664,9 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
             }
         }
         if (filled == 0) break;
+        // acc[63] feeds only lane 63's sum, which is never stored: setting it
+        // here keeps it out of the registers live across the slot loop
+        acc[63] = 0.f;
         const float r = reduce_scatter64(acc, lane);
         uint32_t my_pos = slot_pos[0];
 #pragma unroll

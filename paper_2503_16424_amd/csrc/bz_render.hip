@@ -210,6 +210,15 @@ __device__ inline uint32_t select_lanes_u32(uint64_t m, uint32_t on, uint32_t of
     return __float_as_uint(select_lanes(m, __uint_as_float(on), __uint_as_float(off)));
 }
 
+// The backward's quad origin, re-read from LDS at every staging so that it
+// occupies no register across the slot loop: the index is a zero the compiler
+// cannot see through (one scalar move), so the read is not hoisted.
+__device__ inline int opaque_zero() {
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
 // A wave-uniform float moved to a scalar register.
 __device__ inline float uniform_f32(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -497,6 +506,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     // [waves][kVisCap] batch masks
     extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_top[16];
+    __shared__ float s_q0[16][2];      // each wave's quad origin, read when staging
     const int nwaves = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -506,9 +516,12 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     const bool wave_on = x0 < tg.W && y0 < tg.H;         // quad inside the canvas
     const int x = x0 + (lane & 7), y = y0 + (lane >> 3);
     const bool valid = wave_on && x < tg.W && y < tg.H;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const float lx = (float)(lane & 7), ly = (float)(lane >> 3);   // pixel - first pixel of the quad
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
+    if (lane == 0) {
+        s_q0[w][0] = qx0;
+        s_q0[w][1] = qy0;
+    }
     Staged *my = s_stage + w * 64;
     // Per-tile sums, plane-major [9][tab_cap], indexed by tile-list position:
     // the quads of a tile share most of their Gaussians, so their sums meet
@@ -546,7 +559,10 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
         g1 = dimg[plane + pix];
         g2 = dimg[2 * plane + pix];
     }
-    float A0 = tg.bg0, A1 = tg.bg1, A2 = tg.bg2;
+    // A (the colour composited behind, from the background forward) enters the
+    // gradient only through A . g, so that scalar is what the pass carries:
+    // A <- alpha c + (1 - alpha) A gives A.g <- alpha (c.g) + (1 - alpha) A.g.
+    float Ag = fmaf(tg.bg0, g0, fmaf(tg.bg1, g1, tg.bg2 * g2));
     uint32_t top = nl;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
@@ -573,7 +589,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     // Batches are visited last to first; inside a batch, entries from the
     // highest position down.  Only entries whose bit the forward pass set (at
     // least one pixel of this quad used them) are staged and visited.
-    int64_t k = wave_on ? ((int64_t)top + 63) / 64 : 0;
+    // batch counter (32-bit: its test k > 0 runs on the scalar unit every slot)
+    int32_t k = wave_on ? (int32_t)(((uint64_t)top + 63) / 64) : 0;
     uint64_t mask = 0;
     uint32_t lo = 0;
     // Slots not refilled in a round only feed sums that are never stored.
@@ -601,7 +618,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                                 const uint32_t id = a.ids[start + lo + lane];
                                 Staged st;
                                 float4 q;
-                                stage_record<false>(a, id, qx0, qy0, st, q);
+                                const float *q0 = s_q0[w + opaque_zero()];
+                                stage_record<true>(a, id, q0[0], q0[1], st, q);
                                 my[lane] = st;
                             }
                             wave_lds_sync();
@@ -612,7 +630,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                         if ((uint32_t)lane < avail) {
                             const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
-                            hit = stage_entry<false>(a, id, qx0, qy0, st);
+                            const float *q0 = s_q0[w + opaque_zero()];
+                            hit = stage_entry<true>(a, id, q0[0], q0[1], st);
                             my[lane] = st;
                         }
                         vm = __ballot(hit) & in_list;
@@ -625,8 +644,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     mask &= ~(1ull << b);
                     const Staged st = my[b];
                     const uint32_t pos = lo + (uint32_t)b;
-                    const float dx = (px - st.m.x) - st.m.z;
-                    const float dy = (py - st.m.y) - st.m.w;
+                    const float dx = lx - st.m.x;
+                    const float dy = ly - st.m.y;
                     const float u = st.q.z * dy;
                     const float t1 = fmaf(st.q.x, dx, st.q.y * dy);
                     const float p2 = fmaf(dx, t1, dy * u);       // A dx^2 + B dx dy + C dy^2
@@ -638,11 +657,10 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     const float al = c ? acl : 0.f;
                     const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
                     const float wgt = al * Tb;
-                    const float e0 = st.c.x - A0, e1 = st.c.y - A1, e2 = st.c.z - A2;
-                    const float abar = c ? Tb * (e0 * g0 + e1 * g1 + e2 * g2) : 0.f;
-                    A0 = fmaf(al, e0, A0);
-                    A1 = fmaf(al, e1, A1);
-                    A2 = fmaf(al, e2, A2);
+                    const float cg = fmaf(st.c.x, g0, fmaf(st.c.y, g1, st.c.z * g2));
+                    const float e = cg - Ag;                     // (c - A) . g
+                    const float abar = c ? Tb * e : 0.f;
+                    Ag = fmaf(al, e, Ag);
                     T = Tb;
                     const float f = shaped ? abar : 0.f;
                     // P = -dL/dp; the planes' constant factors (plane_scale)
@@ -726,7 +744,7 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
     extern __shared__ double2 lds_xy[];
     __shared__ float s_tau[256];
     __shared__ float s_red[kCurveThreads / 64][8];
-    __shared__ float s_cp[kCurveThreads / 64][2][3 * kMaxSeg + 1][2];
+    __shared__ float s_cp[2][3 * kMaxSeg + 1][2];
     constexpr int NT = kCurveThreads;
     const int p = blockIdx.x;
     const int lane = threadIdx.x;          // thread of the curve's workgroup
@@ -872,62 +890,46 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
             if (q < v.nopa) dop[q] = ob[q];
     }
 
-    // Control points.  Thread t owns row r = t/2 (and r + NT/2, ...) and
-    // coordinate t&1; it accumulates the gradient of the row's own control
-    // points, sum_k B_{jj-3s_k}(t_k) Xbar[r][k], weighted for the stored points:
-    // open -> as is; closed -> A_jj with (1 - tau_r) (all of it at the shared
-    // endpoints), B's interior points with tau_r.  Sums over rows are
-    // parity-split wave reductions (lanes 0 and 1 end with the x and y sums).
+    // Control points, in two deterministic steps.  (1) Thread (k, coord) sums
+    // column k of Xbar over the rows three ways: all rows (open curves and the
+    // endpoints a closed curve's boundaries share), weighted by 1 - tau_r (A's
+    // interior points) and by tau_r (B's interior points); the sums go to LDS
+    // (the T* terms are dead by now).  (2) Thread (point jj, coord, boundary)
+    // adds B_{jj - 3 s_k}(t_k) times those sums over the columns k in order.
     const int m = 3 * v.S;
-    float accA[3 * kMaxSeg + 1], accB[3 * kMaxSeg + 1];
-#pragma unroll
-    for (int j = 0; j < 3 * kMaxSeg + 1; ++j) accA[j] = accB[j] = 0.f;
-    for (int t = lane; t < 2 * v.rows; t += NT) {
-        const int coord = t & 1, rr = t >> 1;
-        float acc[3 * kMaxSeg + 1];
-#pragma unroll
-        for (int j = 0; j < 3 * kMaxSeg + 1; ++j) acc[j] = 0.f;
-        for (int kk = 0; kk < K; ++kk) {
-            const float4 B = Bw[kk];
-            const int s = Bs[kk];
+    float *colsum = reinterpret_cast<float *>(Tm);      // [K][coord][3]
+    __syncthreads();   // every Xbar written, every T* read
+    for (int t = lane; t < 2 * K; t += NT) {
+        const int coord = t & 1, kk = t >> 1;
+        float sall = 0.f, sa = 0.f, sb = 0.f;
+        for (int rr = 0; rr < v.rows; ++rr) {
             const float2 xb2 = Xbar[rr * K + kk];
             const float xb = coord ? xb2.y : xb2.x;
-#pragma unroll
-            for (int s2 = 0; s2 < kMaxSeg; ++s2) {
-                if (s2 == s) {
-                    acc[3 * s2 + 0] += B.x * xb;
-                    acc[3 * s2 + 1] += B.y * xb;
-                    acc[3 * s2 + 2] += B.z * xb;
-                    acc[3 * s2 + 3] += B.w * xb;
-                }
-            }
+            const float tr = closed ? v.tau[rr] : 0.f;
+            sall += xb;
+            sa = fmaf(1.f - tr, xb, sa);
+            sb = fmaf(tr, xb, sb);
         }
-        const float tr = closed ? v.tau[rr] : 0.f;
-#pragma unroll
-        for (int jj = 0; jj < 3 * kMaxSeg + 1; ++jj) {
-            if (!closed || jj == 0 || jj == m) {
-                accA[jj] += acc[jj];
-            } else {
-                accA[jj] += (1.f - tr) * acc[jj];
-                accB[jj] += tr * acc[jj];
-            }
-        }
+        float *o = colsum + 3 * t;
+        o[0] = sall;
+        o[1] = sa;
+        o[2] = sb;
     }
-    __syncthreads();   // Xbar reads done before s_cp is written
-#pragma unroll
-    for (int jj = 0; jj < 3 * kMaxSeg + 1; ++jj) {
-        if (jj <= m) {
-            float sa = accA[jj], sb = accB[jj];
-#pragma unroll
-            for (int d = 32; d >= 2; d >>= 1) {
-                sa += __shfl_xor(sa, d, 64);
-                sb += __shfl_xor(sb, d, 64);
-            }
-            if ((lane & 63) < 2) {
-                s_cp[lane >> 6][0][jj][lane & 1] = sa;
-                s_cp[lane >> 6][1][jj][lane & 1] = sb;
-            }
+    __syncthreads();
+    for (int t = lane; t < 4 * (m + 1); t += NT) {
+        const int coord = t & 1, which = (t >> 1) & 1, jj = t >> 2;
+        // which 1 (B's interior points) exists only for closed curves
+        if (which == 1 && (!closed || jj == 0 || jj == m)) continue;
+        const int pick = !closed || jj == 0 || jj == m ? 0 : 1 + which;
+        float sum = 0.f;
+        for (int kk = 0; kk < K; ++kk) {
+            const int i = jj - 3 * Bs[kk];
+            if (i < 0 || i > 3) continue;
+            const float4 B = Bw[kk];
+            const float w = i == 0 ? B.x : i == 1 ? B.y : i == 2 ? B.z : B.w;
+            sum = fmaf(w, colsum[3 * (2 * kk + coord) + pick], sum);
         }
+        s_cp[which][jj][coord] = sum;
     }
     __syncthreads();
     const int nstore = closed ? 2 * m : m + 1;
@@ -936,9 +938,7 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
         const int coord = t & 1, j = t >> 1;
         const int which = j <= m ? 0 : 1;       // A (or open) points, then B's interior
         const int jj = j <= m ? j : j - m;
-        float sum = 0.f;
-        for (int wv = 0; wv < NT / 64; ++wv) sum += s_cp[wv][which][jj][coord];
-        out[t] = sum;
+        out[t] = s_cp[which][jj][coord];
     }
 }
 

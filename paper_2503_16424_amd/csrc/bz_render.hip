@@ -219,6 +219,12 @@ __device__ inline int opaque_zero() {
     return z;
 }
 
+// Clear bit b of a wave-uniform mask: one scalar instruction (the compiler's
+// mask & (mask - 1) or mask & ~(1 << b) take two or three).
+__device__ inline void clear_bit(uint64_t &mask, int b) {
+    asm("s_bitset0_b64 %0, %1" : "+s"(mask) : "s"(b));
+}
+
 // A wave-uniform float moved to a scalar register.
 __device__ inline float uniform_f32(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -269,7 +275,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
         wave_lds_sync();
         while (mask) {
             const int b = __builtin_ctzll(mask);
-            mask &= mask - 1;
+            clear_bit(mask, b);
             const Staged st = my[b];
             const float dx = lx - st.m.x;
             const float dy = ly - st.m.y;
@@ -641,7 +647,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                 }
                 if (mask != 0) {
                     const int b = 63 - __builtin_clzll(mask);
-                    mask &= ~(1ull << b);
+                    clear_bit(mask, b);
                     const Staged st = my[b];
                     const uint32_t pos = lo + (uint32_t)b;
                     const float dx = lx - st.m.x;
@@ -665,14 +671,15 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     const float f = shaped ? abar : 0.f;
                     // P = -dL/dp; the planes' constant factors (plane_scale)
                     // are applied to the sums after the reduction
-                    const float P = f * st.q.w * G;
+                    const float fG = f * G;
+                    const float P = fG * st.q.w;
                     const float Pdx = P * dx, Pdy = P * dy;
                     acc[9 * s + 0] = P * fmaf(st.q.x, dx, t1);          // d p2 / d dx
                     acc[9 * s + 1] = P * fmaf(st.q.y, dx, u + u);       // d p2 / d dy
                     acc[9 * s + 2] = Pdx * dx;
                     acc[9 * s + 3] = Pdx * dy;
                     acc[9 * s + 4] = Pdy * dy;
-                    acc[9 * s + 5] = f * (G - g_min);
+                    acc[9 * s + 5] = fmaf(-g_min, f, fG);        // f (G - g_min)
                     acc[9 * s + 6] = wgt * g0;
                     acc[9 * s + 7] = wgt * g1;
                     acc[9 * s + 8] = wgt * g2;

@@ -68,7 +68,7 @@ def parse():
                          "kernel to scale hardware byte counters against)")
     ap.add_argument("--no-learned-init", action="store_true",
                     help="skip the steps-to-PSNR measurement of the learned initialiser")
-    ap.add_argument("--cpu-rows", type=int, default=128,
+    ap.add_argument("--cpu-rows", type=int, default=1024,
                     help="rows of the frame the CPU oracle renders for its baseline")
     return ap.parse_args()
 

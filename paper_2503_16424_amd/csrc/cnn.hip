@@ -31,7 +31,12 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kLdsK = kBK + 8;          // row pitch in bf16 (80 bytes) against bank conflicts
-constexpr int kSplitRows = 1024;        // filter gradient: output pixels per workgroup
+// Filter gradient: output pixels per workgroup.  256 by default; 128 when
+// 256 would leave fewer than 512 workgroups (small late layers).  Measured on
+// the 256-patch training step: 1024 rows per workgroup ran the first layer's
+// 256 workgroups at one per CU (140 us), 128 rows made its 1,728 outputs
+// take too many float atomics (141 us); 256 gives 100 us.
+constexpr int kSplitRows = 256, kSplitRowsSmall = 128, kSplitMinGroups = 512;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -407,7 +412,8 @@ hipError_t launch_conv_bwd_weight(const bz_conv &c, const float *dy, const uint1
     g.dy = dy;
     g.x = x;
     g.out_f = dw;
-    g.k_chunk = kSplitRows;
+    const int64_t tiles = cdiv(g.M, kBM) * cdiv(g.N, kBN);
+    g.k_chunk = cdiv(g.K, kSplitRows) * tiles < kSplitMinGroups ? kSplitRowsSmall : kSplitRows;
     const int64_t nz = g.M * g.N;
     hipLaunchKernelGGL(k_fill0, dim3((unsigned)cdiv(nz, 256) < 4096 ? (unsigned)cdiv(nz, 256) : 4096),
                        dim3(256), 0, s, dw, nz);

@@ -6,7 +6,9 @@
 //   forward      m = output pixel, n = output channel, k = (dy, dx, in channel)
 //                A = shifted input pixels, B = filters
 //   input grad   m = input pixel,  n = in channel,     k = (dy, dx, out channel)
-//                A = the output gradients that pixel fed, B = filters
+//                A = the output gradients that pixel fed, B = filters; one GEMM
+//                per parity class of the input pixels modulo the stride, over
+//                the taps that reach that class only
 //   filter grad  m = out channel,  n = (dy, dx, in channel), k = output pixel
 //                A = output gradients, B = shifted input pixels
 //
@@ -95,7 +97,46 @@ struct GemmArgs {
     float *out_f;             // fwd y, bwd-data dx, bwd-weight dw
     uint16_t *out_b;          // fwd y in bf16
     int64_t k_chunk;          // bwd weight: k range per workgroup
+    // bwd data, one parity class: rows are the input pixels (iy, ix) with
+    // iy = cy, ix = cx (mod stride), hq x wq of them per image; only taps
+    // ky = ky0, kx = kx0 (mod stride) reach them, nkx of them along x
+    int cy, cx, hq, wq, ky0, kx0, nkx;
 };
+
+// Input pixel of class row m (input gradient).
+__device__ inline int64_t cls_pixel(const GemmArgs &g, int64_t m) {
+    if (g.S.s == 1) return m;                   // one class: every pixel
+    const int64_t hw = (int64_t)g.hq * g.wq;
+    const int64_t b = m / hw;
+    const int rem = (int)(m - b * hw);
+    const int qy = rem / g.wq, qx = rem - (rem / g.wq) * g.wq;
+    return (b * g.S.h + qy * g.S.s + g.cy) * g.S.w + qx * g.S.s + g.cx;
+}
+
+// Input gradient: the parity class of workgroup row z (cy = z / stride,
+// cx = z mod stride), its GEMM rows M and its k extent K.
+__device__ inline void set_class(GemmArgs &g, int z) {
+    const Shape &S = g.S;
+    const int st = S.s;
+    g.cy = z / st;
+    g.cx = z - (z / st) * st;
+    g.hq = g.cy < S.h ? (S.h - g.cy + st - 1) / st : 0;
+    g.wq = g.cx < S.w ? (S.w - g.cx + st - 1) / st : 0;
+    g.ky0 = (g.cy + S.p) % st;
+    g.kx0 = (g.cx + S.p) % st;
+    const int nky = g.ky0 < S.r ? (S.r - g.ky0 + st - 1) / st : 0;
+    const int nkx = g.kx0 < S.r ? (S.r - g.kx0 + st - 1) / st : 0;
+    g.nkx = nkx > 0 ? nkx : 1;                  // no taps: K = 0, the class gets zeros
+    g.M = (int64_t)S.n * g.hq * g.wq;
+    g.K = (int64_t)nky * nkx * S.k;
+}
+
+// Filter tap of the class's j-th (ky, kx) pair (input gradient).
+__device__ inline int cls_tap(const GemmArgs &g, int j) {
+    if (g.S.s == 1) return j;                   // one class: every tap
+    const int a = j / g.nkx, b = j - (j / g.nkx) * g.nkx;
+    return (g.ky0 + a * g.S.s) * g.S.r + g.kx0 + b * g.S.s;
+}
 
 // A[m][k .. k+7] and B[k .. k+7][n] for each mode (zeros outside the GEMM).
 template <int MODE>
@@ -112,8 +153,8 @@ __device__ inline void gather_a(const GemmArgs &g, int64_t m, int64_t k0, int64_
                 const int64_t px = in_pixel(S, m, tap);
                 if (px >= 0) u = g.x[px * S.c + ci];
             } else if (MODE == kBwdData) {
-                const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
-                const int64_t px = out_pixel(S, m, tap);
+                const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
+                const int64_t px = out_pixel(S, cls_pixel(g, m), cls_tap(g, j));
                 if (px >= 0) u = f_to_bf(g.dy[px * S.k + co]);
             } else {   // m = out channel, k = output pixel
                 u = f_to_bf(g.dy[k * S.k + m]);
@@ -136,8 +177,8 @@ __device__ inline void gather_b(const GemmArgs &g, int64_t n, int64_t k0, int64_
             if (MODE == kFwd) {
                 u = g.w[n * kf + k];
             } else if (MODE == kBwdData) {        // n = in channel, k = (tap, out channel)
-                const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
-                u = g.w[(int64_t)co * kf + (int64_t)tap * S.c + n];
+                const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
+                u = g.w[(int64_t)co * kf + (int64_t)cls_tap(g, j) * S.c + n];
             } else {                              // n = (tap, in channel), k = output pixel
                 const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
                 const int64_t px = in_pixel(S, k, tap);
@@ -193,8 +234,9 @@ __device__ inline void load_tiles(const GemmArgs &g, int64_t m0, int64_t n0, int
         for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
     } else if (MODE == kBwdData && VA) {
         const int64_t m = m0 + lrow, k = k0 + lk;
-        const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
-        const int64_t px = (m < g.M && k < kend) ? out_pixel(S, m, tap) : -1;
+        const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
+        const int64_t px =
+            (m < g.M && k < kend) ? out_pixel(S, cls_pixel(g, m), cls_tap(g, j)) : -1;
         load8_f32(g.dy + (px >= 0 ? px * S.k + co : 0), px >= 0, v);
 #pragma unroll
         for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
@@ -218,9 +260,9 @@ __device__ inline void load_tiles(const GemmArgs &g, int64_t m0, int64_t n0, int
         for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
     } else if (MODE == kBwdData && VB) {                // B[(tap, co)][ci] = w[co][tap][ci]
         const int64_t k = k0 + tk, n = n0 + tc;
-        const int tap = (int)(k / S.k), co = (int)(k - (int64_t)tap * S.k);
+        const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
         const bool ok = k < kend && n < g.N;
-        load8_bf16(g.w + (ok ? (int64_t)co * kf + (int64_t)tap * S.c + n : 0), ok, v);
+        load8_bf16(g.w + (ok ? (int64_t)co * kf + (int64_t)cls_tap(g, j) * S.c + n : 0), ok, v);
 #pragma unroll
         for (int j = 0; j < 8; ++j) sB[tc + j][tk] = v[j];
     } else if (MODE == kBwdWeight && VB) {              // B[pixel][(tap, ci)] = x[shifted pixel][ci]
@@ -238,11 +280,14 @@ __device__ inline void load_tiles(const GemmArgs &g, int64_t m0, int64_t n0, int
 }
 
 template <int MODE, bool VA, bool VB>
-__global__ __launch_bounds__(256) void k_igemm(GemmArgs g) {
+__global__ __launch_bounds__(256) void k_igemm(GemmArgs args) {
     __shared__ __align__(16) uint16_t sA[kBM][kLdsK];
     __shared__ __align__(16) uint16_t sB[kBN][kLdsK];
+    GemmArgs g = args;
+    if (MODE == kBwdData) set_class(g, (int)blockIdx.z);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * kBN;
+    if (m0 >= g.M) return;                            // this class has fewer rows
     int64_t kbeg = 0, kend = g.K;
     if (MODE == kBwdWeight) {
         kbeg = (int64_t)blockIdx.z * g.k_chunk;
@@ -291,8 +336,9 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs g) {
                     if (g.out_f) g.out_f[m * g.N + n] = v;
                     if (g.out_b) g.out_b[m * g.N + n] = f_to_bf(v);
                 } else if (MODE == kBwdData) {
-                    if (g.mask && !(bf_to_f(g.mask[m * g.N + n]) > 0.f)) v = 0.f;
-                    g.out_f[m * g.N + n] = v;
+                    const int64_t px = cls_pixel(g, m);
+                    if (g.mask && !(bf_to_f(g.mask[px * g.N + n]) > 0.f)) v = 0.f;
+                    g.out_f[px * g.N + n] = v;
                 } else {
                     atomicAdd(&g.out_f[m * g.N + n], v);
                 }
@@ -387,16 +433,20 @@ hipError_t launch_conv_fwd(const bz_conv &c, const uint16_t *x, const uint16_t *
 
 hipError_t launch_conv_bwd_data(const bz_conv &c, const float *dy, const uint16_t *w,
                                 const uint16_t *mask, float *dx, hipStream_t s) {
+    // One GEMM per parity class of the input pixels (stride^2 of them, one
+    // launch, blockIdx.z = class): a tap reaches input row iy only if
+    // iy + pad - ky is a multiple of the stride, so each class gathers only its
+    // own taps (for 3x3 stride 2: 1, 2, 2 or 4 of the 9) instead of zeros.
     GemmArgs g = {};
     g.S = shape_of(c);
-    g.M = (int64_t)c.n * c.h * c.w;
     g.N = c.c;
-    g.K = (int64_t)c.r * c.r * c.k;
     g.dy = dy;
     g.w = w;
     g.mask = mask;
     g.out_f = dx;
-    dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), 1);
+    const int st = c.stride;
+    const int64_t rows = (int64_t)c.n * ((c.h + st - 1) / st) * ((c.w + st - 1) / st);  // class 0
+    dim3 grid((unsigned)cdiv(rows, kBM), (unsigned)cdiv(g.N, kBN), (unsigned)(st * st));
     // A: 8 output channels of dy (k % 8); B: 8 input channels of a filter row (c % 8)
     launch_igemm<kBwdData>(g, c.k % 8 == 0, c.c % 8 == 0, grid, s);
     return hipGetLastError();

@@ -68,8 +68,9 @@ def parse():
                          "kernel to scale hardware byte counters against)")
     ap.add_argument("--no-learned-init", action="store_true",
                     help="skip the steps-to-PSNR measurement of the learned initialiser")
-    ap.add_argument("--cpu-rows", type=int, default=1024,
-                    help="rows of the frame the CPU oracle renders for its baseline")
+    ap.add_argument("--cpu-rows", type=int, default=2048,
+                    help="rows of the frame the CPU oracle renders for its baseline "
+                         "(default: the whole 2048-row frame)")
     return ap.parse_args()
 
 
@@ -93,13 +94,16 @@ def measured_traffic(kernel, workload, tw, th):
 
 
 def cpu_baseline(sc, target, rows):
-    """Time the FP64 oracle on a band of rows of the same workload and scale
-    to one full step (sampling and the per-curve chain are timed whole)."""
+    """Time the FP64 oracle on one step of the same workload: by default the
+    whole frame; with rows < height a band of rows whose forward+backward time
+    is scaled to the frame (an upper bound: the oracle's render has a per-call
+    cost that the scaling multiplies)."""
     import numpy as np
 
     import oracle
     oracle.build()
     H, W = sc.height, sc.width
+    rows = min(rows, H)
     y0 = H // 2 - rows // 2
     y1 = y0 + rows
     t0 = time.perf_counter()

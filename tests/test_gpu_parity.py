@@ -449,3 +449,19 @@ def test_stopping_pixels_match_oracle(torch_cuda, t_min, state):
         # the stored transmittance after each pixel's last contributor
         T = r.t_final.cpu().numpy()
         assert np.abs(T - o0["t_final"]).max() <= 1e-5
+
+
+def test_l2_gradient_and_loss_on_an_odd_sized_canvas(torch_cuda):
+    """131x77 canvas (30,261 values, not a multiple of the kernel's 4-wide
+    loads): d_image and the summed squared error against numpy."""
+    import torch
+    sc = SCENES["mixed_small_b"]()
+    r = _rast(sc)
+    img = r.render().cpu().numpy().astype(np.float64)
+    tgt = scenes.target_noise(4, sc.width, sc.height)
+    r.l2_grad(torch.as_tensor(tgt, device="cuda"))
+    torch.cuda.synchronize()
+    e = img - tgt.astype(np.float64)
+    assert img.size % 4 != 0
+    assert np.abs(r.d_image.cpu().numpy() - 2.0 * e / img.size).max() <= 1e-9
+    assert abs(r.loss.item() - float(np.sum(e * e))) <= 1e-5 * float(np.sum(e * e))

@@ -6,10 +6,18 @@
 // high part and a float low part; squared scales from the neighbour distances
 // of Eq. sigma plus the dilation sigma0^2; Q = Sigma^-1 from the unit tangent
 // of Eq. rotation (Eq. RSSR with R = [c -s; s c], S = diag(sx, sy)).  Records
-// of one curve are contiguous, so the stores of a wave are coalesced.
+// of one curve are contiguous; a wave stages its 64 records of a round in LDS
+// and writes them as three contiguous 1 KB stores.
 #include "bz_geom.h"
 
 namespace bz {
+
+// Wave-level barrier with LDS ordering (the wave's own slice only).
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double inv_rho2, double s0,
                                                float4 *__restrict__ rec) {
@@ -29,21 +37,36 @@ __global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double in
     const float *opa = c.opacity + c.opa_off[v.id];
     const float cid = __int_as_float(v.id);
     const int n = v.rows * v.K;
-    for (int idx = lane; idx < n; idx += kCurveThreads) {
-        int r = idx / v.K, k = idx - r * v.K;
-        Geom g;
-        gauss_geom(v, XA, XB, r, k, inv_rho2, s0, g);
-        double a = 1.0 / g.sx2, b = 1.0 / g.sy2;
-        double qxx = g.cs * g.cs * a + g.sn * g.sn * b;
-        double qxy = g.cs * g.sn * (a - b);
-        double qyy = g.sn * g.sn * a + g.cs * g.cs * b;
-        float hx = (float)g.mu.x, hy = (float)g.mu.y;
-        float lx = (float)(g.mu.x - (double)hx), ly = (float)(g.mu.y - (double)hy);
-        float o = opa[v.nopa == v.S ? g.seg : 0];
-        int64_t gi = v.g0 + idx;
-        rec[3 * gi + 0] = make_float4(hx, hy, lx, ly);
-        rec[3 * gi + 1] = make_float4((float)qxx, (float)qxy, (float)qyy, o);
-        rec[3 * gi + 2] = make_float4(cr, cg, cb, cid);
+    // A wave emits 64 consecutive Gaussians per round: their 48-byte records
+    // meet in the wave's LDS slice and leave as three 1 KB contiguous stores
+    // (written straight, lane l's three 16-byte pieces would be 48 bytes apart).
+    __shared__ float4 s_rec[kCurveThreads / 64][3 * 64];
+    const int w = lane >> 6, l = lane & 63;
+    float4 *my = s_rec[w];
+    for (int base = 64 * w; base < n; base += kCurveThreads) {
+        const int idx = base + l;
+        if (idx < n) {
+            int r = idx / v.K, k = idx - r * v.K;
+            Geom g;
+            gauss_geom(v, XA, XB, r, k, inv_rho2, s0, g);
+            double a = 1.0 / g.sx2, b = 1.0 / g.sy2;
+            double qxx = g.cs * g.cs * a + g.sn * g.sn * b;
+            double qxy = g.cs * g.sn * (a - b);
+            double qyy = g.sn * g.sn * a + g.cs * g.cs * b;
+            float hx = (float)g.mu.x, hy = (float)g.mu.y;
+            float lx = (float)(g.mu.x - (double)hx), ly = (float)(g.mu.y - (double)hy);
+            float o = opa[v.nopa == v.S ? g.seg : 0];
+            my[3 * l + 0] = make_float4(hx, hy, lx, ly);
+            my[3 * l + 1] = make_float4((float)qxx, (float)qxy, (float)qyy, o);
+            my[3 * l + 2] = make_float4(cr, cg, cb, cid);
+        }
+        wave_sync_lds();
+        const int valid = 3 * (n - base < 64 ? n - base : 64);   // float4s of this round
+        float4 *out = rec + 3 * (v.g0 + base);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j * 64 + l < valid) out[j * 64 + l] = my[j * 64 + l];
+        wave_sync_lds();
     }
 }
 

@@ -9,15 +9,18 @@
 // A ballot of the test gives the batch's mask; the wave then iterates only
 // over the surviving entries, reading each one's constants as an LDS
 // broadcast, so pixels never spend ALU on Gaussians that cannot reach their
-// quad.  A wave stops when all 64 of its pixels have terminated.
+// quad.  A wave stops when all 64 of its pixels have terminated.  (In the
+// backward the quads of a tile also share a sum table in LDS, so its waves
+// meet at the tile's start and end.)
 //
 // Blocks are mapped to tiles XCD-contiguously: the dispatcher deals blocks
 // round robin to the 8 XCDs, so block b serves tile (b % 8) * per + b / 8 and
 // each XCD's L2 sees a compact band of neighbouring tiles, which share most
 // of their Gaussians.
 //
-// Stage 2 of the backward pass is per curve (one wave per curve, no atomics):
-// it chains the per-Gaussian gradients through the sampling of Sec. 3.3.
+// Stage 2 of the backward pass is per curve (one 256-thread workgroup per
+// curve, no atomics): it chains the per-Gaussian gradients through the
+// sampling of Sec. 3.3.
 #include "bz_geom.h"
 
 namespace bz {
@@ -489,13 +492,15 @@ constexpr int kTableCap = 512;
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
 // its pixels used down to the first.  Per pixel and contributor (reverse
 // order): T before it = T after / (1 - alpha); colour gradient alpha T g;
-// alpha gradient T sum_ch (c - A) g with A the colour composited behind it
-// (starts at the background, A <- alpha c + (1 - alpha) A); then, unless alpha
-// was clamped, the opacity gradient and dL/dp = -alpha_bar o' G, which gives
-// the mean gradient -dL/dp Q d and the conic gradient dL/dp (dx^2/2, dx dy,
-// dy^2/2).  The nine per-lane values of seven Gaussians are summed over the
-// wave in one transposed reduction and added to the per-Gaussian planes with
-// one 63-lane atomic instruction.
+// alpha gradient T (c - A) . g with A the colour composited behind it (starts
+// at the background, A <- alpha c + (1 - alpha) A; only A . g is carried);
+// then, unless alpha was clamped, the opacity gradient and dL/dp = -alpha_bar
+// o' G, which gives the mean gradient -dL/dp Q d and the conic gradient dL/dp
+// (dx^2/2, dx dy, dy^2/2).  The nine per-lane values of seven Gaussians are
+// summed over the wave in one transposed reduction and added, with one
+// 63-lane atomic instruction, to the tile's LDS sum table (positions below
+// its capacity) or straight to the per-Gaussian planes in HBM; the table is
+// added to the planes when the tile is done.
 //
 // kRecompute: the blend state (T after the last contributor, the bound on its position and
 // the per-batch contribution masks) is not read from memory but recomputed by

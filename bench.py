@@ -311,7 +311,7 @@ def bench_batched(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         return 2
     if a.workload == "batched_64":

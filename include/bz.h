@@ -44,7 +44,7 @@ typedef enum {
     BZ_ERR_ARG = -1,          /* invalid argument (null pointer, bad size, bad option) */
     BZ_ERR_CAPACITY = -2,     /* a host-known size exceeds a caller buffer */
     BZ_ERR_HIP = -3,          /* kernel launch failed */
-    BZ_ERR_UNSUPPORTED = -4   /* valid but outside what this build handles */
+    BZ_ERR_UNSUPPORTED = -4   /* valid but outside what the library supports */
 } bz_status;
 
 /* Kind of a curve (Sec. 3.2). */

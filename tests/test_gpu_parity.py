@@ -465,3 +465,40 @@ def test_l2_gradient_and_loss_on_an_odd_sized_canvas(torch_cuda):
     assert img.size % 4 != 0
     assert np.abs(r.d_image.cpu().numpy() - 2.0 * e / img.size).max() <= 1e-9
     assert abs(r.loss.item() - float(np.sum(e * e))) <= 1e-5 * float(np.sum(e * e))
+
+
+def test_non_finite_curve_is_skipped_and_flagged(torch_cuda):
+    """A NaN control point makes its curve's Gaussians non-finite: binning
+    skips them and raises the status bit; the image and every other curve's
+    gradients are those of the scene with that curve fully transparent."""
+    import torch
+    from paper_2503_16424_amd import bz
+    sc = SCENES["mixed_small_b"]()
+    bad = 3
+    s_nan = sc.copy()
+    pts = np.array(s_nan.ctrl, copy=True)
+    pts[int(s_nan.ctrl_off[bad])] = np.nan
+    s_nan.ctrl = pts
+    s_ref = sc.copy()
+    op = np.array(s_ref.opacity, copy=True)
+    op[int(s_ref.opa_off[bad]):int(s_ref.opa_off[bad + 1])] = 0.0
+    s_ref.opacity = op
+    r = _rast(s_nan)
+    img = r.render().cpu().numpy()
+    assert r.flags() & bz.STATUS_NONFINITE
+    o0 = oracle.forward_backward(s_ref)
+    assert np.abs(img - o0["image"]).max() <= IMG_TOL
+    dimg = _upstream(s_ref, o0["image"])
+    o = oracle.forward_backward(s_ref, dimg.astype(np.float64))
+    r.backward(torch.as_tensor(dimg, device="cuda"))
+    torch.cuda.synchronize()
+    keep = np.arange(sc.n_curves) != bad
+    pts_keep = np.ones(sc.ctrl.shape[0], bool)
+    pts_keep[int(sc.ctrl_off[bad]):int(sc.ctrl_off[bad + 1])] = False
+    opa_keep = np.ones(sc.opacity.shape[0], bool)
+    opa_keep[int(sc.opa_off[bad]):int(sc.opa_off[bad + 1])] = False
+    for k, sel in (("d_ctrl", pts_keep), ("d_color", keep), ("d_width", keep),
+                   ("d_opacity", opa_keep)):
+        got = getattr(r, k).cpu().numpy()[sel]
+        assert np.all(np.isfinite(got)), k
+        assert rel_l2(got, o[k][sel]) <= GRAD_TOL, k

@@ -26,6 +26,10 @@ constexpr int kMaxSeg = 4;
 // Threads of the per-curve kernels (one workgroup per curve).
 constexpr int kCurveThreads = 256;
 
+// Curves of at most this many Gaussians run the per-curve backward as one-wave
+// workgroups.
+constexpr int kSmallCurve = 64;
+
 // log2(e)
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -118,10 +122,10 @@ __host__ __device__ inline int batch_find(const bz_canvas *cv, int n_canvas, int
 }
 
 // LDS of the per-curve backward: boundary samples (2 x double2 per column),
-// Bernstein weights and segment per column, sample-point gradients and the
-// four per-Gaussian stencil terms (float2 each).
+// Bernstein weights and segment per column, and the four per-Gaussian stencil
+// terms (float2 each; the sample-point gradients overwrite the first).
 inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
-    return 2 * 16 * max_k + 16 * max_k + 4 * max_k + 5 * 8 * max_gauss;
+    return 2 * 16 * max_k + 16 * max_k + 4 * max_k + 4 * 8 * max_gauss;
 }
 
 // Visit masks: one plane per 8x8 quad of a tile; a plane holds, for every tile,

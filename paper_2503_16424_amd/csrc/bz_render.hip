@@ -746,32 +746,40 @@ __global__ void k_zero(float *p, int64_t n) {
 // to the control points: X[r][k] = sum_j B_j(t_k) ((1-tau_r) A_{3s+j} + tau_r B_{3s+j}).
 // Sample points and their differences are double precision (coordinates of
 // thousands of pixels, differences of a pixel); the chain itself is float.
-__global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, double inv_rho2,
-                                                              double s0,
-                                                              const float *__restrict__ d_gauss,
-                                                              int64_t ng, float *__restrict__ d_ctrl,
-                                                              float *__restrict__ d_width,
-                                                              float *__restrict__ d_color,
-                                                              float *__restrict__ d_opacity) {
+//
+// NT threads per curve.  Two launches split the curves by size: those of at
+// most kSmallCurve Gaussians (open strokes) run as one-wave workgroups with
+// LDS sized for them, the others with kCurveThreads threads; each launch
+// skips the other's curves.  lk and lg are the K and Gaussian capacities the
+// dynamic LDS is laid out for.
+// Eight waves per SIMD (64 VGPRs, a few spills outside the per-Gaussian
+// loop): the stage waits on latency, and at seven it ran 5% slower.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_bwd_curves(bz_curves c, int lk, int lg, double inv_rho2,
+                                                   double s0, const float *__restrict__ d_gauss,
+                                                   int64_t ng, float *__restrict__ d_ctrl,
+                                                   float *__restrict__ d_width,
+                                                   float *__restrict__ d_color,
+                                                   float *__restrict__ d_opacity) {
     extern __shared__ double2 lds_xy[];
     __shared__ float s_tau[256];
-    __shared__ float s_red[kCurveThreads / 64][8];
+    __shared__ float s_red[NT / 64][8];
     __shared__ float s_cp[2][3 * kMaxSeg + 1][2];
-    constexpr int NT = kCurveThreads;
     const int p = blockIdx.x;
+    const bool small = c.gauss_off[p + 1] - c.gauss_off[p] <= kSmallCurve;
+    if (small != (NT == kWave)) return;   // the other launch's curve
     const int lane = threadIdx.x;          // thread of the curve's workgroup
     CurveView v = load_curve_view(c, p);
     stage_tau(v, s_tau, lane, NT);
-    const int mg = c.max_gauss_per_curve;
     double2 *XA = lds_xy;
-    double2 *XB = lds_xy + c.max_k;
-    float4 *Bw = reinterpret_cast<float4 *>(lds_xy + 2 * c.max_k);     // [K] Bernstein weights
-    int *Bs = reinterpret_cast<int *>(Bw + c.max_k);                   // [K] segment of column k
-    float2 *Xbar = reinterpret_cast<float2 *>(Bs + c.max_k);           // [rows*K]
-    float2 *Tm = Xbar + mg;                                            // mean term
-    float2 *Tf = Tm + mg;                                              // along-row term
-    float2 *Th = Tf + mg;                                              // across-row term
-    float2 *Tv = Th + mg;                                              // tangent term
+    double2 *XB = lds_xy + lk;
+    float4 *Bw = reinterpret_cast<float4 *>(lds_xy + 2 * lk);          // [K] Bernstein weights
+    int *Bs = reinterpret_cast<int *>(Bw + lk);                        // [K] segment of column k
+    float2 *Tm = reinterpret_cast<float2 *>(Bs + lk);                  // mean term, then Xbar
+    float2 *Tf = Tm + lg;                                              // along-row term
+    float2 *Th = Tf + lg;                                              // across-row term
+    float2 *Tv = Th + lg;                                              // tangent term
+    float2 *Xbar = Tm;                                                 // [rows*K]
     boundary_samples(v, XA, XB, lane, NT);
     for (int k = lane; k < v.K; k += NT) {
         int s;
@@ -789,8 +797,10 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
     const float rho2f = (float)inv_rho2;
     const bool closed = v.kind == BZ_CLOSED;
     const int K = v.K, R1 = v.R + 1;
-    for (int idx = lane; idx < n; idx += NT) {
-        const int r = idx / K, k = idx - r * K;
+    // (r, k) of idx = lane + i*NT advance by (NT / K, NT % K) per pass.
+    const int rstep = NT / K, kstep = NT - rstep * K;
+    const int r0 = lane / K, k0 = lane - r0 * K;
+    for (int idx = lane, r = r0, k = k0; idx < n; idx += NT) {
         float dg[kGradPlanes];
 #pragma unroll
         for (int q = 0; q < kGradPlanes; ++q) dg[q] = d_gauss[q * ng + v.g0 + idx];
@@ -844,6 +854,9 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
         cb0 += dg[6];
         cb1 += dg[7];
         cb2 += dg[8];
+        k += kstep;
+        r += rstep;
+        if (k >= K) { k -= K; ++r; }
     }
     __syncthreads();
     // Gather: the terms each sample point (r, k) receives.
@@ -853,10 +866,10 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
     //         -Tv(j) where km(j) = k: j = k+1 (k < K-1), and j = 0 when k = 0
     //  across +Th(i) where ra(i) = r: i = r-1 (r >= 1), and i = R+1 when r = R+1
     //         -Th(i) where rb(i) = r: i = r (r <= R), and i = R+1 when r = R
-    for (int idx = lane; idx < n; idx += NT) {
-        const int r = idx / K, k = idx - r * K;
-        const int row = r * K;
-        float2 x = Tm[idx];
+    // Xbar overwrites Tm in place: a point reads only its own mean term.
+    for (int idx = lane, r = r0, k = k0; idx < n; idx += NT) {
+        const int row = idx - k;
+        const float2 x = Tm[idx];
         float ax = 0.f, ay = 0.f;
         if (k >= 1) { ax += Tf[row + k - 1].x + Tv[row + k - 1].x; ay += Tf[row + k - 1].y + Tv[row + k - 1].y; }
         if (k == K - 1) { ax += Tf[row + K - 1].x + Tv[row + K - 1].x; ay += Tf[row + K - 1].y + Tv[row + K - 1].y; }
@@ -870,6 +883,9 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
             if (r == R1 - 1) { ax -= Th[idx + K].x; ay -= Th[idx + K].y; }
         }
         Xbar[idx] = make_float2(x.x + ax, x.y + ay);
+        k += kstep;
+        r += rstep;
+        if (k >= K) { k -= K; ++r; }
     }
 
     // per-curve sums: wave reduction, then across the workgroup's waves
@@ -906,10 +922,11 @@ __global__ __launch_bounds__(kCurveThreads) void k_bwd_curves(bz_curves c, doubl
     // column k of Xbar over the rows three ways: all rows (open curves and the
     // endpoints a closed curve's boundaries share), weighted by 1 - tau_r (A's
     // interior points) and by tau_r (B's interior points); the sums go to LDS
-    // (the T* terms are dead by now).  (2) Thread (point jj, coord, boundary)
-    // adds B_{jj - 3 s_k}(t_k) times those sums over the columns k in order.
+    // over Tf..Tv (dead by now; 24 K bytes fit in their 24 rows*K).  (2) Thread
+    // (point jj, coord, boundary) adds B_{jj - 3 s_k}(t_k) times those sums
+    // over the columns k in order.
     const int m = 3 * v.S;
-    float *colsum = reinterpret_cast<float *>(Tm);      // [K][coord][3]
+    float *colsum = reinterpret_cast<float *>(Tf);      // [K][coord][3]
     __syncthreads();   // every Xbar written, every T* read
     for (int t = lane; t < 2 * K; t += NT) {
         const int coord = t & 1, kk = t >> 1;
@@ -1110,13 +1127,20 @@ hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
 
 hipError_t launch_bwd_curves(const bz_curves &c, const bz_opts &o, const float *d_gauss,
                              const bz_grads &gr, hipStream_t s) {
-    if (c.n_curves > 0) {
-        size_t lds2 = stage2_lds_bytes(c.max_k, c.max_gauss_per_curve);
-        double rho = (double)o.rho;
-        hipLaunchKernelGGL(k_bwd_curves, dim3(c.n_curves), dim3(kCurveThreads), lds2, s, c,
-                           1.0 / (rho * rho), (double)o.sigma0_sq, d_gauss, c.n_gauss, gr.d_ctrl,
-                           gr.d_width, gr.d_color, gr.d_opacity);
+    if (c.n_curves == 0) return hipSuccess;
+    const double rho = (double)o.rho, inv_rho2 = 1.0 / (rho * rho), s0 = (double)o.sigma0_sq;
+    if (c.max_gauss_per_curve > kSmallCurve) {
+        const size_t lds = stage2_lds_bytes(c.max_k, c.max_gauss_per_curve);
+        hipLaunchKernelGGL(k_bwd_curves<kCurveThreads>, dim3(c.n_curves), dim3(kCurveThreads),
+                           lds, s, c, c.max_k, c.max_gauss_per_curve, inv_rho2, s0, d_gauss,
+                           c.n_gauss, gr.d_ctrl, gr.d_width, gr.d_color, gr.d_opacity);
     }
+    // a small curve has K <= its Gaussian count <= kSmallCurve
+    const int lk = c.max_k < kSmallCurve ? c.max_k : kSmallCurve;
+    const int lg = c.max_gauss_per_curve < kSmallCurve ? c.max_gauss_per_curve : kSmallCurve;
+    hipLaunchKernelGGL(k_bwd_curves<kWave>, dim3(c.n_curves), dim3(kWave), stage2_lds_bytes(lk, lg),
+                       s, c, lk, lg, inv_rho2, s0, d_gauss, c.n_gauss, gr.d_ctrl, gr.d_width,
+                       gr.d_color, gr.d_opacity);
     return hipGetLastError();
 }
 

@@ -80,6 +80,43 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
+def _lens(S, c, L, h):
+    """Control points of an S-segment closed curve: boundary A (3S+1 points)
+    bowed down by h/2 around centre c, then B's 3S-1 interior points a
+    height h above A's straight chord."""
+    import numpy as np
+    A = [c + np.array([(-0.5 + j / (3 * S)) * L, 0.0]) for j in range(3 * S + 1)]
+    B = [c + np.array([(-0.5 + j / (3 * S)) * L, h]) for j in range(1, 3 * S)]
+    A = [a + np.array([0.0, -0.5 * h * np.sin(np.pi * j / (3 * S))]) for j, a in enumerate(A)]
+    return np.array(A + B)
+
+
+def size_split_scene(W=120, H=96):
+    """Curves on both sides of the per-curve kernels' split at 64 Gaussians,
+    interleaved in draw order: open strokes of K = 63, 64, 65 and closed
+    curves of K*(R+2) = 63 (21x3), 64 (16x4, 32x2, 2x32), 65 (13x5) and 96."""
+    import numpy as np
+    from paper_2503_16424_amd import scenes
+    rng = np.random.default_rng(2024)
+    # (kind, S, K, R): 0 open, 1 closed
+    spec = [(0, 2, 63, 0), (1, 1, 16, 2), (0, 1, 64, 0), (1, 2, 13, 3), (0, 3, 65, 0),
+            (1, 1, 21, 1), (1, 2, 32, 0), (1, 1, 2, 30), (0, 1, 24, 0), (1, 3, 24, 2)]
+    kinds, nsegs, ks, rs, ctrl, widths, opa = [], [], [], [], [], [], []
+    for kind, S, K, R in spec:
+        kinds.append(kind); nsegs.append(S); ks.append(K); rs.append(R)
+        if kind == 0:
+            ctrl.append(rng.uniform([4, 4], [W - 4, H - 4], (3 * S + 1, 2)))
+            widths.append(rng.uniform(1.0, 3.0))
+        else:
+            c = rng.uniform([25, 25], [W - 25, H - 25])
+            ctrl.append(_lens(S, c, rng.uniform(16.0, 40.0), rng.uniform(6.0, 16.0)))
+            widths.append(0.0)
+        opa.append(rng.uniform(0.4, 0.95, S if S > 1 and rng.uniform() < 0.5 else 1))
+    rank = rng.permutation(len(spec))
+    return scenes._assemble(W, H, kinds, nsegs, ks, rs, ctrl, widths,
+                            rng.uniform(0, 1, (len(spec), 3)), opa, rank, name="size-split")
+
+
 def max_size_scene(W=96, H=80):
     """Curves at the per-curve limits: a 4-segment stroke of K = 1024 samples,
     a 4-segment closed curve of R = 254 interior rows (K = 8), and a closed
@@ -89,12 +126,8 @@ def max_size_scene(W=96, H=80):
     from paper_2503_16424_amd import scenes
     rng = np.random.default_rng(99)
     stroke = rng.uniform([5, 5], [W - 5, H - 5], (13, 2))
-    def lens(S, c, L, h):
-        A = [c + np.array([(-0.5 + j / (3 * S)) * L, 0.0]) for j in range(3 * S + 1)]
-        B = [c + np.array([(-0.5 + j / (3 * S)) * L, h]) for j in range(1, 3 * S)]
-        A = [a + np.array([0.0, -0.5 * h * np.sin(np.pi * j / (3 * S))]) for j, a in enumerate(A)]
-        return np.array(A + B)
-    ctrl = [stroke, lens(4, np.array([40.0, 40.0]), 60.0, 20.0), lens(1, np.array([60.0, 30.0]), 30.0, 12.0)]
+    ctrl = [stroke, _lens(4, np.array([40.0, 40.0]), 60.0, 20.0),
+            _lens(1, np.array([60.0, 30.0]), 30.0, 12.0)]
     return scenes._assemble(W, H, [0, 1, 1], [4, 4, 1], [1024, 8, 60], [0, 254, 30], ctrl,
                             [2.0, 0.0, 0.0], rng.uniform(0, 1, (3, 3)),
                             [[0.6, 0.9, 0.4, 0.8], [0.7], [0.5]], [2, 0, 1])

@@ -152,10 +152,12 @@ def test_forward_bitwise_across_tile_shapes_and_runs(torch_cuda):
 
 
 @pytest.mark.parametrize("state", ["stored", "recompute"])
-@pytest.mark.parametrize("name", list(SCENES) + ["dense_tile"])
+@pytest.mark.parametrize("name", list(SCENES) + ["dense_tile", "size_split"])
 def test_backward_matches_oracle(torch_cuda, name, state):
     import torch
-    sc = SCENES[name]() if name in SCENES else _dense_tile_scene()
+    from tests.helpers import size_split_scene
+    sc = (SCENES[name]() if name in SCENES else
+          size_split_scene() if name == "size_split" else _dense_tile_scene())
     _note(f"backward parity {name} n_gauss={sc.n_gauss} blend state {state}")
     o0 = oracle.forward_backward(sc)
     dimg = _upstream(sc, o0["image"])

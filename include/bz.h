@@ -12,6 +12,8 @@
  *   bz_render_fwd  per-tile front-to-back alpha blending     (Sec. 3.4, blending sum)
  *   bz_render_bwd  reverse-order gradients to Gaussians, then to curve
  *                  control points, widths, colours, opacities
+ *   bz_l2_grad     the L2 loss gradient of an image          (Sec. 3.5); also fused
+ *                  into the forward as bz_render_fwd_l2
  *
  * Conventions shared by every call:
  *  - Pointers inside the structs and the image/gradient pointers are DEVICE
@@ -266,6 +268,18 @@ bz_status bz_bin(const bz_gaussians *g, const bz_opts *opts, bz_bins *b, hipStre
  * t_final, n_last (and optionally n_contrib) for bz_render_bwd, or NULL. */
 bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *opts,
                         float *image, bz_pixstate *state, hipStream_t stream);
+
+/* bz_render_fwd and bz_l2_grad on its image in one pass (Sec. 3.4 blending,
+ * Sec. 3.5 L2 term).  image and state come out exactly as bz_render_fwd writes
+ * them; as each pixel is written, d_image = scale*(image - target) for its
+ * three channels (bit for bit what bz_l2_grad writes), and loss[0] = sum of
+ * (image - target)^2 over all pixels and channels (zeroed by the call; may be
+ * NULL; the order of its float additions differs from bz_l2_grad's).  target
+ * and d_image have the layout of image ([3][H][W], or a batch's canvases one
+ * after another); d_image may be target itself but not image (BZ_ERR_ARG). */
+bz_status bz_render_fwd_l2(const bz_gaussians *g, const bz_bins *b, const bz_opts *opts,
+                           float *image, bz_pixstate *state, const float *target, float scale,
+                           float *d_image, float *loss, hipStream_t stream);
 
 /* Reverse pass.  Stage 1, per pixel, walks the contributors of the forward
  * pass last to first, recovering T before each one by division by (1 - alpha)

@@ -73,7 +73,7 @@ class Grads(C.Structure):
 
 EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_batch_layout",
            "bz_visit_words", "bz_sample", "bz_bin",
-           "bz_render_fwd", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
+           "bz_render_fwd", "bz_render_fwd_l2", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
            "bz_curve_area", "bz_area_order_workspace", "bz_area_order", "bz_xing_loss",
            "bz_l2_grad", "bz_status_str")
 
@@ -110,6 +110,9 @@ def load_library(path: str = LIB_PATH):
     lib.bz_render_fwd.restype = C.c_int
     lib.bz_render_fwd.argtypes = [P(Gaussians), P(Bins), P(Opts), C.c_void_p, P(PixState),
                                   C.c_void_p]
+    lib.bz_render_fwd_l2.restype = C.c_int
+    lib.bz_render_fwd_l2.argtypes = [P(Gaussians), P(Bins), P(Opts), C.c_void_p, P(PixState),
+                                     C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.bz_render_bwd.restype = C.c_int
     lib.bz_render_bwd.argtypes = [P(Curves), P(Gaussians), P(Bins), P(Opts), C.c_void_p,
                                   P(PixState), P(Grads), C.c_void_p]
@@ -466,6 +469,17 @@ class Rasterizer:
         _check("bz_l2_grad", self.lib.bz_l2_grad(_ptr(self.image), _ptr(target), n, C.c_float(s),
                                                  _ptr(self.d_image), _ptr(self.loss), _stream()))
 
+    def forward_l2(self, target, scale=None):
+        """forward and l2_grad in one pass: the image and blend state of
+        ``forward``, ``d_image`` bit for bit as ``l2_grad`` writes it, ``loss``
+        summed in another order."""
+        s = 2.0 / (3 * self._hw) if scale is None else scale
+        _check("bz_render_fwd_l2", self.lib.bz_render_fwd_l2(
+            C.byref(self.gauss), C.byref(self.bins), C.byref(self.opts), _ptr(self.image),
+            self._state_arg(), _ptr(target), C.c_float(s), _ptr(self.d_image), _ptr(self.loss),
+            _stream()))
+        return self.image
+
     def render(self):
         """sample + bin + forward, growing the pair buffer when needed (synchronises)."""
         self.sample()
@@ -478,8 +492,7 @@ class Rasterizer:
         """One fwd+bwd of the mean squared error against ``target`` (no sync)."""
         self.sample()
         self.bin()
-        self.forward()
-        self.l2_grad(target)
+        self.forward_l2(target)
         self.backward()
 
     # -- host views --------------------------------------------------------------

@@ -246,7 +246,23 @@ bz_status bz_render_fwd(const bz_gaussians *g, const bz_bins *b, const bz_opts *
     if ((st = check_state(state, o, b)) != BZ_OK) return st;
     if ((st = check_persistent(b, o)) != BZ_OK) return st;
     (void)hipGetLastError();
-    return launched(launch_fwd(g->rec, *b, *o, image, state, s));
+    return launched(launch_fwd(g->rec, *b, *o, image, state, nullptr, s));
+}
+
+bz_status bz_render_fwd_l2(const bz_gaussians *g, const bz_bins *b, const bz_opts *o, float *image,
+                           bz_pixstate *state, const float *target, float scale, float *d_image,
+                           float *loss, hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if (!g || g->n < 0 || (g->n > 0 && !g->rec)) return BZ_ERR_ARG;
+    if ((st = check_bins(b, o, g->n, false)) != BZ_OK) return st;
+    if (!image || !target || !d_image || d_image == image) return BZ_ERR_ARG;
+    if (!isfinite(scale)) return BZ_ERR_ARG;
+    if ((st = check_state(state, o, b)) != BZ_OK) return st;
+    if ((st = check_persistent(b, o)) != BZ_OK) return st;
+    (void)hipGetLastError();
+    const L2Out l2 = {target, d_image, loss, scale};
+    return launched(launch_fwd(g->rec, *b, *o, image, state, &l2, s));
 }
 
 bz_status bz_render_bwd_gauss(const bz_gaussians *g, const bz_bins *b, const bz_opts *o,

@@ -51,10 +51,17 @@ struct Status {
 hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipStream_t s);
 hipError_t launch_bin(const float *rec, int64_t n_gauss, const bz_opts &o, const bz_bins &b,
                       hipStream_t s);
+// The L2 loss gradient the forward can write with the image (loss may be null).
+struct L2Out {
+    const float *target;
+    float *d_image;
+    float *loss;
+    float scale;
+};
 // st == nullptr: the forward writes only the image; the backward recomputes
-// the blend state per tile.
+// the blend state per tile.  l2 == nullptr: no loss gradient.
 hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
-                      const bz_pixstate *st, hipStream_t s);
+                      const bz_pixstate *st, const L2Out *l2, hipStream_t s);
 hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
                             const bz_opts &o, const float *d_image, const bz_pixstate *st,
                             float *d_gauss, hipStream_t s);

@@ -84,6 +84,11 @@ struct TileArgs {
     const float *d_image;
     float *d_gauss;
     int64_t n_gauss;
+    // forward with the L2 loss gradient: target, d_image out, loss sum, scale
+    const float *l2_target;
+    float *l2_grad;
+    float *l2_loss;
+    float l2_scale;
 };
 
 // Entry of the wave's LDS slice: the mean, log2-scaled half conic and the
@@ -317,9 +322,11 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
 
 // Forward pass.  With kState the blend state the backward reads is written:
 // T after the last contributor, a bound on its position, and per (quad, batch) the mask
-// of entries that contributed; without it only the image.
-template <bool kState, bool kCount>
-__device__ inline void fwd_tile(const TileArgs &a, int tile) {
+// of entries that contributed; without it only the image.  With kL2, as each
+// pixel is written, also the L2 loss gradient scale * (image - target) (the
+// same float arithmetic as k_l2) and the lane's sum of squared errors in l2.
+template <bool kState, bool kCount, bool kL2>
+__device__ inline void fwd_tile(const TileArgs &a, int tile, float &l2) {
     extern __shared__ Staged s_stage[];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -343,6 +350,13 @@ __device__ inline void fwd_tile(const TileArgs &a, int tile) {
             img[pix] = nan;
             img[plane + pix] = nan;
             img[2 * plane + pix] = nan;
+            if (kL2) {
+                float *dimg = a.l2_grad + 2 * tg.pix0;
+                dimg[pix] = nan;
+                dimg[plane + pix] = nan;
+                dimg[2 * plane + pix] = nan;
+                l2 = nan;
+            }
             if (kState) {
                 a.t_final[pix] = nan;
                 a.n_last[pix] = 0;
@@ -359,9 +373,21 @@ __device__ inline void fwd_tile(const TileArgs &a, int tile) {
                                                 if (kState && lane == 0) vis[k] = bits;
                                             });
     if (valid) {
-        img[pix] = fmaf(r.T, tg.bg0, r.C0);
-        img[plane + pix] = fmaf(r.T, tg.bg1, r.C1);
-        img[2 * plane + pix] = fmaf(r.T, tg.bg2, r.C2);
+        const float v0 = fmaf(r.T, tg.bg0, r.C0), v1 = fmaf(r.T, tg.bg1, r.C1),
+                    v2 = fmaf(r.T, tg.bg2, r.C2);
+        img[pix] = v0;
+        img[plane + pix] = v1;
+        img[2 * plane + pix] = v2;
+        if (kL2) {
+            const float *tgt = a.l2_target + 2 * tg.pix0;
+            float *dimg = a.l2_grad + 2 * tg.pix0;
+            const float e0 = v0 - tgt[pix], e1 = v1 - tgt[plane + pix],
+                        e2 = v2 - tgt[2 * plane + pix];
+            dimg[pix] = a.l2_scale * e0;
+            dimg[plane + pix] = a.l2_scale * e1;
+            dimg[2 * plane + pix] = a.l2_scale * e2;
+            l2 = fmaf(e0, e0, fmaf(e1, e1, fmaf(e2, e2, l2)));
+        }
         if (kState) {
             a.t_final[pix] = r.T;
             a.n_last[pix] = r.last;
@@ -375,7 +401,44 @@ __device__ inline void fwd_tile(const TileArgs &a, int tile) {
 // of entries that contributed; without it only the image.
 template <bool kState, bool kCount>
 __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
-    for_tiles(a, [&](int tile) { fwd_tile<kState, kCount>(a, tile); });
+    float unused = 0.f;
+    for_tiles(a, [&](int tile) { fwd_tile<kState, kCount, false>(a, tile, unused); });
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// The forward with the L2 loss gradient.  Every lane sums its squared errors
+// over the block's tiles; the block's waves add their sums in LDS and the last
+// one out adds the block's total to the loss, one global atomic per block.
+// Every wave of the block reaches the end exactly once (waves outside the
+// canvas leave fwd_tile early, not the kernel).
+template <bool kState, bool kCount>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_fwd_l2(TileArgs a) {
+    __shared__ float s_loss;
+    __shared__ int s_done;
+    if (threadIdx.x == 0) {
+        s_loss = 0.f;
+        s_done = 0;
+    }
+    __syncthreads();
+    float l2 = 0.f;
+    for_tiles(a, [&](int tile) { fwd_tile<kState, kCount, true>(a, tile, l2); });
+    if (!a.l2_loss) return;
+    l2 = wave_sum(l2);
+    if ((threadIdx.x & 63) == 0) {
+        __hip_atomic_fetch_add(&s_loss, l2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int waves = (int)(blockDim.x >> 6);
+        if (__hip_atomic_fetch_add(&s_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+            waves - 1) {
+            const float total =
+                __hip_atomic_load(&s_loss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (total != 0.f) atomicAdd(a.l2_loss, total);
+        }
+    }
 }
 
 // Broadcast lane 0's 64-bit value as a wave-uniform (scalar) value.  The
@@ -385,12 +448,6 @@ __device__ inline uint64_t uniform_u64(uint64_t v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | (uint64_t)lo;
-}
-
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
 }
 
 template <int CTRL>
@@ -1077,23 +1134,40 @@ TileArgs tile_args(const float *rec, const bz_bins &b, const bz_opts &o) {
 }  // namespace
 
 hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, float *image,
-                      const bz_pixstate *st, hipStream_t s) {
+                      const bz_pixstate *st, const L2Out *l2, hipStream_t s) {
     TileArgs a = tile_args(rec, b, o);
     a.image = image;
     int threads = o.tile_w * o.tile_h;
     size_t lds = sizeof(Staged) * (size_t)threads;
-    if (!st) {
-        launch_tiles(k_fwd<false, false>, a, b, o, 0, threads, lds, s);
-        return hipGetLastError();
+    if (l2) {
+        a.l2_target = l2->target;
+        a.l2_grad = l2->d_image;
+        a.l2_loss = l2->loss;
+        a.l2_scale = l2->scale;
+        if (l2->loss) hipLaunchKernelGGL(k_loss_zero, dim3(1), dim3(64), 0, s, l2->loss);
     }
-    a.t_final = st->t_final;
-    a.n_last = st->n_last;
-    a.n_contrib = st->n_contrib;
-    a.visit = st->visit;
-    if (st->n_contrib)
-        launch_tiles(k_fwd<true, true>, a, b, o, 0, threads, lds, s);
-    else
-        launch_tiles(k_fwd<true, false>, a, b, o, 0, threads, lds, s);
+    if (st) {
+        a.t_final = st->t_final;
+        a.n_last = st->n_last;
+        a.n_contrib = st->n_contrib;
+        a.visit = st->visit;
+    }
+    const bool count = st && st->n_contrib;
+    if (l2) {
+        if (!st)
+            launch_tiles(k_fwd_l2<false, false>, a, b, o, 0, threads, lds, s);
+        else if (count)
+            launch_tiles(k_fwd_l2<true, true>, a, b, o, 0, threads, lds, s);
+        else
+            launch_tiles(k_fwd_l2<true, false>, a, b, o, 0, threads, lds, s);
+    } else {
+        if (!st)
+            launch_tiles(k_fwd<false, false>, a, b, o, 0, threads, lds, s);
+        else if (count)
+            launch_tiles(k_fwd<true, true>, a, b, o, 0, threads, lds, s);
+        else
+            launch_tiles(k_fwd<true, false>, a, b, o, 0, threads, lds, s);
+    }
     return hipGetLastError();
 }
 

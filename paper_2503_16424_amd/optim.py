@@ -80,8 +80,8 @@ PAPER_LR = dict(lr_ctrl=2e-4, lr_color=1e-2, lr_opacity=1e-1, lr_width=1e-2)
 @dataclass
 class FitResult:
     psnr: list = field(default_factory=list)        # (step, PSNR of that step's render)
-    fwd_ms: list = field(default_factory=list)      # sample + bin + forward, per logged step
-    bwd_ms: list = field(default_factory=list)      # L2 gradient + backward, per logged step
+    fwd_ms: list = field(default_factory=list)      # sample + bin + forward with the L2 gradient
+    bwd_ms: list = field(default_factory=list)      # backward (and Xing loss), per logged step
     opt_ms: list = field(default_factory=list)      # optimiser update, per logged step
     step_ms: float = 0.0                            # wall clock per step over the loop
     final_psnr: float = 0.0
@@ -164,10 +164,9 @@ def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=No
         if (logged or step % cfg.check_every == 0) and rast.ensure_capacity():
             res.regrown += 1
             rast.bin()
-        rast.forward()
+        rast.forward_l2(target)
         if logged:
             ev[1].record()
-        rast.l2_grad(target)
         rast.backward()
         if cfg.xing_weight > 0.0:
             rast.xing(cfg.xing_weight)          # L = mean squared error + weight * Xing

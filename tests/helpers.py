@@ -131,3 +131,25 @@ def max_size_scene(W=96, H=80):
     return scenes._assemble(W, H, [0, 1, 1], [4, 4, 1], [1024, 8, 60], [0, 254, 30], ctrl,
                             [2.0, 0.0, 0.0], rng.uniform(0, 1, (3, 3)),
                             [[0.6, 0.9, 0.4, 0.8], [0.7], [0.5]], [2, 0, 1])
+
+
+def fused_l2_matches_separate(torch, r, tgt, ref_of):
+    """Render with bz_render_fwd then bz_l2_grad, then with bz_render_fwd_l2
+    over sentinel-filled outputs: image, blend state and d_image bit for bit,
+    the loss within float rounding of its sum (reference: ref_of(image))."""
+    r.render()
+    r.l2_grad(tgt)
+    torch.cuda.synchronize()
+    names = ["image", "d_image"] + (["t_final", "n_last", "n_contrib"] if r.state else [])
+    want = {k: getattr(r, k).clone() for k in names}
+    loss_sep = float(r.loss.item())
+    for k in names:
+        getattr(r, k).fill_(-7)
+    r.loss.fill_(-7.0)
+    r.forward_l2(tgt)
+    torch.cuda.synchronize()
+    for k in names:
+        assert torch.equal(getattr(r, k).view(torch.int32), want[k].view(torch.int32)), k
+    ref = ref_of(r.image)
+    assert abs(float(r.loss.item()) - ref) <= 1e-5 * ref
+    assert abs(loss_sep - ref) <= 1e-5 * ref

@@ -154,6 +154,8 @@ def test_device_calls_reject_null_arguments_before_launch():
     assert lib.bz_render_fwd(None, None, C.byref(o), None, None, None) == bz.BZ_ERR_ARG
     assert lib.bz_render_bwd(None, None, None, C.byref(o), None, None, None, None) == bz.BZ_ERR_ARG
     assert lib.bz_l2_grad(None, None, 10, C.c_float(1.0), None, None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_render_fwd_l2(None, None, C.byref(o), None, None, None, C.c_float(1.0), None,
+                                None, None) == bz.BZ_ERR_ARG
     bad = _opts(tile_w=12)
     assert lib.bz_sample(None, C.byref(bad), None, None) == bz.BZ_ERR_ARG
 

@@ -128,6 +128,25 @@ def test_step_graph_replays_reproduce_the_eager_step(torch_cuda, persistent):
         assert abs(float(r.loss.item()) - ref_loss) <= 1e-5 * abs(ref_loss), rep
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_forward_fused_with_l2_matches_separate_calls(torch_cuda, persistent):
+    """bz_render_fwd_l2 over a batch (a 1x1 canvas and one without curves
+    among them): image, blend state and d_image bit for bit as bz_render_fwd
+    then bz_l2_grad, the loss within float rounding."""
+    torch = torch_cuda
+    from tests.helpers import fused_l2_matches_separate
+    parts = _small_batch()
+    r = _rast(parts, persistent=persistent)
+    tgts = [scenes.target_noise(70 + c, sc.width, sc.height) for c, sc in enumerate(parts)]
+    flat = r.flat_images(tgts)
+    tgt = torch.as_tensor(flat, device="cuda")
+
+    def ref_of(img):
+        e = img.cpu().numpy().astype(np.float64) - np.asarray(flat, np.float64)
+        return float(np.sum(e * e))
+    fused_l2_matches_separate(torch, r, tgt, ref_of)
+
+
 def test_step_graph_grows_the_pair_buffer_and_records_again(torch_cuda):
     torch = torch_cuda
     from paper_2503_16424_amd.graph import StepGraph

@@ -236,7 +236,7 @@ def test_recomputed_blend_state_gives_the_stored_state_results(torch_cuda):
 
 
 def test_step_with_l2_kernel_matches_oracle_gradient(torch_cuda):
-    """The fused step (sample, bin, forward, L2 gradient kernel, backward)."""
+    """The step (sample, bin, forward fused with the L2 gradient, backward)."""
     import torch
     sc = scenes.tiny_128(0)
     tgt = scenes.tiny_128_target(0)
@@ -266,6 +266,10 @@ def test_overflow_is_flagged_and_recovers(torch_cuda):
     assert need > 16
     r.forward()
     assert np.all(np.isnan(r.image.cpu().numpy()))
+    import torch
+    r.forward_l2(torch.zeros_like(r.image))
+    assert np.all(np.isnan(r.image.cpu().numpy()))
+    assert np.all(np.isnan(r.d_image.cpu().numpy())) and np.isnan(r.loss.item())
     assert r.ensure_capacity()
     r.bin()
     assert not (r.flags() & bz.STATUS_OVERFLOW)
@@ -467,6 +471,34 @@ def test_l2_gradient_and_loss_on_an_odd_sized_canvas(torch_cuda):
     assert img.size % 4 != 0
     assert np.abs(r.d_image.cpu().numpy() - 2.0 * e / img.size).max() <= 1e-9
     assert abs(r.loss.item() - float(np.sum(e * e))) <= 1e-5 * float(np.sum(e * e))
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("state", ["stored", "recompute"])
+@pytest.mark.parametrize("name", ["tiny_128", "mixed_small_b", "size_split"])
+def test_forward_fused_with_l2_matches_separate_calls(torch_cuda, name, state, persistent):
+    torch = torch_cuda
+    from paper_2503_16424_amd import bz
+    from tests.helpers import fused_l2_matches_separate, size_split_scene
+    sc = size_split_scene() if name == "size_split" else SCENES[name]()
+    _note(f"fused forward + L2 {name} state {state} persistent {persistent}")
+    r = bz.Rasterizer(sc, bz.RenderOptions(persistent=persistent), blend_state=state)
+    tgt_np = scenes.target_noise(5, sc.width, sc.height)
+    tgt = torch.as_tensor(tgt_np, device="cuda")
+
+    def ref_of(img):
+        e = img.cpu().numpy().astype(np.float64) - tgt_np.astype(np.float64)
+        return float(np.sum(e * e))
+    fused_l2_matches_separate(torch, r, tgt, ref_of)
+    # the fused step's gradients are the separate calls' gradients
+    o0 = oracle.forward_backward(sc)
+    d = 2.0 * (o0["image"] - tgt_np.astype(np.float64)) / o0["image"].size
+    assert np.abs(r.d_image.cpu().numpy() - d).max() < 1e-9
+    r.backward()
+    torch.cuda.synchronize()
+    o = oracle.forward_backward(sc, d)
+    for k in ("d_ctrl", "d_color", "d_opacity"):
+        assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= GRAD_TOL, k
 
 
 def test_non_finite_curve_is_skipped_and_flagged(torch_cuda):

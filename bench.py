@@ -363,9 +363,10 @@ def main():
     torch.cuda.synchronize()
     print(f"# warmup done, {need} pairs", file=sys.stderr, flush=True)
 
-    # the forward writes the L2 loss gradient with the image (bz_render_fwd_l2)
-    stages = ["sample", "bin", "fwd_l2", "bwd_gauss", "bwd_curves"]
-    calls = [r.sample, r.bin, lambda: r.forward_l2(tgt), r.backward_gauss, r.backward_curves]
+    # the sampler does the binning's counting pass (bz_sample_bin) and the
+    # forward writes the L2 loss gradient with the image (bz_render_fwd_l2)
+    stages = ["sample_bin", "fwd_l2", "bwd_gauss", "bwd_curves"]
+    calls = [r.sample_bin, lambda: r.forward_l2(tgt), r.backward_gauss, r.backward_curves]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
           for _ in range(a.steps)]
     torch.cuda.synchronize()
@@ -391,7 +392,7 @@ def main():
           f"contributing pairs {n_alg}; mse {loss:.5f}", file=sys.stderr, flush=True)
 
     # Roofline of the dominant stage's kernel.
-    dom = max(("fwd_l2", "bwd_gauss", "bwd_curves", "bin", "sample"), key=lambda s: stage_ms[s])
+    dom = max(("fwd_l2", "bwd_gauss", "bwd_curves", "sample_bin"), key=lambda s: stage_ms[s])
     if dom == "fwd_l2":
         ach = n_alg * FLOPS_FWD_PAIR / (stage_ms["fwd_l2"] * 1e-3) / 1e12
         roof = dict(kernel="k_fwd_l2 (bz_render_fwd_l2)", bound="alu", achieved=ach,
@@ -405,14 +406,12 @@ def main():
         ach = byts / (stage_ms["bwd_curves"] * 1e-3) / 1e9
         roof = dict(kernel="k_bwd_curves", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
                     unit="GB/s")
-    elif dom == "bin":
-        byts = sc.n_gauss * 28 + need * 4 + r.n_tiles * 8
-        ach = byts / (stage_ms["bin"] * 1e-3) / 1e9
-        roof = dict(kernel="bz_bin", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s")
     else:
-        byts = sc.n_gauss * BYTES_REC
-        ach = byts / (stage_ms["sample"] * 1e-3) / 1e9
-        roof = dict(kernel="k_sample", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s")
+        # records written, then per pair its key and id written and read by the sort
+        byts = sc.n_gauss * BYTES_REC + need * 4 + r.n_tiles * 8
+        ach = byts / (stage_ms["sample_bin"] * 1e-3) / 1e9
+        roof = dict(kernel="bz_sample_bin", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
+                    unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(roof["kernel"].split()[0], a.workload, tw, th)
 

@@ -8,7 +8,8 @@
  * through gradients of any image loss.  The library provides that rasterizer:
  *
  *   bz_sample      curves -> 2D Gaussians                    (Sec. 3.3)
- *   bz_bin         Gaussians -> per-tile lists in draw order (Sec. 3.4, tile pipeline)
+ *   bz_bin         Gaussians -> per-tile lists in draw order (Sec. 3.4, tile pipeline);
+ *                  bz_sample_bin does both in one call
  *   bz_render_fwd  per-tile front-to-back alpha blending     (Sec. 3.4, blending sum)
  *   bz_render_bwd  reverse-order gradients to Gaussians, then to curve
  *                  control points, widths, colours, opacities
@@ -254,6 +255,13 @@ bz_status bz_visit_words(const bz_opts *opts, int64_t cap_pairs, int64_t *words)
  * requires g->cap >= c->n_gauss. */
 bz_status bz_sample(const bz_curves *c, const bz_opts *opts, bz_gaussians *g,
                     hipStream_t stream);
+
+/* bz_sample then bz_bin in one call: the sampler also writes each Gaussian's
+ * tile rectangle and count (the binning's first pass, Sec. 3.4), so the
+ * records are not read back for it.  Gaussians, tile lists, ranges and status
+ * come out exactly as from the two calls; arguments and errors are theirs. */
+bz_status bz_sample_bin(const bz_curves *c, const bz_opts *opts, bz_gaussians *g, bz_bins *b,
+                        hipStream_t stream);
 
 /* Sec. 3.4 tile pipeline: bound each Gaussian's truncated support
  * (1/2 d^T Q d <= -ln g_min), list it in every tile the bound touches, sort

@@ -72,7 +72,7 @@ class Grads(C.Structure):
 
 
 EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_batch_layout",
-           "bz_visit_words", "bz_sample", "bz_bin",
+           "bz_visit_words", "bz_sample", "bz_sample_bin", "bz_bin",
            "bz_render_fwd", "bz_render_fwd_l2", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
            "bz_curve_area", "bz_area_order_workspace", "bz_area_order", "bz_xing_loss",
            "bz_l2_grad", "bz_status_str")
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.bz_visit_words.argtypes = [P(Opts), C.c_int64, P(C.c_int64)]
     lib.bz_sample.restype = C.c_int
     lib.bz_sample.argtypes = [P(Curves), P(Opts), P(Gaussians), C.c_void_p]
+    lib.bz_sample_bin.restype = C.c_int
+    lib.bz_sample_bin.argtypes = [P(Curves), P(Opts), P(Gaussians), P(Bins), C.c_void_p]
     lib.bz_bin.restype = C.c_int
     lib.bz_bin.argtypes = [P(Gaussians), P(Opts), P(Bins), C.c_void_p]
     lib.bz_render_fwd.restype = C.c_int
@@ -431,6 +433,15 @@ class Rasterizer:
         _check("bz_sample", self.lib.bz_sample(C.byref(self.curves), C.byref(self.opts),
                                                C.byref(self.gauss), _stream()))
 
+    def sample_bin(self):
+        """sample and bin in one call: the sampler also does the binning's
+        counting pass; records and tile lists as from the two calls."""
+        if self.draw_order == "area":
+            self.reorder()
+        _check("bz_sample_bin", self.lib.bz_sample_bin(C.byref(self.curves), C.byref(self.opts),
+                                                       C.byref(self.gauss), C.byref(self.bins),
+                                                       _stream()))
+
     def bin(self):
         _check("bz_bin", self.lib.bz_bin(C.byref(self.gauss), C.byref(self.opts),
                                          C.byref(self.bins), _stream()))
@@ -490,8 +501,7 @@ class Rasterizer:
 
     def step(self, target):
         """One fwd+bwd of the mean squared error against ``target`` (no sync)."""
-        self.sample()
-        self.bin()
+        self.sample_bin()
         self.forward_l2(target)
         self.backward()
 

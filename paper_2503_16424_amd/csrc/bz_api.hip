@@ -214,7 +214,24 @@ bz_status bz_sample(const bz_curves *c, const bz_opts *o, bz_gaussians *g, hipSt
     if (c->n_curves > 0 && 2 * 16 * (int64_t)c->max_k > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
     (void)hipGetLastError();
     g->n = c->n_gauss;
-    return launched(launch_sample(*c, *o, g->rec, s));
+    return launched(launch_sample(*c, *o, g->rec, nullptr, s));
+}
+
+bz_status bz_sample_bin(const bz_curves *c, const bz_opts *o, bz_gaussians *g, bz_bins *b,
+                        hipStream_t s) {
+    bz_status st = check_opts(o);
+    if (st != BZ_OK) return st;
+    if ((st = check_curves(c)) != BZ_OK) return st;
+    if (!g || (c->n_gauss > 0 && !g->rec)) return BZ_ERR_ARG;
+    if ((uintptr_t)g->rec & 15) return BZ_ERR_ARG;
+    if (g->cap < c->n_gauss) return BZ_ERR_CAPACITY;
+    if (c->n_curves > 0 && 2 * 16 * (int64_t)c->max_k > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
+    if (c->n_gauss >= (int64_t(1) << 32)) return BZ_ERR_UNSUPPORTED;
+    if (o->batch && o->batch->n_gauss != c->n_gauss) return BZ_ERR_ARG;
+    if ((st = check_bins(b, o, c->n_gauss, true)) != BZ_OK) return st;
+    (void)hipGetLastError();
+    g->n = c->n_gauss;
+    return launched(launch_sample_bin(*c, *o, g->rec, *b, s));
 }
 
 bz_status bz_bin(const bz_gaussians *g, const bz_opts *o, bz_bins *b, hipStream_t s) {

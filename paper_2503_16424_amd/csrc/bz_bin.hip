@@ -84,32 +84,10 @@ __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, i
     int tiles_x_unused;
     uint32_t base_unused;
     gauss_canvas(cv, n_canvas, g, W, H, tiles_x_unused, base_unused);
-    float4 m = rec[3 * g], q = rec[3 * g + 1];
-    float mx = m.x + m.z, my = m.y + m.w;
-    float det = q.x * q.z - q.y * q.y;
-    bool finite = isfinite(mx) && isfinite(my) && isfinite(q.x) && isfinite(q.y) &&
-                  isfinite(q.z) && isfinite(q.w);
-    uint32_t cnt = 0;
-    ushort4 rc = make_ushort4(1, 1, 0, 0);
-    if (finite && q.x > 0.f && q.z > 0.f && det > 0.f && isfinite(det)) {
-        float hx = sqrtf(two_p * q.z / det) * kCullSlackBox + kCullPadBox;
-        float hy = sqrtf(two_p * q.x / det) * kCullSlackBox + kCullPadBox;
-        // pixel x covers centre x + 1/2
-        float fx0 = ceilf(mx - hx - 0.5f), fx1 = floorf(mx + hx - 0.5f);
-        float fy0 = ceilf(my - hy - 0.5f), fy1 = floorf(my + hy - 0.5f);
-        fx0 = fmaxf(fx0, 0.f);
-        fy0 = fmaxf(fy0, 0.f);
-        fx1 = fminf(fx1, (float)(W - 1));
-        fy1 = fminf(fy1, (float)(H - 1));
-        if (fx0 <= fx1 && fy0 <= fy1) {
-            int tx0 = (int)fx0 / tw, tx1 = (int)fx1 / tw;
-            int ty0 = (int)fy0 / th, ty1 = (int)fy1 / th;
-            rc = make_ushort4(tx0, ty0, tx1, ty1);
-            cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-        }
-    } else if (!finite) {
-        atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
-    }
+    ushort4 rc;
+    bool finite;
+    const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, tw, th, two_p, rc, finite);
+    if (!finite) atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
     counts[g] = cnt;
     rects[g] = rc;
 }
@@ -514,56 +492,100 @@ BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
     return L;
 }
 
+namespace {
+
+// The binning workspace's arrays.
+struct BinBufs {
+    BinLayout L;
+    uint32_t *counts;
+    ushort4 *rects;
+    uint32_t *keys_a, *keys_b, *vals_b, *hist;
+    uint64_t *part;
+};
+
+BinBufs bin_bufs(const bz_opts &o, int64_t n, const bz_bins &b) {
+    BinBufs u;
+    u.L = bin_layout(o, n, b.cap_pairs);
+    char *ws = (char *)b.workspace;
+    u.counts = (uint32_t *)(ws + u.L.off_counts);
+    u.rects = (ushort4 *)(ws + u.L.off_rects);
+    u.keys_a = (uint32_t *)(ws + u.L.off_keys_a);
+    u.keys_b = (uint32_t *)(ws + u.L.off_keys_b);
+    u.vals_b = (uint32_t *)(ws + u.L.off_vals_b);
+    u.hist = (uint32_t *)(ws + u.L.off_hist);
+    u.part = (uint64_t *)(ws + u.L.off_part);
+    return u;
+}
+
+float support_two_p(const bz_opts &o) { return 2.0f * (-logf(o.g_min)); }
+
+// Status and ranges cleared: before anything of the call writes a flag.
+void bin_prepare(const BinBufs &u, const bz_bins &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, b.status);
+    hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(2 * u.L.n_tiles, 256)), dim3(256), 0, s, b.ranges,
+                       2 * u.L.n_tiles, 0u);
+}
+
+// From the per-Gaussian tile counts and rectangles: offsets, pairs, sort, ranges.
+hipError_t bin_finish(const BinBufs &u, int64_t n, const bz_opts &o, const bz_bins &b,
+                      hipStream_t s) {
+    const BinLayout &L = u.L;
+    const int tx = (int)tiles_x(o);
+    const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
+    const int ncv = o.batch ? o.batch->n_canvas : 0;
+    hipError_t e = scan_u32(u.counts, u.counts, n, u.part, b.status, b.cap_pairs, b.status, s);
+    if (e != hipSuccess) return e;
+    // The final radix pass must land in (keys_a, ids).
+    bool even = (L.passes % 2) == 0;
+    uint32_t *k0 = even ? u.keys_a : u.keys_b, *v0 = even ? b.ids : u.vals_b;
+    hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 256)), dim3(256), 0, s, u.counts, u.rects, n, tx, cv,
+                       ncv, k0, v0, (const int64_t *)b.status);
+    uint32_t *kin = k0, *vin = v0;
+    for (int p = 0; p < L.passes; ++p) {
+        int shift = 8 * p;
+        int nbits = L.key_bits - shift < 8 ? L.key_bits - shift : 8;
+        uint32_t *kout = (kin == u.keys_a) ? u.keys_b : u.keys_a;
+        uint32_t *vout = (vin == b.ids) ? u.vals_b : b.ids;
+        hipLaunchKernelGGL(k_radix_hist, dim3(L.hist_blocks), dim3(kBlk), 0, s, kin,
+                           (const int64_t *)b.status, shift, nbits, u.hist, L.hist_blocks);
+        e = scan_u32(u.hist, u.hist, kRadix * L.hist_blocks, u.part, nullptr, 0, b.status, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(L.hist_blocks), dim3(kBlk), 0, s, kin, vin, kout,
+                           vout, (const uint32_t *)u.hist, L.hist_blocks,
+                           (const int64_t *)b.status, shift, nbits);
+        kin = kout;
+        vin = vout;
+    }
+    hipLaunchKernelGGL(k_ranges, dim3(cdiv(cdiv(b.cap_pairs, kRangeItems), 256)), dim3(256), 0, s,
+                       kin, (const int64_t *)b.status, b.cap_pairs, b.ranges);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_bins &b,
                       hipStream_t s) {
-    BinLayout L = bin_layout(o, n, b.cap_pairs);
-    char *ws = (char *)b.workspace;
-    uint32_t *counts = (uint32_t *)(ws + L.off_counts);
-    ushort4 *rects = (ushort4 *)(ws + L.off_rects);
-    uint32_t *keys_a = (uint32_t *)(ws + L.off_keys_a);
-    uint32_t *keys_b = (uint32_t *)(ws + L.off_keys_b);
-    uint32_t *vals_b = (uint32_t *)(ws + L.off_vals_b);
-    uint32_t *hist = (uint32_t *)(ws + L.off_hist);
-    uint64_t *part = (uint64_t *)(ws + L.off_part);
-    const float4 *rec = (const float4 *)rec_f;
-    const int tx = (int)tiles_x(o);
+    const BinBufs u = bin_bufs(o, n, b);
+    bin_prepare(u, b, s);
+    if (n == 0) return hipGetLastError();
+    const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
+    const int ncv = o.batch ? o.batch->n_canvas : 0;
+    hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, (const float4 *)rec_f, n,
+                       o.width, o.height, o.tile_w, o.tile_h, support_two_p(o), cv, ncv, u.counts,
+                       u.rects, b.status);
+    return bin_finish(u, n, o, b, s);
+}
 
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, b.status);
-    hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(2 * L.n_tiles, 256)), dim3(256), 0, s, b.ranges,
-                       2 * L.n_tiles, 0u);
-    if (n > 0) {
-        float two_p = 2.0f * (-logf(o.g_min));
-        const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
-        const int ncv = o.batch ? o.batch->n_canvas : 0;
-        hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, rec, n, o.width,
-                           o.height, o.tile_w, o.tile_h, two_p, cv, ncv, counts, rects, b.status);
-        hipError_t e = scan_u32(counts, counts, n, part, b.status, b.cap_pairs, b.status, s);
-        if (e != hipSuccess) return e;
-        // The final radix pass must land in (keys_a, ids).
-        bool even = (L.passes % 2) == 0;
-        uint32_t *k0 = even ? keys_a : keys_b, *v0 = even ? b.ids : vals_b;
-        hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 256)), dim3(256), 0, s, counts, rects, n, tx,
-                           cv, ncv, k0, v0, (const int64_t *)b.status);
-        uint32_t *kin = k0, *vin = v0;
-        for (int p = 0; p < L.passes; ++p) {
-            int shift = 8 * p;
-            int nbits = L.key_bits - shift < 8 ? L.key_bits - shift : 8;
-            uint32_t *kout = (kin == keys_a) ? keys_b : keys_a;
-            uint32_t *vout = (vin == b.ids) ? vals_b : b.ids;
-            hipLaunchKernelGGL(k_radix_hist, dim3(L.hist_blocks), dim3(kBlk), 0, s, kin,
-                               (const int64_t *)b.status, shift, nbits, hist, L.hist_blocks);
-            e = scan_u32(hist, hist, kRadix * L.hist_blocks, part, nullptr, 0, b.status, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_radix_scatter, dim3(L.hist_blocks), dim3(kBlk), 0, s, kin, vin,
-                               kout, vout, (const uint32_t *)hist, L.hist_blocks,
-                               (const int64_t *)b.status, shift, nbits);
-            kin = kout;
-            vin = vout;
-        }
-        hipLaunchKernelGGL(k_ranges, dim3(cdiv(cdiv(b.cap_pairs, kRangeItems), 256)), dim3(256),
-                           0, s, kin, (const int64_t *)b.status, b.cap_pairs, b.ranges);
-    }
-    return hipGetLastError();
+hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, const bz_bins &b,
+                             hipStream_t s) {
+    const int64_t n = c.n_gauss;
+    const BinBufs u = bin_bufs(o, n, b);
+    bin_prepare(u, b, s);
+    if (n == 0) return hipGetLastError();
+    const BinCount bc = {u.counts, u.rects, b.status, o.tile_w, o.tile_h, support_two_p(o)};
+    hipError_t e = launch_sample(c, o, rec, &bc, s);
+    if (e != hipSuccess) return e;
+    return bin_finish(u, n, o, b, s);
 }
 
 }  // namespace bz

@@ -48,9 +48,16 @@ struct Status {
 // ---------------------------------------------------------------------------
 // host launchers implemented in the .hip files
 // ---------------------------------------------------------------------------
-hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipStream_t s);
+struct BinCount;
+// bc non-null: sampling also writes every Gaussian's tile count and rectangle
+// (what the binning's counting pass would write).
+hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, const BinCount *bc,
+                         hipStream_t s);
 hipError_t launch_bin(const float *rec, int64_t n_gauss, const bz_opts &o, const bz_bins &b,
                       hipStream_t s);
+// bz_sample_bin: binning with its counting pass done by the sampler.
+hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec,
+                             const bz_bins &b, hipStream_t s);
 // The L2 loss gradient the forward can write with the image (loss may be null).
 struct L2Out {
     const float *target;
@@ -134,6 +141,46 @@ __host__ __device__ inline int batch_find(const bz_canvas *cv, int n_canvas, int
 inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
     return 2 * 16 * max_k + 16 * max_k + 4 * max_k + 4 * 8 * max_gauss;
 }
+
+// Tiles of a Gaussian record (mean hi + lo, conic Q, opacity): the tile
+// rectangle (x0, y0, x1, y1) that the bounding box of its truncated support
+// (1/2 d^T Q d <= two_p / 2) reaches on a W x H canvas, and the number of
+// tiles in it; 0 with rect (1, 1, 0, 0) when it reaches none or Q is not
+// positive definite.  finite: the record's mean, conic and opacity are finite.
+__device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, int tw, int th,
+                                     float two_p, ushort4 &rc, bool &finite) {
+    const float mx = m.x + m.z, my = m.y + m.w;
+    const float det = q.x * q.z - q.y * q.y;
+    finite = isfinite(mx) && isfinite(my) && isfinite(q.x) && isfinite(q.y) && isfinite(q.z) &&
+             isfinite(q.w);
+    rc = make_ushort4(1, 1, 0, 0);
+    if (!(finite && q.x > 0.f && q.z > 0.f && det > 0.f && isfinite(det))) return 0u;
+    const float hx = sqrtf(two_p * q.z / det) * kCullSlackBox + kCullPadBox;
+    const float hy = sqrtf(two_p * q.x / det) * kCullSlackBox + kCullPadBox;
+    // pixel x covers centre x + 1/2
+    float fx0 = ceilf(mx - hx - 0.5f), fx1 = floorf(mx + hx - 0.5f);
+    float fy0 = ceilf(my - hy - 0.5f), fy1 = floorf(my + hy - 0.5f);
+    fx0 = fmaxf(fx0, 0.f);
+    fy0 = fmaxf(fy0, 0.f);
+    fx1 = fminf(fx1, (float)(W - 1));
+    fy1 = fminf(fy1, (float)(H - 1));
+    if (!(fx0 <= fx1 && fy0 <= fy1)) return 0u;
+    const int tx0 = (int)fx0 / tw, tx1 = (int)fx1 / tw;
+    const int ty0 = (int)fy0 / th, ty1 = (int)fy1 / th;
+    rc = make_ushort4(tx0, ty0, tx1, ty1);
+    return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+}
+
+// Where sampling writes the tile counts and rectangles for the binning that
+// follows it (bz_sample_bin): the binning workspace's arrays, the tile shape
+// and the support constant.
+struct BinCount {
+    uint32_t *counts;
+    ushort4 *rects;
+    int64_t *status;
+    int tw, th;
+    float two_p;
+};
 
 // Visit masks: one plane per 8x8 quad of a tile; a plane holds, for every tile,
 // ceil(len/64) words starting at word start/64 + tile (see visit_word).

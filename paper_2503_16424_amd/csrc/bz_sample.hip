@@ -7,7 +7,10 @@
 // of Eq. sigma plus the dilation sigma0^2; Q = Sigma^-1 from the unit tangent
 // of Eq. rotation (Eq. RSSR with R = [c -s; s c], S = diag(sx, sy)).  Records
 // of one curve are contiguous; a wave stages its 64 records of a round in LDS
-// and writes them as three contiguous 1 KB stores.
+// and writes them as three contiguous 1 KB stores.  With kBin the kernel also
+// does the binning's counting pass (Sec. 3.4): each Gaussian's tile rectangle
+// and count, from the record values it stores, so the binning need not read
+// the records back.
 #include "bz_geom.h"
 
 namespace bz {
@@ -19,8 +22,11 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double inv_rho2, double s0,
-                                               float4 *__restrict__ rec) {
+template <bool kBin>
+__global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sample(bz_curves c, double inv_rho2, double s0,
+                                               float4 *__restrict__ rec, BinCount bc,
+                                               const bz_canvas *__restrict__ cv, int n_canvas,
+                                               int W, int H) {
     extern __shared__ double2 lds_xy[];
     __shared__ float s_tau[256];
     const int p = blockIdx.x;
@@ -37,6 +43,12 @@ __global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double in
     const float *opa = c.opacity + c.opa_off[v.id];
     const float cid = __int_as_float(v.id);
     const int n = v.rows * v.K;
+    if (kBin && cv) {   // the canvas holding the curve (and all its Gaussians)
+        const int ci = batch_find(cv, n_canvas, v.g0, [](const bz_canvas &r) { return r.gauss_off; });
+        W = cv[ci].width;
+        H = cv[ci].height;
+    }
+    bool nonfinite = false;
     // A wave emits 64 consecutive Gaussians per round: their 48-byte records
     // meet in the wave's LDS slice and leave as three 1 KB contiguous stores
     // (written straight, lane l's three 16-byte pieces would be 48 bytes apart).
@@ -56,9 +68,19 @@ __global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double in
             float hx = (float)g.mu.x, hy = (float)g.mu.y;
             float lx = (float)(g.mu.x - (double)hx), ly = (float)(g.mu.y - (double)hy);
             float o = opa[v.nopa == v.S ? g.seg : 0];
-            my[3 * l + 0] = make_float4(hx, hy, lx, ly);
-            my[3 * l + 1] = make_float4((float)qxx, (float)qxy, (float)qyy, o);
+            const float4 m = make_float4(hx, hy, lx, ly);
+            const float4 q = make_float4((float)qxx, (float)qxy, (float)qyy, o);
+            my[3 * l + 0] = m;
+            my[3 * l + 1] = q;
             my[3 * l + 2] = make_float4(cr, cg, cb, cid);
+            if (kBin) {
+                ushort4 rc;
+                bool finite;
+                const uint32_t cnt = tile_rect(m, q, W, H, bc.tw, bc.th, bc.two_p, rc, finite);
+                bc.counts[v.g0 + idx] = cnt;
+                bc.rects[v.g0 + idx] = rc;
+                nonfinite |= !finite;
+            }
         }
         wave_sync_lds();
         const int valid = 3 * (n - base < 64 ? n - base : 64);   // float4s of this round
@@ -68,14 +90,25 @@ __global__ __launch_bounds__(kCurveThreads) void k_sample(bz_curves c, double in
             if (j * 64 + l < valid) out[j * 64 + l] = my[j * 64 + l];
         wave_sync_lds();
     }
+    if (kBin && __builtin_amdgcn_ballot_w64(nonfinite) && l == 0)
+        atomicOr((unsigned long long *)&bc.status[1], (unsigned long long)Status::kNonFinite);
 }
 
-hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, hipStream_t s) {
+hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, const BinCount *bc,
+                         hipStream_t s) {
     if (c.n_curves == 0) return hipSuccess;
     size_t lds = 2 * sizeof(double2) * (size_t)c.max_k;
     double rho = (double)o.rho;
-    hipLaunchKernelGGL(k_sample, dim3(c.n_curves), dim3(kCurveThreads), lds, s, c, 1.0 / (rho * rho),
-                       (double)o.sigma0_sq, reinterpret_cast<float4 *>(rec));
+    const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
+    const int ncv = o.batch ? o.batch->n_canvas : 0;
+    if (bc)
+        hipLaunchKernelGGL(k_sample<true>, dim3(c.n_curves), dim3(kCurveThreads), lds, s, c,
+                           1.0 / (rho * rho), (double)o.sigma0_sq, reinterpret_cast<float4 *>(rec),
+                           *bc, cv, ncv, o.width, o.height);
+    else
+        hipLaunchKernelGGL(k_sample<false>, dim3(c.n_curves), dim3(kCurveThreads), lds, s, c,
+                           1.0 / (rho * rho), (double)o.sigma0_sq, reinterpret_cast<float4 *>(rec),
+                           BinCount{}, cv, ncv, o.width, o.height);
     return hipGetLastError();
 }
 

@@ -153,3 +153,27 @@ def fused_l2_matches_separate(torch, r, tgt, ref_of):
     ref = ref_of(r.image)
     assert abs(float(r.loss.item()) - ref) <= 1e-5 * ref
     assert abs(loss_sep - ref) <= 1e-5 * ref
+
+
+def sample_bin_matches_separate(torch, r):
+    """bz_sample then bz_bin, then bz_sample_bin over sentinel-filled outputs:
+    records, the two status words, tile ranges and the tile lists bit for bit (the
+    lists only without overflow: with it neither call writes them)."""
+    r.sample()
+    r.bin()
+    torch.cuda.synchronize()
+    n = r.pairs_required()
+    want = dict(rec=r.rec[: 12 * r.n_gauss].clone(), status=r.status[:2].clone(),
+                ranges=r.ranges.clone())
+    if n <= r.cap_pairs:
+        want["ids"] = r.ids[:n].clone()
+    r.rec.fill_(-7.0)
+    r.status.fill_(-7)
+    r.ranges.fill_(-7)
+    r.ids.fill_(-7)
+    r.sample_bin()
+    torch.cuda.synchronize()
+    got = dict(rec=r.rec[: 12 * r.n_gauss], status=r.status[:2], ranges=r.ranges, ids=r.ids[:n])
+    for k in want:
+        assert torch.equal(got[k].view(torch.int32), want[k].view(torch.int32)), k
+    return n

@@ -148,6 +148,7 @@ def test_device_calls_reject_null_arguments_before_launch():
     lib = bz.load_library()
     o = _opts()
     assert lib.bz_sample(None, C.byref(o), None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_sample_bin(None, C.byref(o), None, None, None) == bz.BZ_ERR_ARG
     assert lib.bz_bin(None, C.byref(o), None, None) == bz.BZ_ERR_ARG
     g = bz.Gaussians(10, 10, 0)
     assert lib.bz_bin(C.byref(g), C.byref(o), None, None) == bz.BZ_ERR_ARG

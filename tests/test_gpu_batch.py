@@ -147,6 +147,16 @@ def test_batch_forward_fused_with_l2_matches_separate_calls(torch_cuda, persiste
     fused_l2_matches_separate(torch, r, tgt, ref_of)
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_batch_sample_bin_matches_separate_calls(torch_cuda, tile):
+    """bz_sample_bin over a batch (each Gaussian bounded on its own canvas):
+    records and tile lists bit for bit as bz_sample then bz_bin."""
+    from tests.helpers import sample_bin_matches_separate
+    r = _rast(_small_batch(), tile)
+    r.render()
+    assert sample_bin_matches_separate(torch_cuda, r) > 0
+
+
 def test_step_graph_grows_the_pair_buffer_and_records_again(torch_cuda):
     torch = torch_cuda
     from paper_2503_16424_amd.graph import StepGraph

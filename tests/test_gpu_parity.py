@@ -501,6 +501,47 @@ def test_forward_fused_with_l2_matches_separate_calls(torch_cuda, name, state, p
         assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= GRAD_TOL, k
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+@pytest.mark.parametrize("name", ["tiny_128", "mixed_small_b", "mixed_R20", "size_split"])
+def test_sample_bin_matches_separate_calls(torch_cuda, name, tile):
+    torch = torch_cuda
+    from paper_2503_16424_amd import bz
+    from tests.helpers import sample_bin_matches_separate, size_split_scene
+    sc = size_split_scene() if name == "size_split" else SCENES[name]()
+    _note(f"sample+bin {name} tile {tile}")
+    r = _rast(sc, tile)
+    r.render()                                  # sizes the pair buffer
+    assert sample_bin_matches_separate(torch, r) > 0
+    assert not r.flags() & bz.STATUS_OVERFLOW
+
+
+def test_sample_bin_overflow_and_non_finite_flags(torch_cuda):
+    """Too small a pair buffer and a NaN control point: bz_sample_bin raises
+    the same status bits and counts the same pairs as the two calls."""
+    torch = torch_cuda
+    from paper_2503_16424_amd import bz
+    from tests.helpers import sample_bin_matches_separate
+    sc = SCENES["mixed_small_b"]()
+    pts = np.array(sc.ctrl, copy=True)
+    pts[int(sc.ctrl_off[3])] = np.nan
+    sc.ctrl = pts
+    r = _rast(sc, cap_pairs=64)
+    need = sample_bin_matches_separate(torch, r)
+    assert need > 64
+    assert r.flags() & bz.STATUS_OVERFLOW and r.flags() & bz.STATUS_NONFINITE
+
+
+def test_paper_scale_sample_bin_matches_separate_calls(torch_cuda):
+    """2048x2048, 20,000 curves: the fused call's records and tile lists are
+    those of the two calls, bit for bit."""
+    torch = torch_cuda
+    from tests.helpers import sample_bin_matches_separate
+    sc = scenes.paper_2048(0)
+    r = _rast(sc)
+    r.render()
+    assert sample_bin_matches_separate(torch, r) > 10 ** 7
+
+
 def test_non_finite_curve_is_skipped_and_flagged(torch_cuda):
     """A NaN control point makes its curve's Gaussians non-finite: binning
     skips them and raises the status bit; the image and every other curve's

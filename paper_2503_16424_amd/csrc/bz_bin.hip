@@ -232,10 +232,13 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
     const uint32_t begin = s_off[0], total = s_off[nb] - begin;
     for (uint32_t i = t; i < total; i += 256) {
         const uint32_t o = begin + i;
-        int lo = 0, hi = nb - 1;                 // last Gaussian whose offset <= o
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= o) lo = mid; else hi = mid - 1;
+        // last Gaussian whose offset <= o (offsets ascend; s_off[0] <= o):
+        // eight fixed halving steps over the block's 256
+        int lo = 0;
+#pragma unroll
+        for (int step = 128; step >= 1; step >>= 1) {
+            const int mid = lo + step;
+            if (mid < nb && s_off[mid] <= o) lo = mid;
         }
         const ushort4 rc = s_rect[lo];
         const uint32_t w = (uint32_t)(rc.z - rc.x + 1);

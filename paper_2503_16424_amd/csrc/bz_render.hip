@@ -18,9 +18,13 @@
 // each XCD's L2 sees a compact band of neighbouring tiles, which share most
 // of their Gaussians.
 //
-// Stage 2 of the backward pass is per curve (one 256-thread workgroup per
-// curve, no atomics): it chains the per-Gaussian gradients through the
-// sampling of Sec. 3.3.
+// The forward can also write the L2 loss gradient of Sec. 3.5 as it writes
+// each pixel (k_fwd_l2), which spares the step a pass over the image.
+//
+// Stage 2 of the backward pass is per curve (one workgroup per curve: 64
+// threads for curves of at most 64 Gaussians, 256 for larger ones; no
+// atomics): it chains the per-Gaussian gradients through the sampling of
+// Sec. 3.3.
 #include "bz_geom.h"
 
 namespace bz {

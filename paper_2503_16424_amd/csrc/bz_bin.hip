@@ -109,45 +109,21 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// One block: exclusive scan of the block partials in place.  total_out (may be
-// null) receives the grand total; above cap the overflow flag is raised.
-__global__ __launch_bounds__(256) void k_scan_partials(uint64_t *part, int64_t nb,
-                                                       int64_t *total_out, int64_t cap,
-                                                       int64_t *status) {
-    __shared__ uint64_t s_wave[kBlk / 64];
-    uint64_t carry = 0;
-    for (int64_t base = 0; base < nb; base += kTile) {
-        uint64_t v[kItems];
-        uint64_t s = 0;
-#pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            int64_t e = base + threadIdx.x * kItems + j;
-            v[j] = e < nb ? part[e] : 0;
-            s += v[j];
-        }
-        uint64_t tot;
-        uint64_t ex = block_excl_scan(s, s_wave, tot) + carry;
-#pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            int64_t e = base + threadIdx.x * kItems + j;
-            if (e < nb) part[e] = ex;
-            ex += v[j];
-        }
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && total_out) {
-        *total_out = (int64_t)carry;
-        if ((int64_t)carry > cap)
-            atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kOverflow);
-    }
-}
-
+// Block b: exclusive scan of its kTile values, plus the carry-in of the blocks
+// before it, which it adds up from their partials itself.  The last block also
+// writes the grand total to total_out (may be null) and raises the overflow
+// flag when it exceeds cap.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, uint32_t *out, int64_t n,
-                                                    const uint64_t *__restrict__ part) {
+                                                    const uint64_t *__restrict__ part,
+                                                    int64_t *total_out, int64_t cap,
+                                                    int64_t *status) {
     __shared__ uint32_t s_v[kTile + kTile / 32];
     __shared__ uint64_t s_wave[kBlk / 64];
-    int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t c = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kBlk) c += part[i];
+    uint64_t carry;
+    block_excl_scan(c, s_wave, carry);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         int li = j * kBlk + threadIdx.x;
@@ -163,7 +139,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, uint32_t
         s += v[j];
     }
     uint64_t tot;
-    uint64_t ex = block_excl_scan(s, s_wave, tot) + part[blockIdx.x];
+    uint64_t ex = block_excl_scan(s, s_wave, tot) + carry;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         s_v[lds_pad(threadIdx.x * kItems + j)] = (uint32_t)ex;
@@ -176,6 +152,11 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, uint32_t
         int64_t e = base + li;
         if (e < n) out[e] = s_v[lds_pad(li)];
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && total_out) {
+        *total_out = (int64_t)(carry + tot);
+        if ((int64_t)(carry + tot) > cap)
+            atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kOverflow);
+    }
 }
 
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part,
@@ -183,10 +164,8 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part
     int64_t nb = cdiv(n, kTile);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlk), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlk), 0, s, part, nb, total_out, cap,
-                       status);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlk), 0, s, in, out, n,
-                       (const uint64_t *)part);
+                       (const uint64_t *)part, total_out, cap, status);
     return hipGetLastError();
 }
 

@@ -136,7 +136,8 @@ def max_size_scene(W=96, H=80):
 def fused_l2_matches_separate(torch, r, tgt, ref_of):
     """Render with bz_render_fwd then bz_l2_grad, then with bz_render_fwd_l2
     over sentinel-filled outputs: image, blend state and d_image bit for bit,
-    the loss within float rounding of its sum (reference: ref_of(image))."""
+    the loss within float rounding of its sum (reference: ref_of(image)); the
+    same without the contributor counts, which are then left untouched."""
     r.render()
     r.l2_grad(tgt)
     torch.cuda.synchronize()
@@ -146,13 +147,27 @@ def fused_l2_matches_separate(torch, r, tgt, ref_of):
     for k in names:
         getattr(r, k).fill_(-7)
     r.loss.fill_(-7.0)
-    r.forward_l2(tgt)
+    r.forward_l2(tgt, count=True)
     torch.cuda.synchronize()
     for k in names:
         assert torch.equal(getattr(r, k).view(torch.int32), want[k].view(torch.int32)), k
     ref = ref_of(r.image)
     assert abs(float(r.loss.item()) - ref) <= 1e-5 * ref
     assert abs(loss_sep - ref) <= 1e-5 * ref
+    # without the contributor counts (as the step runs it): the rest unchanged,
+    # the counts left as they were
+    if r.state:
+        r.n_contrib.fill_(-5)
+    for k in names:
+        if k != "n_contrib":
+            getattr(r, k).fill_(-7)
+    r.forward_l2(tgt)
+    torch.cuda.synchronize()
+    for k in names:
+        if k == "n_contrib":
+            assert bool((r.n_contrib == -5).all())
+        else:
+            assert torch.equal(getattr(r, k).view(torch.int32), want[k].view(torch.int32)), k
 
 
 def sample_bin_matches_separate(torch, r):

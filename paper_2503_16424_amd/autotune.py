@@ -3,12 +3,13 @@
 The tile shape (tile_w x tile_h pixels = threads per workgroup, one 8x8 quad
 per wave) and the launch form (one workgroup per tile, or persistent
 workgroups taking tiles from a counter) change only speed, never results.
-Which is fastest depends on the workload: large canvases with deep tile
-lists favour small tiles (less culled work per quad), many small canvases
-favour shapes that waste fewer lanes at canvas edges, and a persistent launch
-pays off when tiles are many and cheap.  :func:`autotune` measures every
-candidate on the actual workload, each as a recorded step graph, and returns
-the fastest.
+Which is fastest depends on the workload.  Smaller tiles list and stage a
+Gaussian in more tiles; larger ones stage entries that fewer of their quads
+need and leave more lanes idle at canvas edges; a persistent launch pays off
+when tiles are many and cheap.  :func:`autotune` measures every candidate on
+the actual workload, each as a recorded step graph, and returns the fastest.
+``python -m paper_2503_16424_amd.autotune`` runs it on the 2048x2048,
+20,000-curve workload.
 """
 from __future__ import annotations
 
@@ -64,3 +65,24 @@ def autotune(scenes_or_scene, target, base=None, cands=None, reps: int = 5, log=
         torch.cuda.empty_cache()
     best = min(table, key=lambda t: t[1])[0]
     return replace(base, **best), table
+
+
+def main(argv=None) -> int:
+    """Every candidate on the 2048x2048, 20,000-curve workload (one GPU)."""
+    import argparse
+
+    import torch
+
+    from . import scenes
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--reps", type=int, default=10, help="timed graph replays per candidate")
+    a = ap.parse_args(argv)
+    sc = scenes.paper_2048(0)
+    tgt = torch.as_tensor(scenes.target_noise(1, sc.width, sc.height), device="cuda")
+    best, _ = autotune(sc, tgt, reps=a.reps, log=lambda m: print(m, flush=True))
+    print(f"best: tile {best.tile_w}x{best.tile_h} persistent={int(best.persistent)}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -173,6 +173,51 @@ def test_sample_rejects_small_capacity_on_host():
     assert lib.bz_sample(C.byref(cv), C.byref(o), C.byref(g), None) == bz.BZ_ERR_CAPACITY
 
 
+def _fake_curves(n_gauss=16):
+    cv = bz.Curves()
+    cv.n_curves, cv.n_gauss, cv.max_gauss_per_curve, cv.max_k = 1, n_gauss, 16, 16
+    for f in ("kind", "nseg", "k_samples", "r_interior", "ctrl", "ctrl_off", "tau", "tau_off",
+              "stroke_w", "color", "opacity", "opa_off", "order", "gauss_off"):
+        setattr(cv, f, 4096)                               # never dereferenced on the host
+    return cv
+
+
+def _fake_bins(workspace_bytes=1 << 40):
+    return bz.Bins(1024, 4096, 4096, 4096, workspace_bytes, 4096)
+
+
+def test_sample_bin_checks_both_calls_arguments_on_host():
+    """bz_sample_bin refuses what bz_sample or bz_bin would, before any launch."""
+    lib = bz.load_library()
+    o = _opts()
+    cv = _fake_curves()
+    g = bz.Gaussians(8, 0, 4096)                           # capacity below n_gauss
+    assert lib.bz_sample_bin(C.byref(cv), C.byref(o), C.byref(g), C.byref(_fake_bins()),
+                             None) == bz.BZ_ERR_CAPACITY
+    g = bz.Gaussians(16, 0, 4096)
+    assert lib.bz_sample_bin(C.byref(cv), C.byref(o), C.byref(g), None, None) == bz.BZ_ERR_ARG
+    assert lib.bz_sample_bin(C.byref(cv), C.byref(o), C.byref(g), C.byref(_fake_bins(256)),
+                             None) == bz.BZ_ERR_CAPACITY       # workspace too small
+    misaligned = bz.Gaussians(16, 0, 4104)
+    assert lib.bz_sample_bin(C.byref(cv), C.byref(o), C.byref(misaligned),
+                             C.byref(_fake_bins()), None) == bz.BZ_ERR_ARG
+
+
+def test_fused_forward_checks_its_loss_arguments_on_host():
+    """bz_render_fwd_l2: no target or gradient, d_image on the image itself or
+    a non-finite scale are refused before any launch."""
+    lib = bz.load_library()
+    o = _opts()
+    g = bz.Gaussians(16, 16, 4096)
+    b = _fake_bins()
+    img, tgt, dimg = 8192, 16384, 24576
+    for args in ((img, None, 1.0, dimg), (img, tgt, 1.0, None), (img, tgt, 1.0, img),
+                 (img, tgt, float("inf"), dimg), (img, tgt, float("nan"), dimg)):
+        im, t, sc, d = args
+        assert lib.bz_render_fwd_l2(C.byref(g), C.byref(b), C.byref(o), im, None, t, C.c_float(sc),
+                                    d, None, None) == bz.BZ_ERR_ARG, args
+
+
 def _batch_layout(sizes, goff, bg=None, tile=(16, 16)):
     lib = bz.load_library()
     o = bz.make_opts(1, 1, (1.0, 1.0, 1.0), bz.RenderOptions(tile_w=tile[0], tile_h=tile[1]))

@@ -184,10 +184,11 @@ def bench_curvenet(a):
         y = torch.empty((d.n, d.ho, d.wo, d.k), dtype=torch.int16, device="cuda")
         dy = torch.randn((d.n, d.ho, d.wo, d.k), device="cuda")
         dw = torch.empty(net.params[i][0].shape, device="cuda")
+        db = torch.empty(net.params[i][1].shape, device="cuda")
         dx = torch.empty(acts[i].shape, device="cuda")
         w = net._bf[i]
         calls = {"fwd": lambda: cnn.conv_fwd(d, acts[i], w, net.params[i][1], True, y_bf16=y),
-                 "bwd_weight": lambda: cnn.conv_bwd_weight(d, dy, acts[i], dw),
+                 "bwd_weight": lambda: cnn.conv_bwd_weight(d, dy, acts[i], dw, db),
                  "bwd_data": lambda: cnn.conv_bwd_data(d, dy, w, dx, x_mask=acts[i])}
         for name, fn in calls.items():
             if name == "bwd_data" and i == 0:
@@ -212,13 +213,25 @@ def bench_curvenet(a):
         net.backward(dz)
     e1.record()
     torch.cuda.synchronize()
+    step_ms_eager = e0.elapsed_time(e1) / a.steps
+    # the same step recorded once as a graph and replayed: no host gaps
+    tg = cnn.TrainGraph(net, x, dz)
+    tg.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(a.steps):
+        tg.replay()
+    e1.record()
+    torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / a.steps
     dom = max(rows, key=lambda r: r["ms"])
     out = {"metric": "curve-proposal network training steps/s (forward + backward)",
            "value": 1000.0 / step_ms, "unit": "steps/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": step_ms, "higher_is_better": True,
            "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
-           "config": {"workload": "curvenet-32x32-patches", "batch": a.batch},
+           "config": {"workload": "curvenet-32x32-patches", "batch": a.batch,
+                      "launch": "one HIP graph replay per step"},
+           "ms_per_step_eager": step_ms_eager,
            "roofline": {"kernel": f"k_igemm layer {dom['layer']} {dom['pass']}", "bound": "mfma",
                         "achieved": dom["tflops"], "peak": PEAK_BF16_MFMA_TFLOPS,
                         "unit": "TFLOP/s", "frac": dom["tflops"] / PEAK_BF16_MFMA_TFLOPS,

@@ -201,6 +201,36 @@ MARGIN = 0.25            # control points may leave the patch by a quarter side
 W_MIN, W_SPAN = 0.5, 3.5
 
 
+class TrainGraph:
+    """Forward and backward of ``net`` on fixed buffers ``x`` (BF16 bits,
+    [n, 32, 32, 3]) and ``dz`` (FP32 [n, 104]), recorded once as a HIP graph
+    and replayed with one launch.  Eagerly the step issues ~25 small launches
+    from Python and the GPU waits on the host between them.  After a replay
+    ``z`` holds the outputs and every parameter's ``.grad`` the gradients
+    (buffers of the graph, overwritten by the next replay); the BF16 weight
+    copies are read as they are at replay time."""
+
+    def __init__(self, net: "CurveNet", x, dz, warmup: int = 2):
+        torch = net.torch
+        self.net, self.x, self.dz = net, x, dz
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                net.forward(x)
+                net.backward(dz)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.z = net.forward(x)
+            net.backward(dz)
+
+    def replay(self):
+        self.graph.replay()
+        return self.z
+
+
 def decode(z, side=PATCH):
     """Raw outputs [n, 104] -> normalised curve parameters [n, 8, 13]:
     control points in patch sides (origin at the patch corner), then

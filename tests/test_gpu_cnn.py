@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import cnn_oracle as co
+from tests.helpers import rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -157,3 +158,33 @@ def test_network_forward_and_backward_match_reference(torch_cuda):
         w, b = net.params[i]
         assert rel_l2(w.grad.cpu().numpy().reshape(dw.shape), dw) <= 1e-2, i
         assert rel_l2(b.grad.cpu().numpy(), db) <= 1e-2, i
+
+
+def test_train_graph_replays_match_the_eager_step(torch_cuda):
+    """The recorded forward+backward replayed four times, with eager work and
+    synchronisations between the replays, gives the eager step's outputs and
+    gradients each time (the filter gradients to float-atomic order)."""
+    torch = torch_cuda
+    from paper_2503_16424_amd import cnn
+    net = cnn.CurveNet(seed=3)
+    net.sync_weights()
+    rng = np.random.default_rng(4)
+    x = torch.as_tensor(rng.uniform(0, 1, (64, 32, 32, 3)).astype(np.float32),
+                        device="cuda").to(torch.bfloat16).view(torch.int16)
+    dz = torch.as_tensor(rng.standard_normal((64, cnn.OUT)).astype(np.float32), device="cuda")
+    z_ref = net.forward(x).clone()
+    net.backward(dz)
+    torch.cuda.synchronize()
+    g_ref = [(w.grad.clone(), b.grad.clone()) for w, b in net.params]
+    tg = cnn.TrainGraph(net, x, dz)
+    for rep in range(4):
+        for w, b in net.params:                      # eager work between the replays
+            w.grad.fill_(7.0)
+            b.grad.fill_(7.0)
+        torch.cuda.synchronize()
+        z = tg.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(z, z_ref), rep
+        for (w, b), (gw, gb) in zip(net.params, g_ref):
+            assert rel_l2(w.grad.cpu().numpy(), gw.cpu().numpy()) <= 1e-5, rep
+            assert rel_l2(b.grad.cpu().numpy(), gb.cpu().numpy()) <= 1e-5, rep

@@ -136,10 +136,14 @@ __host__ __device__ inline int batch_find(const bz_canvas *cv, int n_canvas, int
 }
 
 // LDS of the per-curve backward: boundary samples (2 x double2 per column),
-// Bernstein weights and segment per column, and the four per-Gaussian stencil
-// terms (float2 each; the sample-point gradients overwrite the first).
+// Bernstein weights and segment per column, then, from a 16-byte boundary,
+// the four per-Gaussian stencil terms (float2 each; the sample-point
+// gradients overwrite the first).
+__host__ __device__ inline int64_t stage2_terms_offset(int64_t max_k) {
+    return (2 * 16 * max_k + 16 * max_k + 4 * max_k + 15) & ~int64_t(15);
+}
 inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
-    return 2 * 16 * max_k + 16 * max_k + 4 * max_k + 4 * 8 * max_gauss;
+    return stage2_terms_offset(max_k) + 4 * 8 * max_gauss;
 }
 
 // Tiles of a Gaussian record (mean hi + lo, conic Q, opacity): the tile

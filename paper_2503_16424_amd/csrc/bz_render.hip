@@ -836,7 +836,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     double2 *XB = lds_xy + lk;
     float4 *Bw = reinterpret_cast<float4 *>(lds_xy + 2 * lk);          // [K] Bernstein weights
     int *Bs = reinterpret_cast<int *>(Bw + lk);                        // [K] segment of column k
-    float2 *Tm = reinterpret_cast<float2 *>(Bs + lk);                  // mean term, then Xbar
+    float2 *Tm = reinterpret_cast<float2 *>(reinterpret_cast<char *>(lds_xy) +
+                                            stage2_terms_offset(lk));  // mean term, then Xbar
     float2 *Tf = Tm + lg;                                              // along-row term
     float2 *Th = Tf + lg;                                              // across-row term
     float2 *Tv = Th + lg;                                              // tangent term

@@ -159,8 +159,7 @@ def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=No
         logged = step % cfg.log_every == 0 or step == cfg.steps - 1
         if logged:
             ev[0].record()
-        rast.sample()
-        rast.bin()
+        rast.sample_bin()
         if (logged or step % cfg.check_every == 0) and rast.ensure_capacity():
             res.regrown += 1
             rast.bin()

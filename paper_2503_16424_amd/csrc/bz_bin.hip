@@ -75,7 +75,7 @@ __device__ inline void gauss_canvas(const bz_canvas *cv, int n_canvas, int64_t g
 }
 
 __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, int64_t n, int W,
-                                               int H, int tw, int th, float two_p,
+                                               int H, float inv_tw, float inv_th, float two_p,
                                                const bz_canvas *__restrict__ cv, int n_canvas,
                                                uint32_t *__restrict__ counts,
                                                ushort4 *__restrict__ rects, int64_t *status) {
@@ -86,7 +86,8 @@ __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, i
     gauss_canvas(cv, n_canvas, g, W, H, tiles_x_unused, base_unused);
     ushort4 rc;
     bool finite;
-    const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, tw, th, two_p, rc, finite);
+    const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, inv_tw, inv_th, two_p, rc,
+                                   finite);
     if (!finite) atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
     counts[g] = cnt;
     rects[g] = rc;
@@ -577,8 +578,8 @@ hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_
     const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
     const int ncv = o.batch ? o.batch->n_canvas : 0;
     hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, (const float4 *)rec_f, n,
-                       o.width, o.height, o.tile_w, o.tile_h, support_two_p(o), cv, ncv, u.counts,
-                       u.rects, b.status);
+                       o.width, o.height, 1.0f / o.tile_w, 1.0f / o.tile_h, support_two_p(o), cv,
+                       ncv, u.counts, u.rects, b.status);
     return bin_finish(u, n, o, b, s);
 }
 
@@ -588,7 +589,8 @@ hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, c
     const BinBufs u = bin_bufs(o, n, b);
     bin_prepare(u, b, s);
     if (n == 0) return hipGetLastError();
-    const BinCount bc = {u.counts, u.rects, b.status, o.tile_w, o.tile_h, support_two_p(o)};
+    const BinCount bc = {u.counts, u.rects, b.status, 1.0f / o.tile_w, 1.0f / o.tile_h,
+                         support_two_p(o)};
     hipError_t e = launch_sample(c, o, rec, &bc, s);
     if (e != hipSuccess) return e;
     return bin_finish(u, n, o, b, s);

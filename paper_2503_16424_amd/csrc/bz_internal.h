@@ -151,16 +151,21 @@ inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
 // (1/2 d^T Q d <= two_p / 2) reaches on a W x H canvas, and the number of
 // tiles in it; 0 with rect (1, 1, 0, 0) when it reaches none or Q is not
 // positive definite.  finite: the record's mean, conic and opacity are finite.
-__device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, int tw, int th,
-                                     float two_p, ushort4 &rc, bool &finite) {
+// The half extents use the hardware reciprocal and square root (about one
+// ulp): the box slack (kCullSlackBox, kCullPadBox) exceeds their error by
+// orders of magnitude, so the box stays conservative.  inv_tw, inv_th: 1 /
+// tile width and height.
+__device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv_tw,
+                                     float inv_th, float two_p, ushort4 &rc, bool &finite) {
     const float mx = m.x + m.z, my = m.y + m.w;
     const float det = q.x * q.z - q.y * q.y;
     finite = isfinite(mx) && isfinite(my) && isfinite(q.x) && isfinite(q.y) && isfinite(q.z) &&
              isfinite(q.w);
     rc = make_ushort4(1, 1, 0, 0);
     if (!(finite && q.x > 0.f && q.z > 0.f && det > 0.f && isfinite(det))) return 0u;
-    const float hx = sqrtf(two_p * q.z / det) * kCullSlackBox + kCullPadBox;
-    const float hy = sqrtf(two_p * q.x / det) * kCullSlackBox + kCullPadBox;
+    const float pd = two_p * __builtin_amdgcn_rcpf(det);
+    const float hx = __builtin_amdgcn_sqrtf(pd * q.z) * kCullSlackBox + kCullPadBox;
+    const float hy = __builtin_amdgcn_sqrtf(pd * q.x) * kCullSlackBox + kCullPadBox;
     // pixel x covers centre x + 1/2
     float fx0 = ceilf(mx - hx - 0.5f), fx1 = floorf(mx + hx - 0.5f);
     float fy0 = ceilf(my - hy - 0.5f), fy1 = floorf(my + hy - 0.5f);
@@ -169,8 +174,11 @@ __device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, int tw, i
     fx1 = fminf(fx1, (float)(W - 1));
     fy1 = fminf(fy1, (float)(H - 1));
     if (!(fx0 <= fx1 && fy0 <= fy1)) return 0u;
-    const int tx0 = (int)fx0 / tw, tx1 = (int)fx1 / tw;
-    const int ty0 = (int)fy0 / th, ty1 = (int)fy1 / th;
+    // tile of pixel p (a whole number below 2^16): (p + 1/2) / t lies at least
+    // 1 / (2t) from a whole number, far beyond the float error of the
+    // product, so truncating it gives p / t exactly
+    const int tx0 = (int)((fx0 + 0.5f) * inv_tw), tx1 = (int)((fx1 + 0.5f) * inv_tw);
+    const int ty0 = (int)((fy0 + 0.5f) * inv_th), ty1 = (int)((fy1 + 0.5f) * inv_th);
     rc = make_ushort4(tx0, ty0, tx1, ty1);
     return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }
@@ -182,7 +190,7 @@ struct BinCount {
     uint32_t *counts;
     ushort4 *rects;
     int64_t *status;
-    int tw, th;
+    float inv_tw, inv_th;
     float two_p;
 };
 

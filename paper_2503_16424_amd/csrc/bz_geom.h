@@ -140,6 +140,27 @@ __device__ inline double2 sample_at(const CurveView &v, const double2 *XA, const
     return make_double2((1.0 - t) * a.x + t * b.x, (1.0 - t) * a.y + t * b.y);
 }
 
+// 1/x and 1/sqrt(x): for positive normal finite x the hardware estimate
+// (relative error near 2^-22) refined by two Newton steps, each of which
+// squares the relative error, so the result is within an ulp or two of the
+// double quotient, far cheaper than the IEEE division and square root
+// sequences; anything else (zero, subnormal, infinite, NaN) takes those.
+constexpr double kMinNormal = 2.2250738585072014e-308;
+constexpr double kMaxFinite = 1.7976931348623157e308;
+__device__ inline double rcp_f64(double x) {
+    if (!(x >= kMinNormal && x <= kMaxFinite)) return 1.0 / x;
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double rsqrt_f64(double x) {
+    if (!(x >= kMinNormal && x <= kMaxFinite)) return 1.0 / sqrt(x);
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    return y * fma(-hx * y, y, 1.5);
+}
+
 struct Geom {
     double2 mu;
     double sx2, sy2;       // dilated squared scales
@@ -181,11 +202,14 @@ __device__ inline void gauss_geom(const CurveView &v, const double2 *XA, const d
     g.km = k > 0 ? k - 1 : 0;
     double2 Pp = sample_at(v, XA, XB, r, g.kp), Pm = sample_at(v, XA, XB, r, g.km);
     g.v = make_double2(Pp.x - Pm.x, Pp.y - Pm.y);
-    g.nv = sqrt(g.v.x * g.v.x + g.v.y * g.v.y);
-    if (g.nv > 0.0) {
-        g.cs = g.v.x / g.nv;
-        g.sn = g.v.y / g.nv;
+    const double nv2 = g.v.x * g.v.x + g.v.y * g.v.y;
+    if (nv2 > 0.0) {
+        const double inv = rsqrt_f64(nv2);
+        g.nv = nv2 * inv;
+        g.cs = g.v.x * inv;
+        g.sn = g.v.y * inv;
     } else {
+        g.nv = 0.0;
         g.cs = 1.0;
         g.sn = 0.0;
     }

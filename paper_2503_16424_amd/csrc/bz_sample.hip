@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8
             int r = idx / v.K, k = idx - r * v.K;
             Geom g;
             gauss_geom(v, XA, XB, r, k, inv_rho2, s0, g);
-            double a = 1.0 / g.sx2, b = 1.0 / g.sy2;
+            const double a = rcp_f64(g.sx2), b = rcp_f64(g.sy2);
             double qxx = g.cs * g.cs * a + g.sn * g.sn * b;
             double qxy = g.cs * g.sn * (a - b);
             double qyy = g.sn * g.sn * a + g.cs * g.cs * b;

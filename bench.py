@@ -187,7 +187,9 @@ def bench_curvenet(a):
         db = torch.empty(net.params[i][1].shape, device="cuda")
         dx = torch.empty(acts[i].shape, device="cuda")
         w = net._bf[i]
-        calls = {"fwd": lambda: cnn.conv_fwd(d, acts[i], w, net.params[i][1], True, y_bf16=y),
+        # layer 0's forward reads the zero-padded input (net._x8) with its own descriptor
+        df, xf = net._dsf[i], (net._x8 if i == 0 else acts[i])
+        calls = {"fwd": lambda: cnn.conv_fwd(df, xf, w, net.params[i][1], True, y_bf16=y),
                  "bwd_weight": lambda: cnn.conv_bwd_weight(d, dy, acts[i], dw, db),
                  "bwd_data": lambda: cnn.conv_bwd_data(d, dy, w, dx, x_mask=acts[i])}
         for name, fn in calls.items():

@@ -107,6 +107,10 @@ PER_CURVE = 13           # 4 control points (8), width, colour (3), opacity
 OUT = CURVES * PER_CURVE
 LAYERS = ((3, 64, 3, 1, 1), (64, 64, 3, 2, 1), (64, 64, 3, 2, 1), (64, 64, 3, 2, 1))  # c, k, r, s, p
 HEAD_IN = 64 * 4 * 4
+# Input channels of layer 0 as its forward reads them: the 3 of the patch and 5
+# zeros, so that the convolution gathers 8 BF16 channels per 16-byte load; the
+# weights of the zero channels are zero, so the outputs are those of 3.
+C0 = 8
 
 
 class CurveNet:
@@ -127,12 +131,17 @@ class CurveNet:
         self.params.append((wh.to(self.dev).requires_grad_(),
                             torch.zeros(OUT, device=self.dev).requires_grad_()))
         self._bf = [torch.empty(w.shape, dtype=torch.int16, device=self.dev) for w, _ in self.params]
+        k0, r0 = LAYERS[0][1], LAYERS[0][2]
+        self._bf[0] = torch.zeros((k0, r0, r0, C0), dtype=torch.int16, device=self.dev)
         self._acts = None
+        self._x8 = None
 
     def tensors(self):
         return [t for wb in self.params for t in wb]
 
     def _shapes(self, n):
+        """Descriptors of the layers (layer 0 with its 3 real input channels:
+        the backward's)."""
         ds, h = [], PATCH
         for (c, k, r, s, p) in LAYERS:
             d = conv_desc(n, h, h, c, k, r, s, p)
@@ -141,26 +150,42 @@ class CurveNet:
         ds.append(conv_desc(n, 1, 1, HEAD_IN, OUT, 1, 1, 0))
         return ds
 
+    def _fwd_shapes(self, n):
+        """The forward's descriptors: layer 0 reads C0 channels."""
+        ds = self._shapes(n)
+        c, k, r, s, p = LAYERS[0]
+        ds[0] = conv_desc(n, PATCH, PATCH, C0, k, r, s, p)
+        return ds
+
     def sync_weights(self):
-        """FP32 weights -> the BF16 copies the kernels read."""
-        with self.torch.no_grad():
-            for (w, _), wb in zip(self.params, self._bf):
-                to_bf16(w.detach().contiguous(), wb)
+        """FP32 weights -> the BF16 copies the kernels read (layer 0's padded
+        to C0 input channels with zeros)."""
+        torch = self.torch
+        with torch.no_grad():
+            for i, ((w, _), wb) in enumerate(zip(self.params, self._bf)):
+                if i == 0:
+                    wp = torch.zeros(wb.shape, dtype=torch.float32, device=self.dev)
+                    wp[..., :w.shape[-1]] = w.detach()
+                    to_bf16(wp, wb)
+                else:
+                    to_bf16(w.detach().contiguous(), wb)
 
     def forward(self, x):
         """x: BF16 bits (int16) [n, 32, 32, 3] -> raw outputs FP32 [n, 104]."""
         torch = self.torch
         n = x.shape[0]
-        ds = self._shapes(n)
+        ds, dsf = self._shapes(n), self._fwd_shapes(n)
+        x8 = torch.nn.functional.pad(x, (0, C0 - x.shape[-1]))      # BF16 zero bits
         acts = [x]
         for i in range(len(LAYERS)):
-            d = ds[i]
+            d = dsf[i]
             y = torch.empty((n, d.ho, d.wo, d.k), dtype=torch.int16, device=self.dev)
-            conv_fwd(d, acts[-1], self._bf[i], self.params[i][1], relu=True, y_bf16=y)
+            conv_fwd(d, x8 if i == 0 else acts[-1], self._bf[i], self.params[i][1], relu=True,
+                     y_bf16=y)
             acts.append(y)
         z = torch.empty((n, OUT), dtype=torch.float32, device=self.dev)
         conv_fwd(ds[-1], acts[-1], self._bf[-1], self.params[-1][1], relu=False, y=z)
-        self._acts, self._ds = acts, ds
+        self._acts, self._ds, self._dsf, self._x8 = acts, ds, dsf, x8
         return z
 
     def backward(self, dz):

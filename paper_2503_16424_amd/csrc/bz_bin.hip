@@ -56,13 +56,6 @@ __device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t *s_wave, uint64_
     return before + x - v;
 }
 
-__global__ void k_reset(int64_t *status) {
-    if (threadIdx.x == 0) {
-        status[0] = 0;
-        status[1] = 0;
-    }
-}
-
 // canvas (W x H) of Gaussian g: the single canvas, or its batch canvas
 __device__ inline void gauss_canvas(const bz_canvas *cv, int n_canvas, int64_t g, int &W, int &H,
                                     int &tiles_x, uint32_t &tile_base) {
@@ -380,9 +373,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     }
 }
 
-__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+// Start of a binning: the status words (pair count, flags) and every tile's
+// range cleared, in one launch.
+__global__ void k_bin_clear(int64_t *status, uint32_t *ranges, int64_t n_ranges) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_ranges) ranges[i] = 0u;
+    if (i < 2) status[i] = 0;
 }
 
 // First and one-past-last position of every tile: thread t looks at the
@@ -528,9 +524,9 @@ float support_two_p(const bz_opts &o) { return 2.0f * (-logf(o.g_min)); }
 
 // Status and ranges cleared: before anything of the call writes a flag.
 void bin_prepare(const BinBufs &u, const bz_bins &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, b.status);
-    hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(2 * u.L.n_tiles, 256)), dim3(256), 0, s, b.ranges,
-                       2 * u.L.n_tiles, 0u);
+    const int64_t nr = 2 * u.L.n_tiles;
+    hipLaunchKernelGGL(k_bin_clear, dim3(cdiv(nr > 2 ? nr : 2, 256)), dim3(256), 0, s, b.status,
+                       b.ranges, nr);
 }
 
 // From the per-Gaussian tile counts and rectangles: offsets, pairs, sort, ranges.

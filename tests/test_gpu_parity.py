@@ -384,6 +384,13 @@ def test_largest_curves_and_empty_scene(torch_cuda):
     assert np.all(img == empty.bg[:, None, None]) and r.pairs_required() == 0
     r.backward(torch.zeros((3, 24, 40), device="cuda"))
     torch.cuda.synchronize()
+    # the fused step on it: background image, the L2 gradient of the background
+    tgt = np.full((3, 24, 40), 0.5, np.float32)
+    r.step(torch.as_tensor(tgt, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.all(r.image.cpu().numpy() == empty.bg[:, None, None]) and r.pairs_required() == 0
+    want = np.float32(2.0 / tgt.size) * (np.broadcast_to(empty.bg[:, None, None], tgt.shape) - tgt)
+    assert np.array_equal(r.d_image.cpu().numpy(), want)
 
 
 def test_paper_scale_backward_on_a_band(torch_cuda):

@@ -50,9 +50,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper_2048", choices=["paper_2048", "open_512",
-                                                                 "tiny_128", "batched_64",
-                                                                 "curvenet"])
+    ap.add_argument("--workload", default="paper_2048",
+                    choices=["paper_2048", "paper_2048_e400", "paper_analog_open",
+                             "paper_analog_closed", "open_512", "tiny_128", "batched_64",
+                             "curvenet"])
     ap.add_argument("--batch", type=int, default=256, help="curvenet: patches per step")
     ap.add_argument("--persistent", action="store_true",
                     help="persistent blend launches (tiles from a counter)")
@@ -344,6 +345,13 @@ def main():
     tw, th = (int(v) for v in a.tile.split("x"))
     if a.workload == "paper_2048":
         sc, target = scenes.paper_2048(0), scenes.target_noise(1, 2048, 2048)
+    elif a.workload == "paper_2048_e400":
+        sc, target = scenes.paper_2048_e400(0), scenes.target_noise(1, 2048, 2048)
+    elif a.workload.startswith("paper_analog"):
+        # the frame and curve count of the paper's speed comparison (2040x1344,
+        # 2,048 open or closed curves): context beside its published timings
+        sc = scenes.paper_analog(0, closed=a.workload.endswith("closed"))
+        target = scenes.target_noise(1, sc.width, sc.height)
     elif a.workload == "open_512":
         sc, target = scenes.open_512(0), scenes.target_noise(1, 512, 512)
     else:

@@ -145,7 +145,13 @@ typedef struct {
  *   [0..1]  mean, high float part (x, y)
  *   [2..3]  mean, low part: mean = hi + lo to ~2^-48 relative (the mean is
  *           computed in double precision)
- *   [4..6]  Q = Sigma^-1 as (Qxx, Qxy, Qyy); p = 1/2 d^T Q d, d = pixel - mean
+ *   [4..6]  shape (e.x, e.y, k) in the covariance's principal frame (Eq. RSSR):
+ *           e = (cos t, sin t) / sigma_x with (cos t, sin t) the unit tangent of
+ *           Eq. rotation, k = sigma_x / sigma_y (dilated scales), so that
+ *           Q = Sigma^-1 = e e^T + k^2 e' e'^T with e' = (-e.y, e.x), and
+ *           p = 1/2 d^T Q d = 1/2 ((e . d)^2 + k^2 (e' . d)^2), d = pixel - mean.
+ *           (A sum of squares keeps p accurate in float32 for elongated
+ *           Gaussians, where the expanded conic form cancels.)
  *   [7]     opacity o
  *   [8..10] colour
  *   [11]    curve id (int32 bit pattern)
@@ -200,7 +206,8 @@ typedef struct {
 /* Gradients.  Per curve, same layouts as the inputs: d_ctrl [n_ctrl][2],
  * d_width [n_curves], d_color [n_curves][3], d_opacity [n_opa].  d_gauss is
  * required scratch and output: per-Gaussian gradients as 9 planes of n_gauss
- * floats: (mean x, mean y, Qxx, Qxy, Qyy, o, r, g, b).  bz_render_bwd overwrites
+ * floats: (mean x, mean y, Qxx, Qxy, Qyy, o, r, g, b), the conic entries being
+ * those of p = 1/2 (Qxx dx^2 + 2 Qxy dx dy + Qyy dy^2).  bz_render_bwd overwrites
  * all of them (the caller need not zero them). */
 typedef struct {
     float *d_ctrl, *d_width, *d_color, *d_opacity;

@@ -363,7 +363,13 @@ typedef struct {
     int32_t n;          /* contributors so far */
     contrib_t *list;    /* only kept when the reverse pass needs it */
     int32_t cap;
+    double margin;      /* smallest relative distance of a decision to its threshold */
 } pix_t;
+
+/* Relative distance of v from the threshold t of a comparison (|v - t| / t). */
+static double rel_margin(double v, double t) {
+    return fabs(v - t) / t;
+}
 
 /* Evaluate Gaussian g at pixel (x, y) and composite it (one step of the
  * front-to-back loop).  Returns 1 when the Gaussian contributed. */
@@ -374,8 +380,14 @@ static int blend_step(const blend_t *b, pix_t *px, int64_t g, int x, int y, int 
     const double *Q = b->conic + 3 * g;
     double p = 0.5 * (Q[0] * dx * dx + 2.0 * Q[1] * dx * dy + Q[2] * dy * dy);
     double G = exp(-p);
+    /* decision margins: the support test G > g_min, the clamp a_raw > alpha_max
+       and the stop T < t_min, each as a relative distance to its threshold */
+    double m = rel_margin(G, b->g_min);
+    if (m < px->margin) px->margin = m;
     if (!(G > b->g_min)) return 0;                          /* outside the truncated support */
     double a_raw = b->opac[g] * (G - b->g_min) / (1.0 - b->g_min);
+    m = rel_margin(a_raw, b->alpha_max);
+    if (m < px->margin) px->margin = m;
     int clamped = a_raw > b->alpha_max;
     double alpha = clamped ? b->alpha_max : a_raw;
     if (keep) {
@@ -393,6 +405,10 @@ static int blend_step(const blend_t *b, pix_t *px, int64_t g, int x, int y, int 
     for (int ch = 0; ch < 3; ++ch) px->C[ch] += alpha * px->T * b->color[3 * g + ch];
     px->T = px->T * (1.0 - alpha);
     px->n += 1;
+    if (b->t_min > 0.0) {
+        m = rel_margin(px->T, b->t_min);
+        if (m < px->margin) px->margin = m;
+    }
     if (px->T < b->t_min) px->done = 1;                     /* include, then stop */
     return 1;
 }
@@ -481,12 +497,19 @@ static int check_opts(int W, int H, double g_min, double alpha_max, double t_min
  *   d_gauss [n][9] accumulated: (mu_x, mu_y, Qxx, Qxy, Qyy, o, r, g, b)
  *   counters[0] = contributing (pixel, Gaussian) pairs, [1] = pairs inside the
  *   bounding boxes that were tested, [2] = pixels that terminated early.
+ *   margin [H][W] (may be NULL): per pixel, the smallest relative distance
+ *   |v - t| / t of any decision the pixel took to its threshold t: G > g_min
+ *   (every tested pair), alpha_raw > alpha_max and T < t_min (contributors).
+ *   A small margin marks a pixel where a lower-precision evaluation may take
+ *   the other branch; the truncated kernel, the clamp and include-then-stop
+ *   keep every such flip's effect on the image of the order of the margin
+ *   (or at most t_min for the stop).
  */
 int orc_render(int64_t n, const double *mu, const double *conic, const double *opac,
                const double *color, int W, int H, const double *bg, double g_min,
                double alpha_max, double t_min, int ya, int yb, int brute, double *image,
                double *t_final, int32_t *n_contrib, const double *d_image, double *d_gauss,
-               int64_t *counters) {
+               int64_t *counters, double *margin) {
     int st = check_opts(W, H, g_min, alpha_max, t_min);
     if (st) return st;
     if (ya < 0) ya = 0;
@@ -527,6 +550,7 @@ int orc_render(int64_t n, const double *mu, const double *conic, const double *o
                 row[x].C[0] = row[x].C[1] = row[x].C[2] = 0.0;
                 row[x].done = 0;
                 row[x].n = 0;
+                row[x].margin = INFINITY;
             }
             /* Every pixel sees the row's candidates in draw order. */
             for (int64_t q = rw.start[y]; q < rw.start[y + 1]; ++q) {
@@ -544,6 +568,7 @@ int orc_render(int64_t n, const double *mu, const double *conic, const double *o
                     image[(size_t)ch * H * W + pi] = px->C[ch] + px->T * b.bg[ch];
                 if (t_final) t_final[pi] = px->T;
                 if (n_contrib) n_contrib[pi] = px->n;
+                if (margin) margin[pi] = px->margin;
                 c2 += px->done;
                 if (keep) {
                     double gbar[3] = {d_image[pi], d_image[(size_t)H * W + pi],
@@ -587,6 +612,7 @@ int orc_render_pixels(int64_t n, const double *mu, const double *conic, const do
         pix_t p;
         memset(&p, 0, sizeof(p));
         p.T = 1.0;
+        p.margin = INFINITY;
         if (x >= 0 && x < W && y >= 0 && y < H) {
             for (int64_t g = 0; g < n && !p.done; ++g) {
                 if (x < b.x0[g] || x > b.x1[g] || y < b.y0[g] || y > b.y1[g]) continue;
@@ -598,6 +624,101 @@ int orc_render_pixels(int64_t n, const double *mu, const double *conic, const do
         ncontrib[i] = p.n;
     }
     free_ranges(&b);
+    return ORC_OK;
+}
+
+/*
+ * Depth complexity per screen tile of tw x th pixels (row-major tiles):
+ *   depth_contrib[t]: distinct curves with at least one Gaussian that
+ *       contributes (G > g_min before the pixel stopped) to a pixel of tile t;
+ *   depth_support[t]: distinct curves with at least one Gaussian whose support
+ *       bounding box (the culling box of the forward pass) reaches tile t.
+ * curve[g] is the curve index of Gaussian g (0 .. n_curves-1).  The forward
+ * pass is re-run tile by tile, pixel by pixel in draw order.
+ */
+int orc_tile_depth(int64_t n, const double *mu, const double *conic, const double *opac,
+                   const int32_t *curve, int n_curves, int W, int H, double g_min,
+                   double alpha_max, double t_min, int tw, int th, int32_t *depth_contrib,
+                   int32_t *depth_support) {
+    int st = check_opts(W, H, g_min, alpha_max, t_min);
+    if (st) return st;
+    if (tw <= 0 || th <= 0 || n_curves < 0) return ORC_ERR_ARG;
+    for (int64_t g = 0; g < n; ++g)
+        if (curve[g] < 0 || curve[g] >= n_curves) return ORC_ERR_ARG;
+    static const double no_color[3] = {0.0, 0.0, 0.0};
+    blend_t b;
+    setup_blend(&b, n, mu, conic, opac, no_color, W, H, no_color, g_min, alpha_max, t_min, 0);
+    /* blend_step reads a colour per Gaussian: give it zeros */
+    double *zeros = (double *)calloc((size_t)(n > 0 ? n : 1) * 3, sizeof(double));
+    if (!zeros) return ORC_ERR_MEM;
+    b.color = zeros;
+    st = setup_ranges(&b);
+    if (st) { free_ranges(&b); free(zeros); return st; }
+    int tx_n = (W + tw - 1) / tw, ty_n = (H + th - 1) / th;
+    /* candidates per tile row, in draw order */
+    int64_t *start = (int64_t *)calloc(ty_n + 1, sizeof(int64_t));
+    if (!start) { free_ranges(&b); free(zeros); return ORC_ERR_MEM; }
+    for (int64_t g = 0; g < n; ++g)
+        if (b.y0[g] <= b.y1[g] && b.x0[g] <= b.x1[g])
+            for (int ty = b.y0[g] / th; ty <= b.y1[g] / th; ++ty) start[ty + 1]++;
+    for (int ty = 0; ty < ty_n; ++ty) start[ty + 1] += start[ty];
+    int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (start[ty_n] > 0 ? start[ty_n] : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (ty_n + 1));
+    if (!ids || !fill) {
+        free(ids); free(fill); free(start); free_ranges(&b); free(zeros);
+        return ORC_ERR_MEM;
+    }
+    memcpy(fill, start, sizeof(int64_t) * (ty_n + 1));
+    for (int64_t g = 0; g < n; ++g)
+        if (b.y0[g] <= b.y1[g] && b.x0[g] <= b.x1[g])
+            for (int ty = b.y0[g] / th; ty <= b.y1[g] / th; ++ty) ids[fill[ty]++] = g;
+    free(fill);
+#pragma omp parallel
+    {
+        int32_t *seen_c = (int32_t *)malloc(sizeof(int32_t) * (n_curves > 0 ? n_curves : 1));
+        int32_t *seen_s = (int32_t *)malloc(sizeof(int32_t) * (n_curves > 0 ? n_curves : 1));
+        pix_t *px = (pix_t *)calloc((size_t)tw * th, sizeof(pix_t));
+        if (!seen_c || !seen_s || !px) abort();
+        for (int c = 0; c < n_curves; ++c) seen_c[c] = seen_s[c] = -1;
+#pragma omp for schedule(dynamic, 1)
+        for (int t = 0; t < tx_n * ty_n; ++t) {
+            int ty = t / tx_n, tx = t - ty * tx_n;
+            int xa = tx * tw, xb = xa + tw - 1, ya = ty * th, yb = ya + th - 1;
+            if (xb > W - 1) xb = W - 1;
+            if (yb > H - 1) yb = H - 1;
+            for (int i = 0; i < tw * th; ++i) {
+                px[i].T = 1.0;
+                px[i].done = 0;
+                px[i].n = 0;
+                px[i].margin = INFINITY;
+            }
+            int32_t dc = 0, ds = 0;
+            for (int64_t q = start[ty]; q < start[ty + 1]; ++q) {
+                int64_t g = ids[q];
+                if (b.x1[g] < xa || b.x0[g] > xb || b.y1[g] < ya || b.y0[g] > yb) continue;
+                int c = curve[g];
+                if (seen_s[c] != t) { seen_s[c] = t; ds++; }
+                int x0 = b.x0[g] > xa ? b.x0[g] : xa, x1 = b.x1[g] < xb ? b.x1[g] : xb;
+                int y0 = b.y0[g] > ya ? b.y0[g] : ya, y1 = b.y1[g] < yb ? b.y1[g] : yb;
+                for (int y = y0; y <= y1; ++y)
+                    for (int x = x0; x <= x1; ++x)
+                        if (blend_step(&b, &px[(y - ya) * tw + (x - xa)], g, x, y, 0) &&
+                            seen_c[c] != t) {
+                            seen_c[c] = t;
+                            dc++;
+                        }
+            }
+            depth_contrib[t] = dc;
+            depth_support[t] = ds;
+        }
+        free(seen_c);
+        free(seen_s);
+        free(px);
+    }
+    free(ids);
+    free(start);
+    free_ranges(&b);
+    free(zeros);
     return ORC_OK;
 }
 

@@ -44,7 +44,7 @@ def _load():
         _lib = C.CDLL(_LIB)
         _lib.orc_count_gaussians.restype = C.c_int64
         for name in ("orc_sample", "orc_render", "orc_render_pixels", "orc_chain",
-                     "orc_num_threads"):
+                     "orc_tile_depth", "orc_num_threads"):
             getattr(_lib, name).restype = C.c_int
     return _lib
 
@@ -116,6 +116,7 @@ def render(g: dict, W: int, H: int, bg, opts=None, rows=None, d_image=None, brut
     image = np.zeros((3, H, W))
     t_final = np.ones((H, W))
     n_contrib = np.zeros((H, W), np.int32)
+    margin = np.full((H, W), np.inf)
     counters = np.zeros(4, np.int64)
     dimg = None if d_image is None else _c(d_image, np.float64)
     d_gauss = None if d_image is None else np.zeros((ng, 9))
@@ -123,11 +124,12 @@ def render(g: dict, W: int, H: int, bg, opts=None, rows=None, d_image=None, brut
                         C.c_int(H), _p(bgv), C.c_double(o["g_min"]), C.c_double(o["alpha_max"]),
                         C.c_double(o["t_min"]), C.c_int(y0), C.c_int(y1), C.c_int(int(brute)),
                         _p(image), _p(t_final), _p(n_contrib), _p(dimg), _p(d_gauss),
-                        _p(counters))
+                        _p(counters), _p(margin))
     if st != 0:
         raise ValueError(f"oracle render rejected its arguments (status {st})")
     return dict(image=image, t_final=t_final, n_contrib=n_contrib, d_gauss=d_gauss,
-                pairs=int(counters[0]), tested=int(counters[1]), terminated=int(counters[2]))
+                margin=margin, pairs=int(counters[0]), tested=int(counters[1]),
+                terminated=int(counters[2]))
 
 
 def render_pixels(g: dict, W: int, H: int, bg, xs, ys, opts=None) -> dict:
@@ -149,6 +151,27 @@ def render_pixels(g: dict, W: int, H: int, bg, xs, ys, opts=None) -> dict:
     if st != 0:
         raise ValueError(f"oracle render_pixels rejected its arguments (status {st})")
     return dict(rgb=rgb, t_final=T, n_contrib=nc)
+
+
+def tile_depth(g: dict, n_curves: int, W: int, H: int, tile=(16, 16), opts=None) -> dict:
+    """Depth complexity per tile (row-major tiles of tile[0] x tile[1] px):
+    distinct curves contributing to a pixel of the tile (forward pass of Sec.
+    3.4 re-run per tile) and distinct curves whose support box reaches it."""
+    o = _opts(opts)
+    lib = _load()
+    mu, conic = _c(g["mu"], np.float64), _c(g["conic"], np.float64)
+    opac, curve = _c(g["opac"], np.float64), _c(g["curve"], np.int32)
+    tw, th = tile
+    nt = (-(-W // tw)) * (-(-H // th))
+    dc = np.zeros(nt, np.int32)
+    ds = np.zeros(nt, np.int32)
+    st = lib.orc_tile_depth(C.c_int64(mu.shape[0]), _p(mu), _p(conic), _p(opac), _p(curve),
+                            C.c_int(n_curves), C.c_int(W), C.c_int(H), C.c_double(o["g_min"]),
+                            C.c_double(o["alpha_max"]), C.c_double(o["t_min"]), C.c_int(tw),
+                            C.c_int(th), _p(dc), _p(ds))
+    if st != 0:
+        raise ValueError(f"oracle tile_depth rejected its arguments (status {st})")
+    return dict(contrib=dc, support=ds)
 
 
 def chain(sc, d_gauss: np.ndarray, opts=None) -> dict:

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbz.so")
-SOURCES = ["bz_api.hip", "bz_sample.hip", "bz_bin.hip", "bz_render.hip", "bz_shape.hip", "cnn.hip"]
+SOURCES = ["bz_api.hip", "bz_sample.hip", "bz_bin.hip", "bz_render.hip", "bz_shape.hip", "cnn.hip",
+           "bz_peak.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -75,7 +75,7 @@ EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_batch_layo
            "bz_visit_words", "bz_sample", "bz_sample_bin", "bz_bin",
            "bz_render_fwd", "bz_render_fwd_l2", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
            "bz_curve_area", "bz_area_order_workspace", "bz_area_order", "bz_xing_loss",
-           "bz_l2_grad", "bz_status_str")
+           "bz_l2_grad", "bz_status_str", "bz_peak_run", "bz_peak_work")
 
 _lib = None
 
@@ -135,6 +135,11 @@ def load_library(path: str = LIB_PATH):
     lib.bz_l2_grad.restype = C.c_int
     lib.bz_l2_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p,
                                C.c_void_p, C.c_void_p]
+    lib.bz_peak_run.restype = C.c_int
+    lib.bz_peak_run.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int64,
+                                C.c_void_p]
+    lib.bz_peak_work.restype = C.c_int
+    lib.bz_peak_work.argtypes = [C.c_int32, C.c_int64, C.c_int32, P(C.c_double)]
     _lib = lib
     return lib
 
@@ -519,7 +524,11 @@ class Rasterizer:
     def gaussians_host(self) -> dict:
         r = self.rec[: 12 * self.n_gauss].view(-1, 12).cpu().numpy()
         mu = r[:, 0:2].astype(np.float64) + r[:, 2:4].astype(np.float64)
-        return dict(mu=mu, conic=r[:, 4:7].astype(np.float64), opac=r[:, 7].astype(np.float64),
+        # conic from the principal-frame shape: Q = e e^T + k^2 e' e'^T
+        ex, ey, k = (r[:, j].astype(np.float64) for j in (4, 5, 6))
+        k2 = k * k
+        conic = np.stack([ex * ex + k2 * ey * ey, ex * ey * (1.0 - k2), ey * ey + k2 * ex * ex], 1)
+        return dict(mu=mu, conic=conic, shape=r[:, 4:7].copy(), opac=r[:, 7].astype(np.float64),
                     color=r[:, 8:11].astype(np.float64), curve=r[:, 11].view(np.int32).copy(),
                     hi=r[:, 0:2].copy(), lo=r[:, 2:4].copy())
 

@@ -146,26 +146,46 @@ inline int64_t stage2_lds_bytes(int64_t max_k, int64_t max_gauss) {
     return stage2_terms_offset(max_k) + 4 * 8 * max_gauss;
 }
 
-// Tiles of a Gaussian record (mean hi + lo, conic Q, opacity): the tile
+// Shape of a Gaussian record: e = (cos t, sin t) / sigma_x along the tangent
+// and k = sigma_x / sigma_y (dilated scales), so that
+//   d^T Sigma^-1 d = (e . d)^2 + k^2 (e_perp . d)^2,  e_perp = (-e.y, e.x),
+// a sum of two squares: no cancellation for elongated Gaussians, where the
+// expanded form Qxx dx^2 + 2 Qxy dx dy + Qyy dy^2 loses its value to rounding.
+// The conic entries follow from the same identity.
+__host__ __device__ inline void shape_conic(float ex, float ey, float k, float &qxx, float &qxy,
+                                            float &qyy) {
+    const float k2 = k * k;
+    qxx = fmaf(k2 * ey, ey, ex * ex);
+    qxy = ex * ey * (1.f - k2);
+    qyy = fmaf(k2 * ex, ex, ey * ey);
+}
+
+// Tiles of a Gaussian record (mean hi + lo, shape (e, k), opacity): the tile
 // rectangle (x0, y0, x1, y1) that the bounding box of its truncated support
-// (1/2 d^T Q d <= two_p / 2) reaches on a W x H canvas, and the number of
-// tiles in it; 0 with rect (1, 1, 0, 0) when it reaches none or Q is not
-// positive definite.  finite: the record's mean, conic and opacity are finite.
-// The half extents use the hardware reciprocal and square root (about one
-// ulp): the box slack (kCullSlackBox, kCullPadBox) exceeds their error by
-// orders of magnitude, so the box stays conservative.  inv_tw, inv_th: 1 /
-// tile width and height.
+// (1/2 d^T Sigma^-1 d <= two_p / 2) reaches on a W x H canvas, and the number
+// of tiles in it; 0 with rect (1, 1, 0, 0) when it reaches none or the shape
+// is degenerate.  finite: the record's mean, shape and opacity are finite.
+// Half extents sqrt(two_p Sigma_xx), sqrt(two_p Sigma_yy) with
+// Sigma_xx = (e.x^2 + e.y^2 / k^2) / |e|^4 and Sigma_yy likewise (Sigma =
+// sigma_x^2 t t^T + sigma_y^2 n n^T, no cancellation); they use the hardware
+// reciprocal and square root (about one ulp): the box slack (kCullSlackBox,
+// kCullPadBox) exceeds their error by orders of magnitude, so the box stays
+// conservative.  inv_tw, inv_th: 1 / tile width and height.
 __device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv_tw,
                                      float inv_th, float two_p, ushort4 &rc, bool &finite) {
     const float mx = m.x + m.z, my = m.y + m.w;
-    const float det = q.x * q.z - q.y * q.y;
+    const float e2 = q.x * q.x + q.y * q.y;
     finite = isfinite(mx) && isfinite(my) && isfinite(q.x) && isfinite(q.y) && isfinite(q.z) &&
              isfinite(q.w);
     rc = make_ushort4(1, 1, 0, 0);
-    if (!(finite && q.x > 0.f && q.z > 0.f && det > 0.f && isfinite(det))) return 0u;
-    const float pd = two_p * __builtin_amdgcn_rcpf(det);
-    const float hx = __builtin_amdgcn_sqrtf(pd * q.z) * kCullSlackBox + kCullPadBox;
-    const float hy = __builtin_amdgcn_sqrtf(pd * q.x) * kCullSlackBox + kCullPadBox;
+    if (!(finite && e2 > 0.f && q.z > 0.f && isfinite(e2))) return 0u;
+    const float ik2 = __builtin_amdgcn_rcpf(q.z * q.z);
+    const float ie4 = __builtin_amdgcn_rcpf(e2 * e2);
+    const float sxx = fmaf(q.y * q.y, ik2, q.x * q.x) * ie4;
+    const float syy = fmaf(q.x * q.x, ik2, q.y * q.y) * ie4;
+    if (!(isfinite(sxx) && isfinite(syy))) return 0u;
+    const float hx = __builtin_amdgcn_sqrtf(two_p * sxx) * kCullSlackBox + kCullPadBox;
+    const float hy = __builtin_amdgcn_sqrtf(two_p * syy) * kCullSlackBox + kCullPadBox;
     // pixel x covers centre x + 1/2
     float fx0 = ceilf(mx - hx - 0.5f), fx1 = floorf(mx + hx - 0.5f);
     float fy0 = ceilf(my - hy - 0.5f), fy1 = floorf(my + hy - 0.5f);

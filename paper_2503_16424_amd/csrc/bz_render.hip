@@ -95,48 +95,55 @@ struct TileArgs {
     float l2_scale;
 };
 
-// Entry of the wave's LDS slice: the mean, log2-scaled half conic and the
-// opacity divided by (1 - g_min), colour and opacity * g_min / (1 - g_min).
-// The mean is held one of two ways:
-// - kRel (the front-to-back sweep): relative to the quad's first pixel centre
-//   (qx0, qy0), so a pixel's offset from it is one subtraction from the
-//   pixel's place in the quad (0..7 in x and y).  The record's mean is
-//   hi + lo; hi - qx0 is exact for any Gaussian near the quad, so the relative
-//   mean is rounded once.
-// - otherwise (the reverse pass): hi and lo as stored, the offset taken as
-//   (px - hi) - lo; this keeps the quad origin out of the reverse pass's
-//   registers, which are all in use.
+// Entry of the wave's LDS slice, for both sweeps: the mean relative to the
+// quad's first pixel centre (qx0, qy0), so a pixel's offset from it is one
+// subtraction from the pixel's place in the quad (0..7 in x and y); the record's
+// mean is hi + lo and hi - qx0 is exact for any Gaussian near the quad, so the
+// relative mean is rounded once.  The shape as two scaled axis vectors: with
+// e' = e sqrt(log2(e) / 2) and f = k e', the base-2 exponent of the kernel is
+// p2 = (e' . d)^2 + (f x d)^2 (f x d = f.x dy - f.y dx), a sum of two squares.
 struct Staged {
-    float4 m;   // kRel: mean - (qx0, qy0), 0, 0; else hi.x, hi.y, lo.x, lo.y
-    float4 q;   // A, B, C (p*log2e = A dx^2 + B dx dy + C dy^2), o'
+    float4 m;   // mean - (qx0, qy0), e'.x, e'.y
+    float4 q;   // f.x, f.y, Gaussian id (bit pattern), o' = o / (1 - g_min)
     float4 c;   // r, g, b, o' * g_min
 };
 
-// Load a record and compute its LDS constants.
-template <bool kRel>
+// sqrt(log2(e) / 2): scales the record's axis e so that the squares sum to p2.
+constexpr float kHalfLog2eSqrt = 0.84932180028801907f;
+
+// Load a record and compute its LDS constants.  q receives the record's shape
+// (e.x, e.y, k, o).
 __device__ inline void stage_record(const TileArgs &a, uint32_t id, float qx0, float qy0,
                                     Staged &st, float4 &q) {
     const float4 m = a.rec[3 * (int64_t)id];
     q = a.rec[3 * (int64_t)id + 1];
     const float4 c = a.rec[3 * (int64_t)id + 2];
     const float op = q.w * a.inv_1mg;
-    st.m = kRel ? make_float4((m.x - qx0) + m.z, (m.y - qy0) + m.w, 0.f, 0.f) : m;
-    st.q = make_float4(0.5f * kLog2e * q.x, kLog2e * q.y, 0.5f * kLog2e * q.z, op);
+    const float ex = kHalfLog2eSqrt * q.x, ey = kHalfLog2eSqrt * q.y;
+    st.m = make_float4((m.x - qx0) + m.z, (m.y - qy0) + m.w, ex, ey);
+    st.q = make_float4(q.z * ex, q.z * ey, __uint_as_float(id), op);
     st.c = make_float4(c.x, c.y, c.z, op * a.g_min);
 }
 
 // Load a tile-list entry, compute its LDS constants and test its support
 // against the wave's 8x8 quad (first pixel centre qx0, qy0).
-template <bool kRel>
 __device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, float qy0,
                                    Staged &st) {
     float4 q;
-    stage_record<kRel>(a, id, qx0, qy0, st, q);
-    // offsets of the quad's first pixel centre from the mean (the same value
-    // either way: -((hi - qx0) + lo) = (qx0 - hi) - lo under round to nearest)
-    const float x0 = kRel ? -st.m.x : (qx0 - st.m.x) - st.m.z;
-    const float y0 = kRel ? -st.m.y : (qy0 - st.m.y) - st.m.w;
-    return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, q.x, q.y, q.z, a.box_thr);
+    stage_record(a, id, qx0, qy0, st, q);
+    // offsets of the quad's first pixel centre from the mean
+    const float x0 = -st.m.x, y0 = -st.m.y;
+    float qxx, qxy, qyy;
+    shape_conic(q.x, q.y, q.z, qxx, qxy, qyy);
+    return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, qxx, qxy, qyy, a.box_thr);
+}
+
+// Base-2 exponent p2 = (e' . d)^2 + (f x d)^2 of a staged entry at offset
+// (dx, dy); u = e' . d and w = f x d are returned for the gradient.
+__device__ inline float exponent2(const Staged &st, float dx, float dy, float &u, float &w) {
+    u = fmaf(st.m.z, dx, st.m.w * dy);
+    w = fmaf(st.q.x, dy, -st.q.y * dx);
+    return fmaf(u, u, w * w);
 }
 
 // Word of the visit mask of batch k of tile t inside one quad plane: tile t's
@@ -279,7 +286,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
         bool hit = false;
         if (j < end) {
             Staged st;
-            hit = stage_entry<true>(a, a.ids[j], qx0, qy0, st);
+            hit = stage_entry(a, a.ids[j], qx0, qy0, st);
             my[lane] = st;
         }
         uint64_t mask = __ballot(hit);
@@ -291,8 +298,8 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
             const Staged st = my[b];
             const float dx = lx - st.m.x;
             const float dy = ly - st.m.y;
-            const float p2 = dx * (st.q.x * dx + st.q.y * dy) + st.q.z * dy * dy;
-            const float G = __builtin_amdgcn_exp2f(-p2);
+            float u, w;
+            const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
             // contributors: inside the support and not stopped, as a lane mask
             const uint64_t cm = __builtin_amdgcn_ballot_w64(G > g_min) & ~stopped;
             const float araw = fmaf(st.q.w, G, -st.c.w);
@@ -536,11 +543,13 @@ constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
 
 // Planes 0-5 are summed without their constant factors, which are applied
 // once to the reduced sums.  With f the alpha gradient, o' the scaled opacity,
-// P = f o' G and p = A dx^2 + B dx dy + C dy^2 the base-2 exponent (G = 2^-p):
-// dL/dmean = ln 2 P (dp/d dx, dp/d dy), dL/dQ = -P (dx^2 / 2, dx dy, dy^2 / 2),
+// P = f o' G and p2 = u^2 + w^2 the base-2 exponent (G = 2^-p2, u = e' . d,
+// w = f x d): dL/dmean = ln 2 P (dp2/d dx, dp2/d dy) with dp2/d dx =
+// 2 (u e'.x - w f.y), dp2/d dy = 2 (u e'.y + w f.x) (the 2 joins ln 2 here),
+// dL/dQ = -P (dx^2 / 2, dx dy, dy^2 / 2) (Q the conic, p = d^T Q d / 2),
 // dL/do = f (G - g_min) / (1 - g_min).
 __device__ inline float plane_scale(int v, float inv_1mg) {
-    return v < 2 ? 0.69314718056f : v == 3 ? -1.f : (v == 2 || v == 4) ? -0.5f : v == 5 ? inv_1mg : 1.f;
+    return v < 2 ? 1.38629436112f : v == 3 ? -1.f : (v == 2 || v == 4) ? -0.5f : v == 5 ? inv_1mg : 1.f;
 }
 
 // Tile-list positions pooled in LDS by the backward.  With 16x16 tiles a
@@ -691,7 +700,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                                 Staged st;
                                 float4 q;
                                 const float *q0 = s_q0[w + opaque_zero()];
-                                stage_record<true>(a, id, q0[0], q0[1], st, q);
+                                stage_record(a, id, q0[0], q0[1], st, q);
                                 my[lane] = st;
                             }
                             wave_lds_sync();
@@ -703,7 +712,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                             const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
                             const float *q0 = s_q0[w + opaque_zero()];
-                            hit = stage_entry<true>(a, id, q0[0], q0[1], st);
+                            hit = stage_entry(a, id, q0[0], q0[1], st);
                             my[lane] = st;
                         }
                         vm = __ballot(hit) & in_list;
@@ -718,10 +727,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     const uint32_t pos = lo + (uint32_t)b;
                     const float dx = lx - st.m.x;
                     const float dy = ly - st.m.y;
-                    const float u = st.q.z * dy;
-                    const float t1 = fmaf(st.q.x, dx, st.q.y * dy);
-                    const float p2 = fmaf(dx, t1, dy * u);       // A dx^2 + B dx dy + C dy^2
-                    const float G = __builtin_amdgcn_exp2f(-p2);
+                    float u, w;
+                    const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
                     const bool c = pos < nl && G > g_min;
                     const float araw = fmaf(st.q.w, G, -st.c.w);
                     const bool shaped = c && araw <= amax;       // alpha not clamped
@@ -740,8 +747,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     const float fG = f * G;
                     const float P = fG * st.q.w;
                     const float Pdx = P * dx, Pdy = P * dy;
-                    acc[9 * s + 0] = P * fmaf(st.q.x, dx, t1);          // d p2 / d dx
-                    acc[9 * s + 1] = P * fmaf(st.q.y, dx, u + u);       // d p2 / d dy
+                    acc[9 * s + 0] = P * fmaf(u, st.m.z, -w * st.q.y);   // d p2 / d dx / 2
+                    acc[9 * s + 1] = P * fmaf(u, st.m.w, w * st.q.x);    // d p2 / d dy / 2
                     acc[9 * s + 2] = Pdx * dx;
                     acc[9 * s + 3] = Pdx * dy;
                     acc[9 * s + 4] = Pdy * dy;

@@ -4,8 +4,9 @@
 // rows are evaluated once per curve in double precision (LDS), every lane then
 // emits Gaussians (r, k) of the curve: mean in double, split into a float
 // high part and a float low part; squared scales from the neighbour distances
-// of Eq. sigma plus the dilation sigma0^2; Q = Sigma^-1 from the unit tangent
-// of Eq. rotation (Eq. RSSR with R = [c -s; s c], S = diag(sx, sy)).  Records
+// of Eq. sigma plus the dilation sigma0^2; the covariance of Eq. RSSR (R =
+// [c -s; s c], S = diag(sx, sy)) kept in its principal frame as e = (c, s) / sx
+// and k = sx / sy, Sigma^-1 = e e^T + k^2 e_perp e_perp^T.  Records
 // of one curve are contiguous; a wave stages its 64 records of a round in LDS
 // and writes them as three contiguous 1 KB stores.  With kBin the kernel also
 // does the binning's counting pass (Sec. 3.4): each Gaussian's tile rectangle
@@ -61,15 +62,15 @@ __global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8
             int r = idx / v.K, k = idx - r * v.K;
             Geom g;
             gauss_geom(v, XA, XB, r, k, inv_rho2, s0, g);
-            const double a = rcp_f64(g.sx2), b = rcp_f64(g.sy2);
-            double qxx = g.cs * g.cs * a + g.sn * g.sn * b;
-            double qxy = g.cs * g.sn * (a - b);
-            double qyy = g.sn * g.sn * a + g.cs * g.cs * b;
+            // 1 / sx and sx / sy (scales are positive: sigma0^2 > 0, or the
+            // caller's degenerate input gives inf / nan, which binning flags)
+            const double isx = rsqrt_f64(g.sx2);
+            const double kk = g.sx2 * isx * rsqrt_f64(g.sy2);
             float hx = (float)g.mu.x, hy = (float)g.mu.y;
             float lx = (float)(g.mu.x - (double)hx), ly = (float)(g.mu.y - (double)hy);
             float o = opa[v.nopa == v.S ? g.seg : 0];
             const float4 m = make_float4(hx, hy, lx, ly);
-            const float4 q = make_float4((float)qxx, (float)qxy, (float)qyy, o);
+            const float4 q = make_float4((float)(g.cs * isx), (float)(g.sn * isx), (float)kk, o);
             my[3 * l + 0] = m;
             my[3 * l + 1] = q;
             my[3 * l + 2] = make_float4(cr, cg, cb, cid);

@@ -306,3 +306,22 @@ def test_conv_shape_validation():
     assert lib.bz_conv_fwd(C.byref(d2), 1, 1, None, 0, 1, None, None) == bz.BZ_ERR_ARG
     assert lib.bz_conv_fwd(C.byref(d), None, 1, None, 0, 1, None, None) == bz.BZ_ERR_ARG
     assert lib.bz_conv_fwd(C.byref(d), 1, 1, None, 2, 1, None, None) == bz.BZ_ERR_ARG
+
+
+def test_peak_probe_arguments_and_work_counts():
+    """Rate probes: argument checks happen on the host before any launch, and
+    the work counts follow the documented units."""
+    import ctypes as C
+    lib = bz.load_library()
+    w = C.c_double(0.0)
+    assert lib.bz_peak_work(0, 1 << 20, 0, C.byref(w)) == bz.BZ_OK and w.value == 2.0 * (1 << 20)
+    assert lib.bz_peak_work(1, 256, 10, C.byref(w)) == bz.BZ_OK and w.value == 2.0 * 8 * 10 * 256
+    assert lib.bz_peak_work(5, 1024, 3, C.byref(w)) == bz.BZ_OK and w.value == 8 * 3 * 16
+    assert lib.bz_peak_work(99, 256, 1, C.byref(w)) == bz.BZ_ERR_ARG
+    # null buffer, ragged sizes, unknown kind: rejected without a launch
+    assert lib.bz_peak_run(1, 256, 1, None, 1024, None) == bz.BZ_ERR_ARG
+    fake = C.c_void_p(16)
+    assert lib.bz_peak_run(1, 300, 1, fake, 1 << 20, None) == bz.BZ_ERR_ARG
+    assert lib.bz_peak_run(0, 100, 0, fake, 1 << 20, None) == bz.BZ_ERR_ARG
+    assert lib.bz_peak_run(0, 1 << 20, 0, fake, 1 << 20, None) == bz.BZ_ERR_ARG
+    assert lib.bz_peak_run(42, 256, 1, fake, 1 << 20, None) == bz.BZ_ERR_ARG

@@ -423,38 +423,6 @@ def test_paper_scale_backward_on_a_band(torch_cuda):
         assert e <= GRAD_TOL, k
 
 
-def test_paper_scale_fused_step_on_a_band(torch_cuda):
-    """The benchmark's step (bz_sample_bin, bz_render_fwd_l2, bz_render_bwd)
-    at 2048x2048, 20,000 curves, against a target equal to the image outside
-    rows 960..1087: d_image is exactly zero there and scale*(image - target)
-    inside, and the gradients are the oracle's for that d_image."""
-    torch = torch_cuda
-    sc = scenes.paper_2048(0)
-    H, W = sc.height, sc.width
-    y0, y1 = 960, 1088
-    _note("paper-scale fused step, target off the image on rows 960..1087")
-    r = _rast(sc)
-    img = r.render().cpu().numpy()
-    tgt = img.copy()
-    tgt[:, y0:y1] -= np.random.default_rng(9).uniform(-0.05, 0.05, (3, y1 - y0, W)).astype(np.float32)
-    r.step(torch.as_tensor(tgt, device="cuda"))
-    torch.cuda.synchronize()
-    assert np.array_equal(r.image.cpu().numpy(), img)
-    d = r.d_image.cpu().numpy()
-    scale = np.float32(2.0 / img.size)
-    assert np.array_equal(d, scale * (img - tgt))
-    assert not d[:, :y0].any() and not d[:, y1:].any()
-    g = oracle.sample(sc)
-    ob = oracle.render(g, W, H, sc.bg, rows=(y0, y1), d_image=d.astype(np.float64))
-    oc = oracle.chain(sc, ob["d_gauss"])
-    for k in ("d_ctrl", "d_width", "d_color", "d_opacity"):
-        e = rel_l2(getattr(r, k).cpu().numpy(), oc[k])
-        _note(f"  {k}: rel L2 {e:.2e}")
-        assert e <= GRAD_TOL, k
-    e = np.sum((img.astype(np.float64) - tgt) ** 2)
-    assert abs(float(r.loss.item()) - e) <= 1e-5 * e
-
-
 def _opaque_scene():
     """Overlapping opaque lenses and strokes on a 96x80 canvas: the lens
     interiors are sampled densely, so most pixels stop (T below t_min) after a

@@ -19,7 +19,8 @@
  * Conventions shared by every call:
  *  - Pointers inside the structs and the image/gradient pointers are DEVICE
  *    pointers owned by the caller; functions marked "host" take host pointers.
- *    The library never allocates or frees memory and keeps no global state.
+ *    The library never allocates or frees memory and keeps no global state,
+ *    except the fixed device array of bz_sample_bin_static (see there).
  *  - Every device call is asynchronous and ordered on the caller's stream; no
  *    call synchronises.  The return code reports argument errors (BZ_ERR_ARG,
  *    BZ_ERR_UNSUPPORTED) detected on the host before anything is launched, and
@@ -269,6 +270,26 @@ bz_status bz_sample(const bz_curves *c, const bz_opts *opts, bz_gaussians *g,
  * come out exactly as from the two calls; arguments and errors are theirs. */
 bz_status bz_sample_bin(const bz_curves *c, const bz_opts *opts, bz_gaussians *g, bz_bins *b,
                         hipStream_t stream);
+
+/* bz_sample_bin for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the binning workspace is a fixed device array inside the library,
+ * BZ_STATIC_SCRATCH_BYTES (32 MiB) per GPU, held from the first call on a GPU
+ * until the process ends; b->workspace and b->workspace_bytes are ignored.
+ * Everything else (arguments, outputs, status words, errors) is bz_sample_bin's,
+ * and the Gaussians, tile lists, ranges and status come out bit for bit as its.
+ * Returns BZ_ERR_CAPACITY, before anything is launched, when the workspace
+ * for c->n_gauss Gaussians and b->cap_pairs pairs (bz_workspace_size) exceeds
+ * BZ_STATIC_SCRATCH_BYTES (size it with bz_workspace_size), and BZ_ERR_HIP if
+ * the array's device address cannot be obtained.  The call allocates nothing.  The array needs no initialisation
+ * (every byte the binning reads was written earlier in the same call); it keeps
+ * the last call's contents.  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (different streams, or host threads) race and
+ * must be serialised by the caller.  Persistent blend launches still need the
+ * 256 bytes of tile counters at bz_bins.workspace. */
+#define BZ_STATIC_SCRATCH_BYTES (32 * 1024 * 1024)
+bz_status bz_sample_bin_static(const bz_curves *c, const bz_opts *opts, bz_gaussians *g,
+                               bz_bins *b, hipStream_t stream);
 
 /* Sec. 3.4 tile pipeline: bound each Gaussian's truncated support
  * (1/2 d^T Q d <= -ln g_min), list it in every tile the bound touches, sort

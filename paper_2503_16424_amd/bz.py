@@ -75,7 +75,10 @@ EXPORTS = ("bz_layout_host", "bz_workspace_size", "bz_num_tiles", "bz_batch_layo
            "bz_visit_words", "bz_sample", "bz_sample_bin", "bz_bin",
            "bz_render_fwd", "bz_render_fwd_l2", "bz_render_bwd", "bz_render_bwd_gauss", "bz_render_bwd_curves",
            "bz_curve_area", "bz_area_order_workspace", "bz_area_order", "bz_xing_loss",
-           "bz_l2_grad", "bz_status_str", "bz_peak_run", "bz_peak_work")
+           "bz_l2_grad", "bz_status_str", "bz_peak_run", "bz_peak_work",
+           "bz_sample_bin_static")
+
+STATIC_SCRATCH_BYTES = 32 * 1024 * 1024   # BZ_STATIC_SCRATCH_BYTES of bz.h
 
 _lib = None
 
@@ -107,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     lib.bz_sample.argtypes = [P(Curves), P(Opts), P(Gaussians), C.c_void_p]
     lib.bz_sample_bin.restype = C.c_int
     lib.bz_sample_bin.argtypes = [P(Curves), P(Opts), P(Gaussians), P(Bins), C.c_void_p]
+    lib.bz_sample_bin_static.restype = C.c_int
+    lib.bz_sample_bin_static.argtypes = [P(Curves), P(Opts), P(Gaussians), P(Bins), C.c_void_p]
     lib.bz_bin.restype = C.c_int
     lib.bz_bin.argtypes = [P(Gaussians), P(Opts), P(Bins), C.c_void_p]
     lib.bz_render_fwd.restype = C.c_int
@@ -455,6 +460,16 @@ class Rasterizer:
         _check("bz_sample_bin", self.lib.bz_sample_bin(C.byref(self.curves), C.byref(self.opts),
                                                        C.byref(self.gauss), C.byref(self.bins),
                                                        _stream()))
+
+    def sample_bin_static(self):
+        """sample_bin with the binning workspace in the library's fixed device
+        array (bz_sample_bin_static: allocates nothing; limited to
+        STATIC_SCRATCH_BYTES of workspace)."""
+        if self.draw_order == "area":
+            self.reorder()
+        _check("bz_sample_bin_static", self.lib.bz_sample_bin_static(
+            C.byref(self.curves), C.byref(self.opts), C.byref(self.gauss), C.byref(self.bins),
+            _stream()))
 
     def bin(self):
         _check("bz_bin", self.lib.bz_bin(C.byref(self.gauss), C.byref(self.opts),

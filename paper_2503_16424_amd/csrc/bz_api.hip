@@ -2,13 +2,39 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "bz_internal.h"
 
 using namespace bz;
 
+// Binning workspace of bz_sample_bin_static: a fixed device array that every
+// call on a device shares.  In host code `scratch` names a host-side stand-in,
+// not the device memory: the device address comes from hipGetSymbolAddress
+// (static_scratch below), once per device.
+static __device__ __align__(256) unsigned char scratch[BZ_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call there (with that device current) and kept for later calls.
+bz_status static_scratch(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BZ_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BZ_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BZ_OK;
+}
 
 // Per-curve limits of the per-curve kernels (LDS sizes).
 constexpr int kMaxK = 1024;
@@ -217,8 +243,9 @@ bz_status bz_sample(const bz_curves *c, const bz_opts *o, bz_gaussians *g, hipSt
     return launched(launch_sample(*c, *o, g->rec, nullptr, s));
 }
 
-bz_status bz_sample_bin(const bz_curves *c, const bz_opts *o, bz_gaussians *g, bz_bins *b,
-                        hipStream_t s) {
+// Arguments of bz_sample_bin other than the bin workspace.
+static bz_status check_sample_bin(const bz_curves *c, const bz_opts *o, const bz_gaussians *g,
+                                  const bz_bins *b) {
     bz_status st = check_opts(o);
     if (st != BZ_OK) return st;
     if ((st = check_curves(c)) != BZ_OK) return st;
@@ -228,10 +255,35 @@ bz_status bz_sample_bin(const bz_curves *c, const bz_opts *o, bz_gaussians *g, b
     if (c->n_curves > 0 && 2 * 16 * (int64_t)c->max_k > kMaxLdsBytes) return BZ_ERR_UNSUPPORTED;
     if (c->n_gauss >= (int64_t(1) << 32)) return BZ_ERR_UNSUPPORTED;
     if (o->batch && o->batch->n_gauss != c->n_gauss) return BZ_ERR_ARG;
+    return check_bins(b, o, c->n_gauss, false);
+}
+
+bz_status bz_sample_bin(const bz_curves *c, const bz_opts *o, bz_gaussians *g, bz_bins *b,
+                        hipStream_t s) {
+    bz_status st = check_sample_bin(c, o, g, b);
+    if (st != BZ_OK) return st;
     if ((st = check_bins(b, o, c->n_gauss, true)) != BZ_OK) return st;
     (void)hipGetLastError();
     g->n = c->n_gauss;
     return launched(launch_sample_bin(*c, *o, g->rec, *b, s));
+}
+
+bz_status bz_sample_bin_static(const bz_curves *c, const bz_opts *o, bz_gaussians *g,
+                               bz_bins *b, hipStream_t s) {
+    bz_status st = check_sample_bin(c, o, g, b);
+    if (st != BZ_OK) return st;
+    // sizes first, on the host: nothing touches the device for a call that
+    // cannot fit
+    if (bin_layout(*o, c->n_gauss, b->cap_pairs).total > (int64_t)BZ_STATIC_SCRATCH_BYTES)
+        return BZ_ERR_CAPACITY;
+    void *ws = nullptr;
+    if ((st = static_scratch(&ws)) != BZ_OK) return st;
+    bz_bins bs = *b;
+    bs.workspace = ws;
+    bs.workspace_bytes = BZ_STATIC_SCRATCH_BYTES;
+    (void)hipGetLastError();
+    g->n = c->n_gauss;
+    return launched(launch_sample_bin(*c, *o, g->rec, bs, s));
 }
 
 bz_status bz_bin(const bz_gaussians *g, const bz_opts *o, bz_bins *b, hipStream_t s) {

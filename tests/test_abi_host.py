@@ -325,3 +325,25 @@ def test_peak_probe_arguments_and_work_counts():
     assert lib.bz_peak_run(0, 100, 0, fake, 1 << 20, None) == bz.BZ_ERR_ARG
     assert lib.bz_peak_run(0, 1 << 20, 0, fake, 1 << 20, None) == bz.BZ_ERR_ARG
     assert lib.bz_peak_run(42, 256, 1, fake, 1 << 20, None) == bz.BZ_ERR_ARG
+
+
+def test_static_sample_bin_checks_arguments_and_size_on_host():
+    """bz_sample_bin_static refuses bad arguments and workspaces beyond its
+    fixed array on the host, before touching the device (none here)."""
+    lib = bz.load_library()
+    o = _opts()
+    g = bz.Gaussians(16, 0, 4096)
+    assert lib.bz_sample_bin_static(None, C.byref(o), C.byref(g), C.byref(_fake_bins()),
+                                    None) == bz.BZ_ERR_ARG
+    assert lib.bz_sample_bin_static(C.byref(_fake_curves()), C.byref(o), C.byref(g), None,
+                                    None) == bz.BZ_ERR_ARG
+    small_cap = bz.Gaussians(8, 0, 4096)
+    assert lib.bz_sample_bin_static(C.byref(_fake_curves()), C.byref(o), C.byref(small_cap),
+                                    C.byref(_fake_bins()), None) == bz.BZ_ERR_CAPACITY
+    # a pair capacity whose workspace exceeds BZ_STATIC_SCRATCH_BYTES (12 bytes a pair)
+    big = bz.Bins(4 << 20, 4096, 4096, 0, 0, 4096)
+    need = C.c_int64(0)
+    assert lib.bz_workspace_size(C.byref(o), 16, 4 << 20, C.byref(need)) == bz.BZ_OK
+    assert need.value > bz.STATIC_SCRATCH_BYTES
+    assert lib.bz_sample_bin_static(C.byref(_fake_curves()), C.byref(o), C.byref(g), C.byref(big),
+                                    None) == bz.BZ_ERR_CAPACITY

@@ -38,11 +38,51 @@ METRIC = "fwd+bwd steps/s at 2048², 20k curves; steps-to-PSNR learned vs plain 
 #             p grad (3), d and d d^T moments (5)                          = 53
 FLOPS_FWD_PAIR = 25
 FLOPS_BWD_PAIR = 53
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, plain
-# (non-packed) FP32 VALU: the build disables packed FP32 instructions.
-PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# The same work as VALU issue slots (one lane operation each, an FMA one
+# slot): 13 plain operations + 1 transcendental (exp2) per pair forward, 30 +
+# 2 (exp2, reciprocal) backward.  A transcendental's slot cost is measured by
+# the rate probes (bz_peak.h); the default below is what they measured on
+# MI355X (exp2 and rcp issue at half the FMA rate).
+VALU_FWD_PAIR, TRANS_FWD_PAIR = 13, 1
+VALU_BWD_PAIR, TRANS_BWD_PAIR = 30, 2
+TRANS_SLOTS_DEFAULT = 2.0
+# MI355X published peaks: HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s
+# (256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz).  The
+# build leaves packed FP32 off, so its attainable vector rate is half that:
+# 78.6 TFLOP/s, 39.3 T lane operations/s.
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+PEAK_FP32_VALU_TFLOPS = PEAK_FP32_TFLOPS / 2
 BYTES_REC = 48
+
+
+def stage_rooflines(ms, n_gauss, pairs, n_alg, n_tiles, hw, trans_slots, bw_gbs, lane_ops):
+    """Per-stage roofline times (ms) of one step at HBM bandwidth bw_gbs and
+    lane_ops VALU slots per second: max(algorithmic bytes / bandwidth,
+    algorithmic slots / issue rate), with the byte and slot counts of the
+    method's work (not of the kernels' tiling):
+      sample_bin: records written (48 B per Gaussian), tile lists (4 B per
+                  pair) and ranges (8 B per tile);
+      fwd_l2:     per pair 13 slots + 1 transcendental; per pixel the image,
+                  t_final, n_last written and target read, d_image written
+                  (44 B);
+      bwd_gauss:  per pair 30 slots + 2 transcendentals; per pixel d_image and
+                  state read (20 B); per Gaussian its nine gradient planes
+                  read and written (72 B);
+      bwd_curves: per Gaussian its nine planes read (36 B)."""
+    work = {
+        "sample_bin": (BYTES_REC * n_gauss + 4 * pairs + 8 * n_tiles, 0.0),
+        "fwd_l2": (44 * hw, n_alg * (VALU_FWD_PAIR + TRANS_FWD_PAIR * trans_slots)),
+        "bwd_gauss": (20 * hw + 72 * n_gauss, n_alg * (VALU_BWD_PAIR + TRANS_BWD_PAIR * trans_slots)),
+        "bwd_curves": (36 * n_gauss, 0.0),
+    }
+    out = {}
+    for k, (byts, slots) in work.items():
+        t_mem = byts / (bw_gbs * 1e9) * 1e3
+        t_alu = slots / lane_ops * 1e3
+        out[k] = {"roof_ms": max(t_mem, t_alu), "bound": "alu" if t_alu > t_mem else "hbm",
+                  "ms": ms[k], "bytes": byts, "slots": slots}
+    return out
 
 
 def parse():
@@ -64,6 +104,9 @@ def parse():
                     help="keep the forward's per-pixel blend state for the backward, or "
                          "recompute it per tile inside the backward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the rate probes (roofline fractions then use the published "
+                         "peaks and a transcendental cost of 2 slots)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the timed steps, copy a MIB-sized buffer once (a known-size "
                          "kernel to scale hardware byte counters against)")
@@ -94,15 +137,24 @@ def measured_traffic(kernel, workload, tw, th):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(sc, target, rows):
-    """Time the FP64 oracle on one step of the same workload: by default the
-    whole frame; with rows < height a band of rows whose forward+backward time
-    is scaled to the frame (an upper bound: the oracle's render has a per-call
-    cost that the scaling multiplies)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_step(sc, target, rows):
+    """One step of the FP64 oracle on sc: sampling, forward + backward of
+    `rows` (with the mean-L2 gradient against target), chain to the curves.
+    Returns (seconds of the step scaled to the whole frame, details)."""
     import numpy as np
 
     import oracle
-    oracle.build()
     H, W = sc.height, sc.width
     rows = min(rows, H)
     y0 = H // 2 - rows // 2
@@ -118,40 +170,95 @@ def cpu_baseline(sc, target, rows):
     t3 = time.perf_counter()
     oracle.chain(sc, bw["d_gauss"])
     t4 = time.perf_counter()
-    band = t3 - t2                  # the backward call re-runs the band's forward itself
-    step = (t1 - t0) + band * (H / rows) + (t4 - t3)
-    return dict(value=1.0 / step, unit="steps/s", cores=oracle.num_threads(), kind="oracle",
-                sample=(f"FP64 oracle: full sampling ({t1 - t0:.2f} s) and per-curve chain "
-                        f"({t4 - t3:.2f} s); forward+backward of rows {y0}..{y1 - 1} "
-                        f"({rows} of {H}, {t3 - t2:.2f} s) scaled by {H / rows:.0f}; "
-                        f"host {platform.processor() or platform.machine()}"),
-                seconds=t4 - t0)
+    # the backward call re-runs the band's forward itself
+    step = (t1 - t0) + (t3 - t2) * (H / rows) + (t4 - t3)
+    return step, dict(sample_s=t1 - t0, band_s=t3 - t2, chain_s=t4 - t3, rows=(y0, y1),
+                      pairs=bw["pairs"], g=g)
+
+
+def cpu_baseline(sc, target, rows, one_core_rows=64):
+    """The FP64 oracle timed on the host: one step of the same workload on all
+    cores (by default the whole frame; with rows < height a band whose time is
+    scaled to the frame), the same on one core over a band of one_core_rows
+    rows, and one step of the 128x128 and 512x512 workloads on all cores."""
+    import numpy as np
+
+    import oracle
+    from paper_2503_16424_amd import scenes
+    oracle.build()
+    cores = oracle.num_threads()
+    H = sc.height
+    step, det = _oracle_step(sc, target, rows)
+    y0, y1 = det["rows"]
+    out = dict(value=1.0 / step, unit="steps/s", cores=cores, kind="oracle",
+               sample=(f"FP64 oracle on {cores} threads: full sampling ({det['sample_s']:.2f} s) "
+                       f"and per-curve chain ({det['chain_s']:.2f} s); forward+backward of rows "
+                       f"{y0}..{y1 - 1} ({y1 - y0} of {H}, {det['band_s']:.2f} s) scaled by "
+                       f"{H / (y1 - y0):.0f}; host CPU {cpu_model()}"),
+               seconds=step, cpu_model=cpu_model(), oracle_pairs=det["pairs"])
+    if y1 - y0 < H:
+        out["oracle_pairs_band"] = out.pop("oracle_pairs")
+    oracle.set_threads(1)
+    try:
+        s1, d1 = _oracle_step(sc, target, one_core_rows)
+    finally:
+        oracle.set_threads(cores)
+    out["one_core"] = {"value": 1.0 / s1, "seconds": s1,
+                       "sample": (f"1 thread: full sampling ({d1['sample_s']:.2f} s), chain "
+                                  f"({d1['chain_s']:.2f} s), forward+backward of "
+                                  f"{one_core_rows} rows ({d1['band_s']:.2f} s) scaled by "
+                                  f"{H / one_core_rows:.0f}")}
+    small = {}
+    for name, scn, tgt in (("tiny_128", scenes.tiny_128(0), scenes.tiny_128_target(0)),
+                           ("open_512", scenes.open_512(0), scenes.target_noise(1, 512, 512))):
+        st, _ = _oracle_step(scn, tgt.astype(np.float64), scn.height)
+        small[name] = {"steps_per_s": 1.0 / st, "seconds": st}
+    out["configs"] = small
+    out["_gauss"] = det["g"]
+    return out
+
+
+def tile_depth(sc, g):
+    """Distinct curves per 16x16 tile (the workload's depth complexity), from
+    the oracle: curves contributing to a pixel of the tile, and curves whose
+    support box reaches it."""
+    import numpy as np
+
+    import oracle
+    d = oracle.tile_depth(g, sc.n_curves, sc.width, sc.height, (16, 16))
+    return {k: {"mean": float(np.mean(v)), "p99": float(np.percentile(v, 99)),
+                "max": int(np.max(v))} for k, v in d.items()}
 
 
 def learned_init_figure(size=1024, steps=1000, seed=77):
     """Second half of the metric: steps the learned start needs to reach the
-    PSNR the uniform random start has after `steps` Adam steps (learning rates
-    of Sec. 4.1), on one synthetic 1024x1024 target."""
+    PSNR the uniform random start has after `steps` Adam steps, on one
+    synthetic 1024x1024 target, under the learning rates of Sec. 4.1 and under
+    the 512x512 workload's (control points 1e-2)."""
     import numpy as np
 
     from paper_2503_16424_amd import cnn, learned_init
-    from paper_2503_16424_amd.optim import PAPER_LR
     if not os.path.exists(learned_init.WEIGHTS):
         return None
     print("# learned initialiser: steps-to-PSNR at 1024x1024", file=sys.stderr, flush=True)
     net = cnn.CurveNet()
     with np.load(learned_init.WEIGHTS, allow_pickle=False) as f:
         net.load_state_dict({k: f[k] for k in f.files})
-    o = learned_init.evaluate(net, size, steps, seed, sets={"paper_lr": dict(PAPER_LR)})
-    e = o["paper_lr"]
-    return {"metric": "steps to the random start's PSNR after 1000 steps", "size": size,
-            "steps": steps, "target_seed": seed, "lr": "Sec. 4.1 (control points 2e-4)",
-            "random_psnr_1000": e["random"]["psnr_final"],
-            "learned_psnr_initial": e["learned"]["psnr_initial"],
-            "learned_psnr_1000": e["learned"]["psnr_final"],
-            "learned_steps": e["learned"]["steps_to_random_final"],
-            "fraction_of_steps": e["learned"]["fraction_of_steps"],
-            "propose_ms": o["propose_ms"]}
+    o = learned_init.evaluate(net, size, steps, seed)
+    labels = {"paper_lr": "Sec. 4.1 (control points 2e-4)",
+              "ctrl_lr_1e-2": "512x512 workload (control points 1e-2)"}
+    out = {"metric": "steps to the random start's PSNR after 1000 steps", "size": size,
+           "steps": steps, "target_seed": seed, "propose_ms": o["propose_ms"], "sets": {}}
+    for key, lab in labels.items():
+        e = o[key]
+        out["sets"][key] = {"lr": lab, "random_psnr_1000": e["random"]["psnr_final"],
+                            "learned_psnr_initial": e["learned"]["psnr_initial"],
+                            "learned_psnr_1000": e["learned"]["psnr_final"],
+                            "learned_steps": e["learned"]["steps_to_random_final"],
+                            "fraction_of_steps": e["learned"]["fraction_of_steps"]}
+    fr = [v["fraction_of_steps"] for v in out["sets"].values()]
+    out["fraction_of_steps_worst"] = None if None in fr else max(fr)
+    return out
 
 
 PEAK_BF16_MFMA_TFLOPS = 2500.0
@@ -414,29 +521,55 @@ def main():
           f"stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}; "
           f"contributing pairs {n_alg}; mse {loss:.5f}", file=sys.stderr, flush=True)
 
-    # Roofline of the dominant stage's kernel.
+    # Rate probes: the sustained HBM copy rate, FP32 FMA rate and the issue
+    # cost of the transcendentals, measured on this device.
+    peaks = None
+    if not a.no_peaks:
+        from paper_2503_16424_amd import peaks as peak_probes
+        peaks = peak_probes.measure()
+        print(f"# rate probes: {json.dumps({k: round(v, 4) for k, v in peaks.items()})}",
+              file=sys.stderr, flush=True)
+    trans = peaks["exp2_fma_slots"] if peaks else TRANS_SLOTS_DEFAULT
+    hw = sc.width * sc.height
+    bases = {"published": (PEAK_HBM_GBS, PEAK_FP32_TFLOPS * 1e12 / 2),
+             "nonpacked": (PEAK_HBM_GBS, PEAK_FP32_VALU_TFLOPS * 1e12 / 2)}
+    if peaks:
+        bases["measured"] = (peaks["copy_GBs"], peaks["fma_TFLOPs"] * 1e12 / 2)
+    step_roof = {}
+    for basis, (bw, lanes) in bases.items():
+        st = stage_rooflines(stage_ms, sc.n_gauss, need, n_alg, r.n_tiles, hw, trans, bw, lanes)
+        step_roof[basis] = {"step_frac": sum(v["roof_ms"] for v in st.values()) / ms_per_step,
+                            "stages": {k: {"roof_ms": round(v["roof_ms"], 4), "bound": v["bound"],
+                                           "frac": v["roof_ms"] / v["ms"]}
+                                       for k, v in st.items()}}
+
+    # Roofline of the dominant stage's kernel, against the published FP32
+    # vector peak (and, beside it, the non-packed and measured rates).
     dom = max(("fwd_l2", "bwd_gauss", "bwd_curves", "sample_bin"), key=lambda s: stage_ms[s])
-    if dom == "fwd_l2":
-        ach = n_alg * FLOPS_FWD_PAIR / (stage_ms["fwd_l2"] * 1e-3) / 1e12
-        roof = dict(kernel="k_fwd_l2 (bz_render_fwd_l2)", bound="alu", achieved=ach,
-                    peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
-    elif dom == "bwd_gauss":
-        ach = n_alg * FLOPS_BWD_PAIR / (stage_ms["bwd_gauss"] * 1e-3) / 1e12
-        roof = dict(kernel="k_bwd_tiles (bz_render_bwd_gauss, with its d_gauss clear)",
-                    bound="alu", achieved=ach, peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s")
+    if dom in ("fwd_l2", "bwd_gauss"):
+        flops = FLOPS_FWD_PAIR if dom == "fwd_l2" else FLOPS_BWD_PAIR
+        ach = n_alg * flops / (stage_ms[dom] * 1e-3) / 1e12
+        kern = ("k_fwd_l2 (bz_render_fwd_l2)" if dom == "fwd_l2" else
+                "k_bwd_tiles (bz_render_bwd_gauss, with its d_gauss clear)")
+        roof = dict(kernel=kern, bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")
+        roof["frac_nonpacked"] = ach / PEAK_FP32_VALU_TFLOPS
+        if peaks:
+            roof["frac_measured"] = ach / peaks["fma_TFLOPs"]
     elif dom == "bwd_curves":
         byts = sc.n_gauss * 36
         ach = byts / (stage_ms["bwd_curves"] * 1e-3) / 1e9
         roof = dict(kernel="k_bwd_curves", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
                     unit="GB/s")
     else:
-        # records written, then per pair its key and id written and read by the sort
         byts = sc.n_gauss * BYTES_REC + need * 4 + r.n_tiles * 8
         ach = byts / (stage_ms["sample_bin"] * 1e-3) / 1e9
         roof = dict(kernel="bz_sample_bin", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
                     unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(roof["kernel"].split()[0], a.workload, tw, th)
+    roof["step_frac"] = step_roof["published"]["step_frac"]
+    roof["step"] = step_roof
+    roof["transcendental_slots"] = trans
 
     out = {
         "metric": METRIC,
@@ -460,11 +593,19 @@ def main():
         "pairs": {"tile_pairs": need, "contributing": n_alg},
         "roofline": roof,
     }
+    if peaks:
+        out["peaks_measured"] = peaks
     if not a.no_learned_init and a.workload == "paper_2048":
         out["learned_init"] = learned_init_figure()
     if not a.no_cpu_baseline:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(sc, target.astype(np.float64), a.cpu_rows)
+        cb = cpu_baseline(sc, target.astype(np.float64), a.cpu_rows)
+        g = cb.pop("_gauss")
+        if "oracle_pairs" in cb:
+            out["pairs"]["contributing_oracle"] = cb["oracle_pairs"]
+        out["cpu_baseline"] = cb
+        print("# per-tile depth (oracle)", file=sys.stderr, flush=True)
+        out["config"]["tile_depth"] = tile_depth(sc, g)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -851,6 +851,15 @@ int orc_chain(int n, const int32_t *kind, const int32_t *nseg, const int32_t *ks
     return st;
 }
 
+/* Threads the following calls use (OpenMP); n < 1 leaves it unchanged. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

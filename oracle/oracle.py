@@ -53,6 +53,11 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """Threads the oracle's parallel loops use from now on."""
+    _load().orc_set_threads(C.c_int(int(n)))
+
+
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 

@@ -499,47 +499,52 @@ __device__ inline float dpp_f(float v) {
                  : OUT(d[od + 0]), OUT(d[od + 1]), OUT(d[od + 2]), OUT(d[od + 3])        \
                  : "v"(s[os + 0]), "v"(s[os + 1]), "v"(s[os + 2]), "v"(s[os + 3]))
 
-// Transposed reduction of 64 per-lane values: on return lane l holds the sum
-// over all 64 lanes of v[l].  Each level halves the values a lane holds by
-// exchanging half of them with a partner lane: lanes l and l^32 (permlane32
-// swap), l^16 (permlane16 swap), l^8 (DPP row rotate by 8), l^7 (DPP half-row
-// mirror), l^3 and l^1 (DPP quad permutes).  Bit b of the lane index decides
-// which half a lane keeps, so after the six levels lane l holds index l.
-// Lanes l and l^8 differ in bit 1 of their bank, lanes l and l^7 in bit 0, so
-// those two levels are pairs of bank-masked DPP adds (lanes of a bank add
-// the index they keep).  Works in place: v holds partial sums afterwards.
-__device__ inline float reduce_scatter64(float (&v)[64], int lane) {
-    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 0);
-    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 8);
-    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 16);
-    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 32), 24);
-#pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] += v[i + 32];
-    BZ_SWAP8("v_permlane16_swap_b32", v, (v + 16), 0);
-    BZ_SWAP8("v_permlane16_swap_b32", v, (v + 16), 8);
+// d[i] (2 registers) on the banks in MASK = s[i] + s[i] of the DPP partner.
+#define BZ_DPPADD2(OUT, CTRL, MASK, d, s, od, os)                                        \
+    asm volatile("s_nop 1\n\t"                                                          \
+                 "v_add_f32_dpp %0, %2, %2 " CTRL " row_mask:0xf bank_mask:" MASK "\n\t"  \
+                 "v_add_f32_dpp %1, %3, %3 " CTRL " row_mask:0xf bank_mask:" MASK          \
+                 : OUT(d[od + 0]), OUT(d[od + 1])                                        \
+                 : "v"(s[os + 0]), "v"(s[os + 1]))
+
+// Transposed reduction of 32 per-lane values over the 64 lanes: on return
+// lanes 2i and 2i + 1 both hold the sum over all lanes of v[i].  Each level
+// halves the values a lane holds by exchanging half of them with a partner
+// lane: lanes l and l^32 (permlane32 swap), l^16 (permlane16 swap), l^8 (DPP
+// row rotate by 8), l^7 (DPP half-row mirror), l^3 (DPP quad permute); bit b
+// of the lane index decides which half a lane keeps, so after five levels
+// lanes 2i and 2i + 1 hold index i, and a last DPP add over l^1 completes the
+// sum.  Lanes l and l^8 differ in bit 1 of their bank, lanes l and l^7 in bit
+// 0, so those two levels are pairs of bank-masked DPP adds (the lanes of a
+// bank add the index they keep).  Works in place: v holds partial sums
+// afterwards.
+__device__ inline float reduce_scatter32(float (&v)[32], int lane) {
+    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 16), 0);
+    BZ_SWAP8("v_permlane32_swap_b32", v, (v + 16), 8);
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] += v[i + 16];
-    // lane ^ 8: banks 0, 1 keep index i, banks 2, 3 keep i + 8 (written into v[i])
-    float w[8];
-    BZ_DPPADD4("=&v", "row_ror:8", "0x3", w, v, 0, 0);
-    BZ_DPPADD4("=&v", "row_ror:8", "0x3", w, v, 4, 4);
-    BZ_DPPADD4("+v", "row_ror:8", "0xc", w, v, 0, 8);
-    BZ_DPPADD4("+v", "row_ror:8", "0xc", w, v, 4, 12);
-    // lane ^ 7: banks 0, 2 keep index i, banks 1, 3 keep i + 4
-    float u[4];
-    BZ_DPPADD4("=&v", "row_half_mirror", "0x5", u, w, 0, 0);
-    BZ_DPPADD4("+v", "row_half_mirror", "0xa", u, w, 0, 4);
-    const bool b1 = lane & 2, b0 = lane & 1;
+    BZ_SWAP8("v_permlane16_swap_b32", v, (v + 8), 0);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        float keep = b1 ? u[i + 2] : u[i], send = b1 ? u[i] : u[i + 2];
-        u[i] = keep + dpp_f<0x1B>(send);           // quad_perm [3,2,1,0] (lane ^ 3)
-    }
-    float keep = b0 ? u[1] : u[0], send = b0 ? u[0] : u[1];
-    return keep + dpp_f<0xB1>(send);               // quad_perm [1,0,3,2] (lane ^ 1)
+    for (int i = 0; i < 8; ++i) v[i] += v[i + 8];
+    float w[4];
+    BZ_DPPADD4("=&v", "row_ror:8", "0x3", w, v, 0, 0);
+    BZ_DPPADD4("+v", "row_ror:8", "0xc", w, v, 0, 4);
+    float u[2];
+    BZ_DPPADD2("=&v", "row_half_mirror", "0x5", u, w, 0, 0);
+    BZ_DPPADD2("+v", "row_half_mirror", "0xa", u, w, 0, 2);
+    const bool b1 = lane & 2;
+    const float keep = b1 ? u[1] : u[0], send = b1 ? u[0] : u[1];
+    const float r = keep + dpp_f<0x1B>(send);      // quad_perm [3,2,1,0] (lane ^ 3)
+    return r + dpp_f<0xB1>(r);                     // quad_perm [1,0,3,2] (lane ^ 1)
 }
 
-constexpr int kSlots = 7;   // Gaussians per reduction batch: 7 x 9 = 63 sums
+// Gaussians per reduction batch: 3 x 9 = 27 sums in 32 registers.  (Seven
+// Gaussians in 64 registers cost fewer reduction instructions per sum, but the
+// kernel then needs 96 registers and spills; the reverse pass waits on memory
+// more than it issues arithmetic, and the smaller form, with more waves and no
+// spills, runs it 30% faster.)
+constexpr int kSlots = 3;
+constexpr int kAcc = 32;
 
 // Planes 0-5 are summed without their constant factors, which are applied
 // once to the reduced sums.  With f the alpha gradient, o' the scaled opacity,
@@ -553,11 +558,11 @@ __device__ inline float plane_scale(int v, float inv_1mg) {
 }
 
 // Tile-list positions pooled in LDS by the backward.  With 16x16 tiles a
-// block then takes 256 x 48 B of staging + 9 x 512 x 4 B of sums = 30 KiB,
-// so five blocks share a CU's 160 KiB of LDS: five waves per SIMD, the
-// occupancy the kernel's register budget is held to.  (560 entries, 31.7 KiB,
-// measured as four blocks: the allocation is rounded up.)
-constexpr int kTableCap = 512;
+// block then takes 256 x 48 B of staging + 9 x 384 x 4 B of sums = 25.5 KiB,
+// so six blocks share a CU's 160 KiB of LDS.  (512 positions leave five
+// blocks and ran 5% slower; 256 send more sums to global atomics and ran
+// 16% slower.)
+constexpr int kTableCap = 384;
 
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
 // its pixels used down to the first.  Per pixel and contributor (reverse
@@ -662,7 +667,11 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
 
     const float g_min = a.g_min, amax = a.alpha_max, inv_1mg = a.inv_1mg;
     const int64_t ng = a.n_gauss;
-    const int my_v = lane % 9, my_s = lane / 9;
+    // sum index of this lane after the reduction (lanes 2i and 2i + 1 hold
+    // sum i; the even one stores it)
+    const int my_o = lane >> 1;
+    const bool my_store = (lane & 1) == 0;
+    const int my_v = my_o % 9, my_s = my_o / 9;
     uint32_t slot_pos[kSlots];
 #pragma unroll
     for (int i = 0; i < kSlots; ++i) slot_pos[i] = 0;
@@ -674,10 +683,11 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     int32_t k = wave_on ? (int32_t)(((uint64_t)top + 63) / 64) : 0;
     uint64_t mask = 0;
     uint32_t lo = 0;
+
     // Slots not refilled in a round only feed sums that are never stored.
-    float acc[64];
+    float acc[kAcc];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) acc[i] = 0.f;
+    for (int i = 0; i < kAcc; ++i) acc[i] = 0.f;
     while (true) {
         int filled = 0;
 #pragma unroll
@@ -762,14 +772,16 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
             }
         }
         if (filled == 0) break;
-        // acc[63] feeds only lane 63's sum, which is never stored: setting it
-        // here keeps it out of the registers live across the slot loop
-        acc[63] = 0.f;
-        const float r = reduce_scatter64(acc, lane);
+        // the registers past 9 * kSlots feed only sums that are never stored:
+        // setting them here keeps them out of the registers live across the
+        // slot loop
+#pragma unroll
+        for (int i = 9 * kSlots; i < kAcc; ++i) acc[i] = 0.f;
+        const float r = reduce_scatter32(acc, lane);
         uint32_t my_pos = slot_pos[0];
 #pragma unroll
         for (int i = 1; i < kSlots; ++i) my_pos = my_s == i ? slot_pos[i] : my_pos;
-        if (lane < 9 * filled) {
+        if (my_store && my_o < 9 * filled) {
             if (my_pos < (uint32_t)tab_cap)
                 atomicAdd(&table[my_v * tab_cap + my_pos], r);
             else
@@ -786,11 +798,12 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     }
 }
 
-// Held to 96 VGPRs (five waves per SIMD): the 64 in-place reduction registers
-// dominate, and the few spills this costs sit outside the per-Gaussian
-// arithmetic; at four waves per SIMD the stage ran 8% slower.
+// Held to 80 VGPRs (six waves per SIMD; it needs 77, without spills), which
+// matches the six blocks per CU its LDS allows: the pass waits on memory
+// (records, tile ids, atomics) for a large part of its time, so resident waves
+// count more than instruction count.
 template <bool kRecompute>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_bwd_tiles(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_bwd_tiles(
     TileArgs a) {
     if (a.status[1] & Status::kOverflow) return;         // whole grid
     for_tiles(a, [&](int tile) { bwd_tile<kRecompute>(a, tile); });

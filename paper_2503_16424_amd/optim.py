@@ -130,6 +130,38 @@ class Fitter:
             self.opacity.clamp_(0.0, 1.0)
             self.width.clamp_(min=self.cfg.min_width)
 
+    def state_arrays(self, step: int) -> dict:
+        """Everything a resumed run needs, as host arrays: the step reached,
+        the parameters (control points in normalised coordinates), the
+        optimiser's per-parameter state (Adam moments and step counts) and the
+        torch random generators' states."""
+        out = {"step": np.array(step, np.int64),
+               "ctrl_n": self.ctrl_n.detach().cpu().numpy(),
+               "color": self.color.detach().cpu().numpy(),
+               "opacity": self.opacity.detach().cpu().numpy(),
+               "width": self.width.detach().cpu().numpy(),
+               "rng_cpu": torch.get_rng_state().numpy()}
+        if torch.cuda.is_available():
+            out["rng_cuda"] = torch.cuda.get_rng_state().numpy()
+        out.update(optimizer_state_arrays(self.opt))
+        return out
+
+    def load_state_arrays(self, a: dict) -> int:
+        """Restore what state_arrays saved (shapes must match); returns its step."""
+        with torch.no_grad():
+            for name in ("ctrl_n", "color", "opacity", "width"):
+                p = getattr(self, name)
+                src = torch.as_tensor(np.asarray(a[name]), device=p.device)
+                if src.shape != p.shape:
+                    raise ValueError(f"checkpoint {name} has shape {tuple(src.shape)}, "
+                                     f"the optimisation {tuple(p.shape)}")
+                p.copy_(src)
+        load_optimizer_state(self.opt, a)
+        torch.set_rng_state(torch.as_tensor(np.asarray(a["rng_cpu"]), dtype=torch.uint8))
+        if "rng_cuda" in a and torch.cuda.is_available():
+            torch.cuda.set_rng_state(torch.as_tensor(np.asarray(a["rng_cuda"]), dtype=torch.uint8))
+        return int(a["step"])
+
     def params_host(self) -> dict:
         """Current parameters in the rasterizer's units (px for points)."""
         with torch.no_grad():
@@ -138,7 +170,52 @@ class Fitter:
                         stroke_w=self.width.cpu().numpy())
 
 
-def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=None) -> FitResult:
+def optimizer_state_arrays(opt) -> dict:
+    """A torch optimiser's per-parameter state as host arrays keyed
+    ``opt_<group>_<param>_<name>`` (tensors only; Adam: step, exp_avg,
+    exp_avg_sq)."""
+    out = {}
+    for gi, group in enumerate(opt.param_groups):
+        for pi, p in enumerate(group["params"]):
+            for k, v in opt.state.get(p, {}).items():
+                if torch.is_tensor(v):
+                    out[f"opt_{gi}_{pi}_{k}"] = v.detach().cpu().numpy()
+    return out
+
+
+def load_optimizer_state(opt, a: dict) -> None:
+    """Inverse of optimizer_state_arrays for the same parameter layout (state
+    tensors go back to the device and dtype torch keeps them on: a step count
+    stays where the optimiser creates it, on the host)."""
+    for gi, group in enumerate(opt.param_groups):
+        for pi, p in enumerate(group["params"]):
+            pre = f"opt_{gi}_{pi}_"
+            keys = [k for k in a if k.startswith(pre)]
+            if not keys:
+                opt.state.pop(p, None)
+                continue
+            st = {}
+            for k in keys:
+                name = k[len(pre):]
+                v = torch.as_tensor(np.asarray(a[k]))
+                st[name] = v if name == "step" else v.to(p.device)
+            opt.state[p] = st
+
+
+def save_checkpoint(path: str, fitter: "Fitter", step: int) -> None:
+    """Write fitter.state_arrays(step) to ``path`` (.npz, plain arrays only)."""
+    np.savez(path, **fitter.state_arrays(step))
+
+
+def load_checkpoint(path: str) -> dict:
+    """Read a checkpoint written by save_checkpoint (no pickled objects)."""
+    with np.load(path, allow_pickle=False) as f:
+        return {k: f[k] for k in f.files}
+
+
+def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=None,
+        checkpoint_path: str | None = None, checkpoint_every: int = 0,
+        resume_from: str | None = None) -> FitResult:
     """Optimise the curve parameters of ``rast`` against ``target`` ([3, H, W]
     float32 on the device) for ``cfg.steps`` steps; the rasterizer ends up
     holding the optimised parameters.
@@ -146,15 +223,24 @@ def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=No
     The pair buffer is checked for overflow every ``check_every`` steps (and
     on logged steps); a step whose binning overflowed is binned again with the
     grown buffer before its gradient is used.  A step that overflows between
-    checks yields zero gradients (libbz skips blending on overflow)."""
+    checks yields zero gradients (libbz skips blending on overflow).
+
+    Checkpoints: with ``checkpoint_path`` and ``checkpoint_every`` > 0 the
+    parameters, optimiser moments and random-generator states are written
+    there (.npz) after every ``checkpoint_every``-th step; ``resume_from``
+    restores such a file and continues from the step it reached, so a run
+    interrupted and resumed takes the same steps as an uninterrupted one."""
     f = Fitter(rast, cfg)
     cfg = f.cfg
+    start = 0
+    if resume_from is not None:
+        start = f.load_state_arrays(load_checkpoint(resume_from))
     res = FitResult()
     n = 3 * rast.W * rast.H
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for step in range(cfg.steps):
+    for step in range(start, cfg.steps):
         f.push()
         logged = step % cfg.log_every == 0 or step == cfg.steps - 1
         if logged:
@@ -180,8 +266,10 @@ def fit(rast: "bz.Rasterizer", target, cfg: FitConfig | None = None, callback=No
             res.opt_ms.append(ev[2].elapsed_time(ev[3]))
             if callback:
                 callback(step, res.psnr[-1][1])
+        if checkpoint_path and checkpoint_every > 0 and (step + 1) % checkpoint_every == 0:
+            save_checkpoint(checkpoint_path, f, step + 1)
     torch.cuda.synchronize()
-    res.step_ms = (time.perf_counter() - t0) * 1000.0 / max(cfg.steps, 1)
+    res.step_ms = (time.perf_counter() - t0) * 1000.0 / max(cfg.steps - start, 1)
     f.push()
     rast.render()
     rast.l2_grad(target)

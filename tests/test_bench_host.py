@@ -30,3 +30,21 @@ def test_cpu_baseline_record():
     assert "rows 48..79 (32 of 128" in rec["sample"]
     full = bench.cpu_baseline(sc, tgt, rows=10 ** 6)           # clamped to the frame
     assert "(128 of 128" in full["sample"]
+    assert full["oracle_pairs"] > 0 and "oracle_pairs_band" in rec
+    assert full["one_core"]["value"] > 0 and set(full["configs"]) == {"tiny_128", "open_512"}
+    assert full["cpu_model"] and "_gauss" in full
+
+
+def test_stage_rooflines_take_the_larger_bound():
+    sys.path.insert(0, ROOT)
+    import bench
+    ms = {"sample_bin": 1.0, "fwd_l2": 1.0, "bwd_gauss": 1.0, "bwd_curves": 1.0}
+    st = bench.stage_rooflines(ms, n_gauss=10 ** 6, pairs=10 ** 7, n_alg=10 ** 9, n_tiles=10 ** 4,
+                               hw=10 ** 6, trans_slots=2.0, bw_gbs=8000.0, lane_ops=4e13)
+    # sample_bin: 48e6 + 4e7 + 8e4 bytes at 8 TB/s
+    assert abs(st["sample_bin"]["roof_ms"] - (48e6 + 4e7 + 8e4) / 8e12 * 1e3) < 1e-12
+    assert st["sample_bin"]["bound"] == "hbm" and st["bwd_curves"]["bound"] == "hbm"
+    # forward: 1e9 pairs x (13 + 2) slots at 4e13 slots/s
+    assert st["fwd_l2"]["bound"] == "alu"
+    assert abs(st["fwd_l2"]["roof_ms"] - 1e9 * 15 / 4e13 * 1e3) < 1e-9
+    assert abs(st["bwd_gauss"]["roof_ms"] - 1e9 * 34 / 4e13 * 1e3) < 1e-9

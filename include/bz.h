@@ -167,8 +167,10 @@ typedef struct {
 /* Tile lists.  ids[ranges[2t] .. ranges[2t+1]) are the Gaussians whose support
  * may reach a pixel of tile t (row-major tiles), in increasing draw order.
  * status (device, 4 x int64): [0] pairs required by the last bz_bin,
- * [1] flags: bit 0 = ids capacity exceeded (the lists are then invalid and the
- * render calls fill the image with NaN), bit 1 = non-finite Gaussian skipped.
+ * [1] flags: bit 0 = the lists are invalid (ids capacity exceeded, or bit 2)
+ * and the render calls fill the image with NaN, bit 1 = non-finite Gaussian
+ * skipped, bit 2 = a Gaussian's emitted tiles disagreed with its count (an
+ * internal consistency check; never expected).
  * workspace: device scratch of bz_workspace_size bytes, 256-byte aligned. */
 typedef struct {
     int64_t cap_pairs;       /* capacity of ids, < 2^32 */
@@ -291,10 +293,11 @@ bz_status bz_sample_bin(const bz_curves *c, const bz_opts *opts, bz_gaussians *g
 bz_status bz_sample_bin_static(const bz_curves *c, const bz_opts *opts, bz_gaussians *g,
                                bz_bins *b, hipStream_t stream);
 
-/* Sec. 3.4 tile pipeline: bound each Gaussian's truncated support
- * (1/2 d^T Q d <= -ln g_min), list it in every tile the bound touches, sort
- * the (tile, Gaussian) pairs by tile keeping draw order, and write per-tile
- * ranges.  Uses b->workspace; reports through b->status. */
+/* Sec. 3.4 tile pipeline: list each Gaussian in every tile its truncated
+ * support (1/2 d^T Sigma^-1 d <= -ln g_min, slightly inflated) reaches, tile
+ * row by tile row (the ellipse's span over the row's pixels, not its bounding
+ * box), sort the (tile, Gaussian) pairs by tile keeping draw order, and write
+ * per-tile ranges.  Uses b->workspace; reports through b->status. */
 bz_status bz_bin(const bz_gaussians *g, const bz_opts *opts, bz_bins *b, hipStream_t stream);
 
 /* Sec. 3.4 blending: per pixel, front to back over its tile's list,

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libbz.so")
 BZ_OK, BZ_ERR_ARG, BZ_ERR_CAPACITY, BZ_ERR_HIP, BZ_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_OVERFLOW = 1
 STATUS_NONFINITE = 2
+STATUS_LIST_MISMATCH = 4
 
 
 class Canvas(C.Structure):
@@ -379,7 +380,10 @@ class Rasterizer:
     def ensure_capacity(self, slack: float = 1.25) -> bool:
         """After a bz_bin: grow the pair buffer if it overflowed (synchronises).
         Returns True when it had to grow (the caller then bins again)."""
-        if self.flags() & STATUS_OVERFLOW:
+        f = self.flags()
+        if f & STATUS_LIST_MISMATCH:
+            raise RuntimeError("libbz tile lists inconsistent (emitted tiles differ from counts)")
+        if f & STATUS_OVERFLOW:
             self._alloc_pairs(int(math.ceil(self.pairs_required() * slack)) + 1024)
             return True
         return False

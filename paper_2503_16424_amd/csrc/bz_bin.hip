@@ -1,13 +1,15 @@
 // bz_bin.hip -- tile lists of the splatting pipeline (Sec. 3.4).
 //
-// 1. count : per Gaussian, the axis-aligned box of its truncated support
-//            1/2 d^T Q d <= -ln g_min (half extents sqrt(2 P Sigma_xx),
-//            sqrt(2 P Sigma_yy), padded), clipped to the canvas -> tile rectangle
-//            and number of tiles.
+// 1. count : per Gaussian, the tiles its truncated support
+//            1/2 d^T Sigma^-1 d <= -ln g_min (slightly inflated) reaches: the
+//            tile rows of its bounding box on the canvas, and in each row the
+//            tile columns the ellipse itself spans over that row's pixels
+//            (tile_rect) -> tile rectangle and number of tiles.
 // 2. scan  : exclusive scan of the counts -> pair offsets; the total is the pair
 //            count (status[0]); more than cap_pairs sets the overflow flag and
 //            every later stage of this call does nothing.
-// 3. emit  : (tile, Gaussian) pairs, Gaussians in draw order.
+// 3. emit  : (tile, Gaussian) pairs, Gaussians in draw order, row by row with
+//            the same per-row spans the count used.
 // 4. sort  : stable LSD radix sort on the tile id only (8-bit digits, LDS
 //            ranking with wave ballots, LDS staging so that the scattered
 //            writes leave a block as contiguous runs).  Stability keeps the
@@ -68,7 +70,8 @@ __device__ inline void gauss_canvas(const bz_canvas *cv, int n_canvas, int64_t g
 }
 
 __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, int64_t n, int W,
-                                               int H, float inv_tw, float inv_th, float two_p,
+                                               int H, float inv_tw, float inv_th, int th,
+                                               float two_p,
                                                const bz_canvas *__restrict__ cv, int n_canvas,
                                                uint32_t *__restrict__ counts,
                                                ushort4 *__restrict__ rects, int64_t *status) {
@@ -79,8 +82,8 @@ __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, i
     gauss_canvas(cv, n_canvas, g, W, H, tiles_x_unused, base_unused);
     ushort4 rc;
     bool finite;
-    const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, inv_tw, inv_th, two_p, rc,
-                                   finite);
+    const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, inv_tw, inv_th, th, two_p,
+                                   rc, finite);
     if (!finite) atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
     counts[g] = cnt;
     rects[g] = rc;
@@ -165,60 +168,157 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part
 
 // --- pair emission ---------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ offs,
-                                              const ushort4 *__restrict__ rects, int64_t n,
-                                              int tiles_x, const bz_canvas *__restrict__ cv,
-                                              int n_canvas, uint32_t *__restrict__ keys,
-                                              uint32_t *__restrict__ vals,
-                                              const int64_t *status) {
-    // The 256 Gaussians of a block own one contiguous output range (their
-    // scan offsets are consecutive), so the block writes that range with
-    // consecutive threads on consecutive positions; each position finds its
-    // Gaussian by binary search over the block's offsets in LDS.  In a batch
-    // the key is the global tile: the canvas's first tile + its local tile.
-    __shared__ uint32_t s_off[257];
-    __shared__ ushort4 s_rect[256];
-    __shared__ uint32_t s_base[256];
-    __shared__ int s_tx[256];
-    if (status[1] & Status::kOverflow) return;
-    const int64_t g0 = (int64_t)blockIdx.x * 256;
-    const int nb = (int)(n - g0 < 256 ? n - g0 : 256);
-    const int t = threadIdx.x;
-    if (t < nb) {
-        s_off[t] = offs[g0 + t];
-        s_rect[t] = rects[g0 + t];
-        int W = 0, H = 0, tx = tiles_x;
-        uint32_t base = 0;
-        gauss_canvas(cv, n_canvas, g0 + t, W, H, tx, base);
-        s_base[t] = base;
-        s_tx[t] = tx;
-    }
-    __syncthreads();
-    if (t == 0) {
-        const ushort4 rc = s_rect[nb - 1];
-        const uint32_t c = rc.x <= rc.z && rc.y <= rc.w
-                               ? (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1)
-                               : 0u;
-        s_off[nb] = s_off[nb - 1] + c;
-    }
-    __syncthreads();
-    const uint32_t begin = s_off[0], total = s_off[nb] - begin;
-    for (uint32_t i = t; i < total; i += 256) {
-        const uint32_t o = begin + i;
-        // last Gaussian whose offset <= o (offsets ascend; s_off[0] <= o):
-        // eight fixed halving steps over the block's 256
-        int lo = 0;
+// Pair emission, one wave per 64 consecutive Gaussians, which own one
+// contiguous output range (their scan offsets are consecutive).  Their tile
+// rows are taken as (Gaussian, row) items, kRowChunk at a time: every item's
+// span of tile columns (support_row: the same function of the same record
+// bits as the count, so the widths add up to the counts exactly) and an
+// exclusive scan of the widths give each row its place; the wave then writes
+// the chunk's output range, consecutive lanes on consecutive positions, each
+// finding its row by binary search.  In a batch the key is the global
+// tile: the canvas's first tile + its local tile.  Every Gaussian's last row
+// must end where its range ends; otherwise the lists are marked invalid
+// (never expected), and nothing downstream reads them.  Any position left
+// unwritten then holds the key one past the last tile, which sorts after
+// every real tile and no range covers.
+constexpr int kEmitG = 64;        // Gaussians per wave
+constexpr int kRowChunk = 256;    // row items per round
+
+// Exclusive prefix over the wave of one value per lane; total in *tot.
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
+    uint32_t x = v;
 #pragma unroll
-        for (int step = 128; step >= 1; step >>= 1) {
-            const int mid = lo + step;
-            if (mid < nb && s_off[mid] <= o) lo = mid;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+        if ((threadIdx.x & 63) >= d) x += y;
+    }
+    tot = (uint32_t)__shfl((int)x, 63, 64);
+    return x - v;
+}
+
+__device__ inline void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64) void k_emit(const float4 *__restrict__ rec,
+                                             const uint32_t *__restrict__ offs,
+                                             const ushort4 *__restrict__ rects, int64_t n, int W,
+                                             int H, int tiles_x, float inv_tw, int th,
+                                             float two_p, const bz_canvas *__restrict__ cv,
+                                             int n_canvas, uint32_t end_key,
+                                             uint32_t *__restrict__ keys,
+                                             uint32_t *__restrict__ vals,
+                                             const int64_t *status) {
+    __shared__ uint32_t s_rows[kEmitG + 1];   // exclusive prefix of tile rows per Gaussian
+    __shared__ uint32_t s_off[kEmitG + 1];    // pair offsets (the last: the wave's end)
+    __shared__ Support s_sup[kEmitG];         // each Gaussian's support, computed once
+    __shared__ uint32_t s_key0[kEmitG];       // key of tile (0, first row of its rectangle)
+    __shared__ uint16_t s_ty0[kEmitG];        // first tile row of its rectangle
+    __shared__ int s_tx[kEmitG];              // tiles per row of its canvas
+    __shared__ uint32_t s_item_off[kRowChunk + 1];
+    __shared__ uint32_t s_item_key[kRowChunk];  // key of the row's first tile
+    __shared__ uint8_t s_item_g[kRowChunk];     // Gaussian of the row (in the wave)
+    if (status[1] & Status::kOverflow) return;
+    const int64_t g0 = (int64_t)blockIdx.x * kEmitG;
+    const int nb = (int)(n - g0 < kEmitG ? n - g0 : kEmitG);
+    const int t = threadIdx.x;
+    uint32_t my_rows = 0;
+    if (t < nb) {
+        const int64_t g = g0 + t;
+        const ushort4 rc = rects[g];
+        s_off[t] = offs[g];
+        int Wc = W, Hc = H, txc = tiles_x;
+        uint32_t base = 0;
+        gauss_canvas(cv, n_canvas, g, Wc, Hc, txc, base);
+        Support sp;
+        bool finite;
+        // the count's function on the same record bits; a Gaussian without
+        // support has the empty rectangle and no rows
+        if (rc.x <= rc.z && rc.y <= rc.w &&
+            support_of(rec[3 * g], rec[3 * g + 1], Wc, Hc, two_p, sp, finite)) {
+            my_rows = (uint32_t)(rc.w - rc.y + 1);
+            s_sup[t] = sp;
+            s_key0[t] = base + (uint32_t)rc.y * (uint32_t)txc;
+            s_ty0[t] = rc.y;
+            s_tx[t] = txc;
         }
-        const ushort4 rc = s_rect[lo];
-        const uint32_t w = (uint32_t)(rc.z - rc.x + 1);
-        const uint32_t li = o - s_off[lo];
-        const uint32_t ty = rc.y + li / w, tx = rc.x + li % w;
-        keys[o] = s_base[lo] + ty * (uint32_t)s_tx[lo] + tx;
-        vals[o] = (uint32_t)(g0 + lo);
+    }
+    uint32_t nrows;
+    s_rows[t] = wave_excl_scan(my_rows, nrows);
+    if (t == 0) {
+        s_rows[kEmitG] = nrows;
+        s_off[nb] = g0 + nb < n ? offs[g0 + nb] : (uint32_t)status[0];
+    }
+    wave_lds_fence();
+    uint32_t out = s_off[0];                   // next output position
+    for (uint32_t c0 = 0; c0 < nrows; c0 += kRowChunk) {
+        const uint32_t ci = nrows - c0 < (uint32_t)kRowChunk ? nrows - c0 : (uint32_t)kRowChunk;
+        // the round's rows (four per lane, consecutive): span of tile columns, width
+        uint32_t wsum = 0;
+        uint32_t wid[kRowChunk / 64];
+#pragma unroll
+        for (int j = 0; j < kRowChunk / 64; ++j) {
+            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
+            wid[j] = 0;
+            if (it < ci) {
+                const uint32_t r = c0 + it;
+                int lo = 0;                    // last Gaussian whose first row <= r
+#pragma unroll
+                for (int step = kEmitG / 2; step >= 1; step >>= 1)
+                    if (lo + step < nb && s_rows[lo + step] <= r) lo += step;
+                const int dr = (int)(r - s_rows[lo]);
+                int cl, ch;
+                support_row(s_sup[lo], (int)s_ty0[lo] + dr, th, inv_tw, cl, ch);
+                wid[j] = ch >= cl ? (uint32_t)(ch - cl + 1) : 0u;
+                s_item_key[it] = s_key0[lo] + (uint32_t)dr * (uint32_t)s_tx[lo] + (uint32_t)cl;
+                s_item_g[it] = (uint8_t)lo;
+                wsum += wid[j];
+            }
+        }
+        uint32_t cnt;
+        uint32_t ex = wave_excl_scan(wsum, cnt);
+#pragma unroll
+        for (int j = 0; j < kRowChunk / 64; ++j) {
+            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
+            if (it < ci) s_item_off[it] = ex;
+            ex += wid[j];
+        }
+        if (t == 0) s_item_off[ci] = cnt;
+        wave_lds_fence();
+#pragma unroll
+        for (int j = 0; j < kRowChunk / 64; ++j) {
+            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
+            if (it < ci) {
+                const int gl = s_item_g[it];
+                if (c0 + it + 1 == s_rows[gl + 1] && out + s_item_off[it + 1] != s_off[gl + 1])
+                    atomicOr((unsigned long long *)&status[1],
+                             (unsigned long long)(Status::kOverflow | Status::kListMismatch));
+            }
+        }
+        // consecutive lanes on consecutive positions (coalesced stores), each
+        // finding its row by binary search
+        for (uint32_t i = t; i < cnt; i += 64) {
+            int lo = 0;                        // last row item whose offset <= i
+#pragma unroll
+            for (int step = kRowChunk / 2; step >= 1; step >>= 1)
+                if ((uint32_t)(lo + step) < ci && s_item_off[lo + step] <= i) lo += step;
+            const uint32_t o = out + i;
+            const int gl = s_item_g[lo];
+            // only inside the Gaussian's own range (the counts agree, so this holds)
+            if (o >= s_off[gl] && o < s_off[gl + 1]) {
+                keys[o] = s_item_key[lo] + (i - s_item_off[lo]);
+                vals[o] = (uint32_t)(g0 + gl);
+            }
+        }
+        out += cnt;
+        wave_lds_fence();
+    }
+    // positions of the wave's range no row filled
+    for (uint32_t o = out + t; o < s_off[nb]; o += 64) {
+        keys[o] = end_key;
+        vals[o] = (uint32_t)(g0 + nb - 1);
     }
 }
 
@@ -387,7 +487,7 @@ constexpr int kRangeItems = 8;
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ keys,
                                                 const int64_t *status, int64_t cap,
-                                                uint32_t *__restrict__ ranges) {
+                                                uint32_t n_tiles, uint32_t *__restrict__ ranges) {
     if (status[1] & Status::kOverflow) return;
     const int64_t n0 = status[0];
     const int64_t n = n0 < cap ? n0 : cap;
@@ -408,7 +508,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ key
 #pragma unroll
     for (int j = 0; j < kRangeItems; ++j) {
         const int64_t i = i0 + j;
-        if (i >= n) break;
+        if (i >= n || k[j] >= n_tiles) break;      // keys past the last tile: no range
         if ((j == 0 ? prev : k[j - 1]) != k[j]) ranges[2 * (int64_t)k[j]] = (uint32_t)i;
         if (k[j + 1] != k[j]) ranges[2 * (int64_t)k[j] + 1] = (uint32_t)(i + 1);
     }
@@ -467,7 +567,7 @@ BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
     BinLayout L;
     L.n_tiles = num_tiles(o);
     int bits = 0;
-    while ((int64_t(1) << bits) < L.n_tiles) ++bits;
+    while ((int64_t(1) << bits) <= L.n_tiles) ++bits;   // keys 0 .. n_tiles
     if (bits == 0) bits = 1;
     L.key_bits = bits;
     L.passes = (bits + 7) / 8;
@@ -530,8 +630,8 @@ void bin_prepare(const BinBufs &u, const bz_bins &b, hipStream_t s) {
 }
 
 // From the per-Gaussian tile counts and rectangles: offsets, pairs, sort, ranges.
-hipError_t bin_finish(const BinBufs &u, int64_t n, const bz_opts &o, const bz_bins &b,
-                      hipStream_t s) {
+hipError_t bin_finish(const float *rec, const BinBufs &u, int64_t n, const bz_opts &o,
+                      const bz_bins &b, hipStream_t s) {
     const BinLayout &L = u.L;
     const int tx = (int)tiles_x(o);
     const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
@@ -541,8 +641,10 @@ hipError_t bin_finish(const BinBufs &u, int64_t n, const bz_opts &o, const bz_bi
     // The final radix pass must land in (keys_a, ids).
     bool even = (L.passes % 2) == 0;
     uint32_t *k0 = even ? u.keys_a : u.keys_b, *v0 = even ? b.ids : u.vals_b;
-    hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 256)), dim3(256), 0, s, u.counts, u.rects, n, tx, cv,
-                       ncv, k0, v0, (const int64_t *)b.status);
+    hipLaunchKernelGGL(k_emit, dim3(cdiv(n, kEmitG)), dim3(kEmitG), 0, s, (const float4 *)rec,
+                       u.counts, u.rects, n, o.width, o.height, tx, 1.0f / o.tile_w, o.tile_h,
+                       support_two_p(o), cv, ncv, (uint32_t)L.n_tiles, k0, v0,
+                       (const int64_t *)b.status);
     uint32_t *kin = k0, *vin = v0;
     for (int p = 0; p < L.passes; ++p) {
         int shift = 8 * p;
@@ -560,7 +662,7 @@ hipError_t bin_finish(const BinBufs &u, int64_t n, const bz_opts &o, const bz_bi
         vin = vout;
     }
     hipLaunchKernelGGL(k_ranges, dim3(cdiv(cdiv(b.cap_pairs, kRangeItems), 256)), dim3(256), 0, s,
-                       kin, (const int64_t *)b.status, b.cap_pairs, b.ranges);
+                       kin, (const int64_t *)b.status, b.cap_pairs, (uint32_t)L.n_tiles, b.ranges);
     return hipGetLastError();
 }
 
@@ -574,9 +676,9 @@ hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_
     const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
     const int ncv = o.batch ? o.batch->n_canvas : 0;
     hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, (const float4 *)rec_f, n,
-                       o.width, o.height, 1.0f / o.tile_w, 1.0f / o.tile_h, support_two_p(o), cv,
-                       ncv, u.counts, u.rects, b.status);
-    return bin_finish(u, n, o, b, s);
+                       o.width, o.height, 1.0f / o.tile_w, 1.0f / o.tile_h, o.tile_h,
+                       support_two_p(o), cv, ncv, u.counts, u.rects, b.status);
+    return bin_finish(rec_f, u, n, o, b, s);
 }
 
 hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, const bz_bins &b,
@@ -585,11 +687,11 @@ hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, c
     const BinBufs u = bin_bufs(o, n, b);
     bin_prepare(u, b, s);
     if (n == 0) return hipGetLastError();
-    const BinCount bc = {u.counts, u.rects, b.status, 1.0f / o.tile_w, 1.0f / o.tile_h,
+    const BinCount bc = {u.counts, u.rects, b.status, 1.0f / o.tile_w, 1.0f / o.tile_h, o.tile_h,
                          support_two_p(o)};
     hipError_t e = launch_sample(c, o, rec, &bc, s);
     if (e != hipSuccess) return e;
-    return bin_finish(u, n, o, b, s);
+    return bin_finish(rec, u, n, o, b, s);
 }
 
 }  // namespace bz

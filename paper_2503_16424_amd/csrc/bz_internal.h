@@ -43,6 +43,7 @@ constexpr float kCullPadBox = 0.02f;       // px added to the half extents
 struct Status {
     static constexpr int64_t kOverflow = 1;
     static constexpr int64_t kNonFinite = 2;
+    static constexpr int64_t kListMismatch = 4;   // set with kOverflow: lists invalid
 };
 
 // ---------------------------------------------------------------------------
@@ -160,47 +161,115 @@ __host__ __device__ inline void shape_conic(float ex, float ey, float k, float &
     qyy = fmaf(k2 * ex, ex, ey * ey);
 }
 
-// Tiles of a Gaussian record (mean hi + lo, shape (e, k), opacity): the tile
-// rectangle (x0, y0, x1, y1) that the bounding box of its truncated support
-// (1/2 d^T Sigma^-1 d <= two_p / 2) reaches on a W x H canvas, and the number
-// of tiles in it; 0 with rect (1, 1, 0, 0) when it reaches none or the shape
-// is degenerate.  finite: the record's mean, shape and opacity are finite.
-// Half extents sqrt(two_p Sigma_xx), sqrt(two_p Sigma_yy) with
-// Sigma_xx = (e.x^2 + e.y^2 / k^2) / |e|^4 and Sigma_yy likewise (Sigma =
-// sigma_x^2 t t^T + sigma_y^2 n n^T, no cancellation); they use the hardware
-// reciprocal and square root (about one ulp): the box slack (kCullSlackBox,
-// kCullPadBox) exceeds their error by orders of magnitude, so the box stays
-// conservative.  inv_tw, inv_th: 1 / tile width and height.
-__device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv_tw,
-                                     float inv_th, float two_p, ushort4 &rc, bool &finite) {
-    const float mx = m.x + m.z, my = m.y + m.w;
+// Support of a Gaussian record (mean hi + lo, shape (e, k), opacity) for the
+// tile lists: the truncated support 1/2 d^T Sigma^-1 d <= two_p / 2, inflated
+// (radius^2 x kCullSlackBox^2, kCullPadBox px) so that float rounding anywhere
+// in the pipeline cannot drop a pixel whose kernel value exceeds g_min.
+// Sigma = sigma_x^2 t t^T + sigma_y^2 n n^T is formed from (e, k) as sums of
+// positive terms: Sigma_xx = (e.x^2 + e.y^2 / k^2) / |e|^4, Sigma_yy likewise,
+// Sigma_xy = e.x e.y (1 - 1/k^2) / |e|^4, det = 1 / (k^2 |e|^4).  At a row
+// offset dy the ellipse spans x = mx + a dy +- sqrt((r2 - dy^2 / Sigma_yy) D),
+// a = Sigma_xy / Sigma_yy, D = det / Sigma_yy; over a band of rows its right
+// edge peaks at dy = dys = Sigma_xy sqrt(r2 / Sigma_xx) (the ellipse's
+// rightmost point) and its left edge at -dys.  The reciprocals and square
+// roots are the hardware ones (about one ulp), far inside the inflation.
+struct Support {
+    float mx, my;            // mean
+    float a, D, isyy, dys;   // row geometry (see above)
+    float r2;                // inflated radius^2
+    int px0, px1, py0, py1;  // bounding box of the support in pixels, on the canvas
+};
+
+// The support of a record; false when it reaches no pixel of the W x H canvas
+// or the shape is degenerate.  finite: mean, shape and opacity are finite.
+__device__ inline bool support_of(float4 m, float4 q, int W, int H, float two_p, Support &s,
+                                  bool &finite) {
+    // no contraction: counting and emission must take the same operations
+#pragma clang fp contract(off)
+    s.mx = m.x + m.z;
+    s.my = m.y + m.w;
     const float e2 = q.x * q.x + q.y * q.y;
-    finite = isfinite(mx) && isfinite(my) && isfinite(q.x) && isfinite(q.y) && isfinite(q.z) &&
-             isfinite(q.w);
-    rc = make_ushort4(1, 1, 0, 0);
-    if (!(finite && e2 > 0.f && q.z > 0.f && isfinite(e2))) return 0u;
+    finite = isfinite(s.mx) && isfinite(s.my) && isfinite(q.x) && isfinite(q.y) &&
+             isfinite(q.z) && isfinite(q.w);
+    if (!(finite && e2 > 0.f && q.z > 0.f && isfinite(e2))) return false;
     const float ik2 = __builtin_amdgcn_rcpf(q.z * q.z);
     const float ie4 = __builtin_amdgcn_rcpf(e2 * e2);
     const float sxx = fmaf(q.y * q.y, ik2, q.x * q.x) * ie4;
     const float syy = fmaf(q.x * q.x, ik2, q.y * q.y) * ie4;
-    if (!(isfinite(sxx) && isfinite(syy))) return 0u;
+    const float sxy = q.x * q.y * (1.f - ik2) * ie4;
+    const float det = ik2 * ie4;
+    if (!(isfinite(sxx) && isfinite(syy) && isfinite(det) && sxx > 0.f && syy > 0.f)) return false;
+    s.r2 = two_p * (kCullSlackBox * kCullSlackBox);
+    s.isyy = __builtin_amdgcn_rcpf(syy);
+    s.a = sxy * s.isyy;
+    s.D = det * s.isyy;
+    s.dys = sxy * __builtin_amdgcn_sqrtf(s.r2 * __builtin_amdgcn_rcpf(sxx));
     const float hx = __builtin_amdgcn_sqrtf(two_p * sxx) * kCullSlackBox + kCullPadBox;
     const float hy = __builtin_amdgcn_sqrtf(two_p * syy) * kCullSlackBox + kCullPadBox;
     // pixel x covers centre x + 1/2
-    float fx0 = ceilf(mx - hx - 0.5f), fx1 = floorf(mx + hx - 0.5f);
-    float fy0 = ceilf(my - hy - 0.5f), fy1 = floorf(my + hy - 0.5f);
-    fx0 = fmaxf(fx0, 0.f);
-    fy0 = fmaxf(fy0, 0.f);
-    fx1 = fminf(fx1, (float)(W - 1));
-    fy1 = fminf(fy1, (float)(H - 1));
-    if (!(fx0 <= fx1 && fy0 <= fy1)) return 0u;
-    // tile of pixel p (a whole number below 2^16): (p + 1/2) / t lies at least
-    // 1 / (2t) from a whole number, far beyond the float error of the
-    // product, so truncating it gives p / t exactly
-    const int tx0 = (int)((fx0 + 0.5f) * inv_tw), tx1 = (int)((fx1 + 0.5f) * inv_tw);
-    const int ty0 = (int)((fy0 + 0.5f) * inv_th), ty1 = (int)((fy1 + 0.5f) * inv_th);
-    rc = make_ushort4(tx0, ty0, tx1, ty1);
-    return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    const float fx0 = fmaxf(ceilf(s.mx - hx - 0.5f), 0.f);
+    const float fx1 = fminf(floorf(s.mx + hx - 0.5f), (float)(W - 1));
+    const float fy0 = fmaxf(ceilf(s.my - hy - 0.5f), 0.f);
+    const float fy1 = fminf(floorf(s.my + hy - 0.5f), (float)(H - 1));
+    if (!(fx0 <= fx1 && fy0 <= fy1)) return false;
+    s.px0 = (int)fx0;
+    s.px1 = (int)fx1;
+    s.py0 = (int)fy0;
+    s.py1 = (int)fy1;
+    return true;
+}
+
+// Pixel columns [x0, x1] of the support over pixel rows [ya, yb] (inside its
+// box); x1 < x0 when it reaches none of them.
+__device__ inline void support_cols(const Support &s, int ya, int yb, int &x0, int &x1) {
+#pragma clang fp contract(off)
+    const float da = (float)ya + 0.5f - s.my, db = (float)yb + 0.5f - s.my;
+    const float dr = fminf(fmaxf(s.dys, da), db), dl = fminf(fmaxf(-s.dys, da), db);
+    const float hr = __builtin_amdgcn_sqrtf(fmaxf(s.r2 - dr * dr * s.isyy, 0.f) * s.D);
+    const float hl = __builtin_amdgcn_sqrtf(fmaxf(s.r2 - dl * dl * s.isyy, 0.f) * s.D);
+    const float xr = fmaf(s.a, dr, s.mx) + hr + kCullPadBox;
+    const float xl = fmaf(s.a, dl, s.mx) - hl - kCullPadBox;
+    x0 = max(s.px0, (int)fmaxf(ceilf(xl - 0.5f), -1.f));
+    x1 = min(s.px1, (int)fminf(floorf(xr - 0.5f), 65535.f));
+}
+
+// Tile of pixel p (a whole number below 2^16): (p + 1/2) / t lies at least
+// 1 / (2t) from a whole number, far beyond the float error of the product,
+// so truncating it gives p / t exactly.  inv_t = 1 / tile side.
+__device__ inline int tile_of(int p, float inv_t) { return (int)(((float)p + 0.5f) * inv_t); }
+
+// Tile columns [c0, c1] of tile row ty (of height th) that the support
+// reaches; c1 < c0 when none.
+__device__ inline void support_row(const Support &s, int ty, int th, float inv_tw, int &c0,
+                                   int &c1) {
+    const int ya = max(ty * th, s.py0), yb = min(ty * th + th - 1, s.py1);
+    int x0, x1;
+    support_cols(s, ya, yb, x0, x1);
+    c0 = tile_of(x0, inv_tw);
+    c1 = x0 <= x1 ? tile_of(x1, inv_tw) : c0 - 1;
+}
+
+// Tile rows of a record's support: rc = (x0, y0, x1, y1) the tile rectangle
+// of its bounding box ((1, 1, 0, 0) when it reaches no pixel), and the
+// number of (tile, Gaussian) pairs: the sum over the rectangle's tile rows of
+// the tile columns the support itself reaches there (support_row), which
+// leaves out the corners of the box that an elongated, rotated Gaussian never
+// touches.  finite: the record is finite.
+__device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv_tw,
+                                     float inv_th, int th, float two_p, ushort4 &rc,
+                                     bool &finite) {
+    Support s;
+    rc = make_ushort4(1, 1, 0, 0);
+    if (!support_of(m, q, W, H, two_p, s, finite)) return 0u;
+    const int ty0 = tile_of(s.py0, inv_th), ty1 = tile_of(s.py1, inv_th);
+    rc = make_ushort4(tile_of(s.px0, inv_tw), ty0, tile_of(s.px1, inv_tw), ty1);
+    uint32_t n = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        int c0, c1;
+        support_row(s, ty, th, inv_tw, c0, c1);
+        n += c1 >= c0 ? (uint32_t)(c1 - c0 + 1) : 0u;
+    }
+    return n;
 }
 
 // Where sampling writes the tile counts and rectangles for the binning that
@@ -211,6 +280,7 @@ struct BinCount {
     ushort4 *rects;
     int64_t *status;
     float inv_tw, inv_th;
+    int th;
     float two_p;
 };
 

@@ -77,8 +77,8 @@ __global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8
             if (kBin) {
                 ushort4 rc;
                 bool finite;
-                const uint32_t cnt = tile_rect(m, q, W, H, bc.inv_tw, bc.inv_th, bc.two_p, rc,
-                                               finite);
+                const uint32_t cnt = tile_rect(m, q, W, H, bc.inv_tw, bc.inv_th, bc.th,
+                                               bc.two_p, rc, finite);
                 bc.counts[v.g0 + idx] = cnt;
                 bc.rects[v.g0 + idx] = rc;
                 nonfinite |= !finite;

@@ -62,6 +62,7 @@ def psnr_from_mse(mse: float) -> float:
 class FitConfig:
     steps: int = 500
     optimizer: str = "adam"     # "adam" or "sgd"
+    momentum: float = 0.0       # sgd only
     lr_ctrl: float = 1e-2       # normalised coordinates
     lr_color: float = 1e-2      # Sec. 4.1
     lr_opacity: float = 1e-1    # Sec. 4.1
@@ -106,7 +107,7 @@ class Fitter:
         if c.optimizer == "adam":
             self.opt = torch.optim.Adam(groups)
         elif c.optimizer == "sgd":
-            self.opt = torch.optim.SGD(groups)
+            self.opt = torch.optim.SGD(groups, momentum=c.momentum)
         else:
             raise ValueError(f"unknown optimizer {c.optimizer!r}")
 

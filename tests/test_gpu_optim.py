@@ -223,22 +223,28 @@ def test_gradient_at_the_512_workload_after_adam_steps(torch_cuda):
 
 
 def test_fit_checkpoint_resume_matches_uninterrupted_run(torch_cuda, tmp_path):
-    """60 Adam steps straight against 30 steps, a checkpoint (.npz of the
-    parameters, Adam moments and generator states), a fresh rasterizer and 30
-    resumed steps: the same parameters, up to the run-to-run spread of the
-    backward's float atomics (measured here with a second straight run)."""
+    """60 optimiser steps straight against 30 steps, a checkpoint (.npz of the
+    parameters, the optimiser's momentum buffers and the generator states), a
+    fresh rasterizer and 30 resumed steps: the same parameters, up to the
+    run-to-run spread of the backward's float atomics (measured here with a
+    second straight run).  Momentum SGD keeps that spread at the rounding
+    level (Adam's normalisation amplifies it chaotically; its moments' round
+    trip is checked bit for bit on the host)."""
     torch = torch_cuda
     from paper_2503_16424_amd import bz
     from paper_2503_16424_amd.optim import FitConfig, fit
     hidden = scenes.uniform_open(21, 96, 80, 300, 16)
     clean = torch.as_tensor(bz.Rasterizer(hidden).render().cpu().numpy(), device="cuda")
     sc = scenes.uniform_open(22, 96, 80, 120, 16)
-    cfg = FitConfig(steps=60, log_every=20)
+    kw = dict(optimizer="sgd", momentum=0.9, lr_ctrl=2.0, lr_color=20.0, lr_opacity=20.0,
+              lr_width=20.0, log_every=20)
+    cfg = FitConfig(steps=60, **kw)
 
     def params(r):
         return np.concatenate([r.ctrl.cpu().numpy().ravel(), r.color.cpu().numpy().ravel(),
                                r.opacity.cpu().numpy().ravel(), r.stroke_w.cpu().numpy().ravel()])
 
+    start = params(bz.Rasterizer(sc))
     straight = []
     for _ in range(2):
         r = bz.Rasterizer(sc)
@@ -246,17 +252,19 @@ def test_fit_checkpoint_resume_matches_uninterrupted_run(torch_cuda, tmp_path):
         straight.append(params(r))
     path = str(tmp_path / "fit.npz")
     r = bz.Rasterizer(sc)
-    fit(r, clean, FitConfig(steps=30, log_every=20), checkpoint_path=path, checkpoint_every=30)
+    fit(r, clean, FitConfig(steps=30, **kw), checkpoint_path=path, checkpoint_every=30)
     mid = params(r)
     r2 = bz.Rasterizer(sc)
     fit(r2, clean, cfg, resume_from=path)
     resumed = params(r2)
+    moved = float(np.abs(straight[0] - mid).max())
     spread = float(np.abs(straight[1] - straight[0]).max())
     err = float(np.abs(resumed - straight[0]).max())
-    _note(f"  resumed vs straight {err:.2e}, straight vs straight {spread:.2e}")
-    assert not np.array_equal(mid, straight[0])          # the resumed half did work
-    assert err <= max(10.0 * spread, 1e-5)
-    # the checkpoint holds the step and the moments of all four groups
+    _note(f"  resumed vs straight {err:.2e}, straight vs straight {spread:.2e}, "
+          f"second half moved {moved:.2e}, whole run {float(np.abs(straight[0] - start).max()):.2e}")
+    assert moved > 1e-3                                   # the resumed half did work
+    assert err <= max(10.0 * spread, 1e-4)
+    # the checkpoint holds the step and the momentum buffers of all four groups
     with np.load(path, allow_pickle=False) as f:
         assert int(f["step"]) == 30
-        assert all(f"opt_{g}_0_exp_avg_sq" in f.files for g in range(4))
+        assert all(f"opt_{g}_0_momentum_buffer" in f.files for g in range(4))

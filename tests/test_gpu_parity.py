@@ -87,6 +87,25 @@ def _aabb_tiles(mu, conic, W, H, tw, th, g_min, scale, pad):
     return ok, (x0 // tw).astype(int), (x1 // tw).astype(int), (y0 // th).astype(int), (y1 // th).astype(int)
 
 
+def _support_tiles(mu, conic, W, H, tw, th, g_min):
+    """(Gaussian, tile) pairs whose tile holds a pixel centre inside the exact
+    support ellipse (float64, a relative 1e-9 inside the boundary)."""
+    lim = -2.0 * math.log(g_min) * (1.0 - 1e-9)
+    ok, x0, x1, y0, y1 = _aabb_tiles(mu, conic, W, H, 1, 1, g_min, 1.0, 1.0)
+    tx = -(-W // tw)
+    out = set()
+    for g in np.nonzero(ok)[0]:
+        xs = np.arange(x0[g], x1[g] + 1)
+        ys = np.arange(y0[g], y1[g] + 1)
+        dx = xs[None, :] + 0.5 - mu[g, 0]
+        dy = ys[:, None] + 0.5 - mu[g, 1]
+        q = conic[g, 0] * dx * dx + 2 * conic[g, 1] * dx * dy + conic[g, 2] * dy * dy
+        iy, ix = np.nonzero(q <= lim)
+        for t in set(((ys[iy] // th) * tx + xs[ix] // tw).tolist()):
+            out.add((int(g), int(t)))
+    return out
+
+
 @pytest.mark.parametrize("name", ["tiny_128", "mixed_small_b", "mixed_R20"])
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
 def test_tile_lists_valid_and_complete(torch_cuda, name, tile):
@@ -107,16 +126,20 @@ def test_tile_lists_valid_and_complete(torch_cuda, name, tile):
         got.update((int(g), t) for g in lst)
     assert len(got) == r.pairs_required() == sum(e - s for s, e in ranges)
     gm = oracle.DEFAULTS["g_min"]
-    must = _aabb_tiles(o["mu"], o["conic"], sc.width, sc.height, tw, th, gm, 1.0, -1e-3)
     may = _aabb_tiles(o["mu"], o["conic"], sc.width, sc.height, tw, th, gm, 1.0012, 0.02 + 1e-3)
-    want_min, want_max = set(), set()
-    for which, (ok, x0, x1, y0, y1) in ((want_min, must), (want_max, may)):
-        for g in np.nonzero(ok)[0]:
-            for ty in range(y0[g], y1[g] + 1):
-                for txx in range(x0[g], x1[g] + 1):
-                    which.add((int(g), ty * tx + txx))
+    want_max = set()
+    ok, x0, x1, y0, y1 = may
+    for g in np.nonzero(ok)[0]:
+        for ty in range(y0[g], y1[g] + 1):
+            for txx in range(x0[g], x1[g] + 1):
+                want_max.add((int(g), ty * tx + txx))
+    # required: every tile holding a pixel centre inside the exact support
+    # ellipse d^T Q d <= -2 ln g_min (brute force over the box's pixels)
+    want_min = _support_tiles(o["mu"], o["conic"], sc.width, sc.height, tw, th, gm)
     assert want_min <= got, f"{len(want_min - got)} required pairs missing"
     assert got <= want_max, f"{len(got - want_max)} pairs outside the padded support box"
+    # the lists stay close to the support: at most 10% more pairs than it needs
+    assert len(got) <= 1.1 * len(want_min) + 16, (len(got), len(want_min))
 
 
 @pytest.mark.parametrize("name", list(SCENES) + ["open_512"])

@@ -95,16 +95,21 @@ struct TileArgs {
     float l2_scale;
 };
 
-// Entry of the wave's LDS slice, for both sweeps: the mean relative to the
-// quad's first pixel centre (qx0, qy0), so a pixel's offset from it is one
-// subtraction from the pixel's place in the quad (0..7 in x and y); the record's
-// mean is hi + lo and hi - qx0 is exact for any Gaussian near the quad, so the
-// relative mean is rounded once.  The shape as two scaled axis vectors: with
-// e' = e sqrt(log2(e) / 2) and f = k e', the base-2 exponent of the kernel is
-// p2 = (e' . d)^2 + (f x d)^2 (f x d = f.x dy - f.y dx), a sum of two squares.
+// Entry of the wave's LDS slice.  The shape as two scaled axis vectors: with
+// e' = e sqrt(log2(e) / 2) and f = k e', the base-2 exponent of the kernel at
+// offset d = pixel - mean is p2 = u^2 + w^2, u = e' . d, w = f x d (= f.x dy
+// - f.y dx), a sum of two squares.  The mean is taken relative to the quad's
+// first pixel centre (qx0, qy0): the record's mean is hi + lo and hi - qx0 is
+// exact for any Gaussian near the quad, so the relative mean m' is rounded
+// once, and a pixel's offset is its place in the quad l (0..7 in x and y)
+// minus m'.
+// - The front-to-back sweep (kSweep) needs u and w only: with u0 = e' . m'
+//   and w0 = f x m' staged, u = e' . l - u0 and w = f x l - w0 cost two FMAs
+//   each and no offsets.
+// - The reverse pass also needs the offsets (conic gradient) and stages m'.
 struct Staged {
-    float4 m;   // mean - (qx0, qy0), e'.x, e'.y
-    float4 q;   // f.x, f.y, Gaussian id (bit pattern), o' = o / (1 - g_min)
+    float4 m;   // kSweep: -u0, -w0, e'.x, e'.y;  else: m'.x, m'.y, e'.x, e'.y
+    float4 q;   // f.x, f.y, (unused), o' = o / (1 - g_min)
     float4 c;   // r, g, b, o' * g_min
 };
 
@@ -113,6 +118,7 @@ constexpr float kHalfLog2eSqrt = 0.84932180028801907f;
 
 // Load a record and compute its LDS constants.  q receives the record's shape
 // (e.x, e.y, k, o).
+template <bool kSweep>
 __device__ inline void stage_record(const TileArgs &a, uint32_t id, float qx0, float qy0,
                                     Staged &st, float4 &q) {
     const float4 m = a.rec[3 * (int64_t)id];
@@ -120,29 +126,48 @@ __device__ inline void stage_record(const TileArgs &a, uint32_t id, float qx0, f
     const float4 c = a.rec[3 * (int64_t)id + 2];
     const float op = q.w * a.inv_1mg;
     const float ex = kHalfLog2eSqrt * q.x, ey = kHalfLog2eSqrt * q.y;
-    st.m = make_float4((m.x - qx0) + m.z, (m.y - qy0) + m.w, ex, ey);
-    st.q = make_float4(q.z * ex, q.z * ey, __uint_as_float(id), op);
+    const float fx = q.z * ex, fy = q.z * ey;
+    const float mx = (m.x - qx0) + m.z, my = (m.y - qy0) + m.w;
+    if (kSweep) {
+        const float nu0 = -fmaf(ex, mx, ey * my);      // -(e' . m')
+        const float nw0 = -fmaf(fx, my, -fy * mx);     // -(f x m')
+        st.m = make_float4(nu0, nw0, ex, ey);
+    } else {
+        st.m = make_float4(mx, my, ex, ey);
+    }
+    st.q = make_float4(fx, fy, 0.f, op);
     st.c = make_float4(c.x, c.y, c.z, op * a.g_min);
 }
 
 // Load a tile-list entry, compute its LDS constants and test its support
 // against the wave's 8x8 quad (first pixel centre qx0, qy0).
+template <bool kSweep>
 __device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, float qy0,
                                    Staged &st) {
     float4 q;
-    stage_record(a, id, qx0, qy0, st, q);
+    stage_record<kSweep>(a, id, qx0, qy0, st, q);
     // offsets of the quad's first pixel centre from the mean
-    const float x0 = -st.m.x, y0 = -st.m.y;
+    const float4 m = a.rec[3 * (int64_t)id];
+    const float x0 = -((m.x - qx0) + m.z), y0 = -((m.y - qy0) + m.w);
     float qxx, qxy, qyy;
     shape_conic(q.x, q.y, q.z, qxx, qxy, qyy);
     return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, qxx, qxy, qyy, a.box_thr);
 }
 
-// Base-2 exponent p2 = (e' . d)^2 + (f x d)^2 of a staged entry at offset
-// (dx, dy); u = e' . d and w = f x d are returned for the gradient.
+// Base-2 exponent p2 = (e' . d)^2 + (f x d)^2 of an entry staged for the
+// reverse pass, at offset (dx, dy); u = e' . d and w = f x d are returned for
+// the gradient.
 __device__ inline float exponent2(const Staged &st, float dx, float dy, float &u, float &w) {
     u = fmaf(st.m.z, dx, st.m.w * dy);
     w = fmaf(st.q.x, dy, -st.q.y * dx);
+    return fmaf(u, u, w * w);
+}
+
+// The same for an entry staged for the front-to-back sweep, at the pixel's
+// place (lx, ly) in the quad.
+__device__ inline float exponent2_sweep(const Staged &st, float lx, float ly) {
+    const float u = fmaf(st.m.z, lx, fmaf(st.m.w, ly, st.m.x));
+    const float w = fmaf(st.q.x, ly, fmaf(-st.q.y, lx, st.m.y));
     return fmaf(u, u, w * w);
 }
 
@@ -286,7 +311,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
         bool hit = false;
         if (j < end) {
             Staged st;
-            hit = stage_entry(a, a.ids[j], qx0, qy0, st);
+            hit = stage_entry<true>(a, a.ids[j], qx0, qy0, st);
             my[lane] = st;
         }
         uint64_t mask = __ballot(hit);
@@ -296,10 +321,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
             const int b = __builtin_ctzll(mask);
             clear_bit(mask, b);
             const Staged st = my[b];
-            const float dx = lx - st.m.x;
-            const float dy = ly - st.m.y;
-            float u, w;
-            const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
+            const float G = __builtin_amdgcn_exp2f(-exponent2_sweep(st, lx, ly));
             // contributors: inside the support and not stopped, as a lane mask
             const uint64_t cm = __builtin_amdgcn_ballot_w64(G > g_min) & ~stopped;
             const float araw = fmaf(st.q.w, G, -st.c.w);
@@ -710,7 +732,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                                 Staged st;
                                 float4 q;
                                 const float *q0 = s_q0[w + opaque_zero()];
-                                stage_record(a, id, q0[0], q0[1], st, q);
+                                stage_record<false>(a, id, q0[0], q0[1], st, q);
                                 my[lane] = st;
                             }
                             wave_lds_sync();
@@ -722,7 +744,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                             const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
                             const float *q0 = s_q0[w + opaque_zero()];
-                            hit = stage_entry(a, id, q0[0], q0[1], st);
+                            hit = stage_entry<false>(a, id, q0[0], q0[1], st);
                             my[lane] = st;
                         }
                         vm = __ballot(hit) & in_list;

@@ -106,7 +106,9 @@ struct TileArgs {
 // - The front-to-back sweep (kSweep) needs u and w only: with u0 = e' . m'
 //   and w0 = f x m' staged, u = e' . l - u0 and w = f x l - w0 cost two FMAs
 //   each and no offsets.
-// - The reverse pass also needs the offsets (conic gradient) and stages m'.
+// - The reverse pass also needs the offsets (conic gradient) and stages m',
+//   taken relative to the tile centre instead (the origin the per-tile sums
+//   of every quad share).
 struct Staged {
     float4 m;   // kSweep: -u0, -w0, e'.x, e'.y;  else: m'.x, m'.y, e'.x, e'.y
     float4 q;   // f.x, f.y, (unused), o' = o / (1 - g_min)
@@ -149,6 +151,18 @@ __device__ inline bool stage_entry(const TileArgs &a, uint32_t id, float qx0, fl
     // offsets of the quad's first pixel centre from the mean
     const float4 m = a.rec[3 * (int64_t)id];
     const float x0 = -((m.x - qx0) + m.z), y0 = -((m.y - qy0) + m.w);
+    float qxx, qxy, qyy;
+    shape_conic(q.x, q.y, q.z, qxx, qxy, qyy);
+    return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, qxx, qxy, qyy, a.box_thr);
+}
+
+// stage_entry for the reverse pass: the record staged relative to the tile
+// centre (ox, oy), the quad's first pixel centre at (bx, by) from it.
+__device__ inline bool stage_entry_bwd(const TileArgs &a, uint32_t id, float ox, float oy,
+                                       float bx, float by, Staged &st) {
+    float4 q;
+    stage_record<false>(a, id, ox, oy, st, q);
+    const float x0 = bx - st.m.x, y0 = by - st.m.y;
     float qxx, qxy, qyy;
     shape_conic(q.x, q.y, q.z, qxx, qxy, qyy);
     return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, qxx, qxy, qyy, a.box_thr);
@@ -560,31 +574,39 @@ __device__ inline float reduce_scatter32(float (&v)[32], int lane) {
     return r + dpp_f<0xB1>(r);                     // quad_perm [1,0,3,2] (lane ^ 1)
 }
 
-// Gaussians per reduction batch: 3 x 9 = 27 sums in 32 registers.  (Seven
+// Gaussians per reduction batch: 3 x 10 = 30 sums in 32 registers.  (Seven
 // Gaussians in 64 registers cost fewer reduction instructions per sum, but the
 // kernel then needs 96 registers and spills; the reverse pass waits on memory
 // more than it issues arithmetic, and the smaller form, with more waves and no
 // spills, runs it 30% faster.)
 constexpr int kSlots = 3;
 constexpr int kAcc = 32;
+constexpr int kSums = 10;     // per-lane values of one Gaussian
 
-// Planes 0-5 are summed without their constant factors, which are applied
-// once to the reduced sums.  With f the alpha gradient, o' the scaled opacity,
-// P = f o' G and p2 = u^2 + w^2 the base-2 exponent (G = 2^-p2, u = e' . d,
-// w = f x d): dL/dmean = ln 2 P (dp2/d dx, dp2/d dy) with dp2/d dx =
-// 2 (u e'.x - w f.y), dp2/d dy = 2 (u e'.y + w f.x) (the 2 joins ln 2 here),
-// dL/dQ = -P (dx^2 / 2, dx dy, dy^2 / 2) (Q the conic, p = d^T Q d / 2),
-// dL/do = f (G - g_min) / (1 - g_min).
+// What a Gaussian's sums hold.  With f the alpha gradient, o' the scaled
+// opacity, G = 2^-p2, p2 = u^2 + w^2 (u = e' . d, w = f x d, d = pixel - mean)
+// and P = f o' G = -dL/dp (p = d^T Q d / 2, Q the conic):
+//   dL/dmean = 2 ln 2 P (u e'.x - w f.y, u e'.y + w f.x)
+//            = 2 ln 2 o' [A B; B C] sum(f G d),
+//     A = e'.x^2 + f.y^2, B = e'.x e'.y - f.x f.y, C = e'.y^2 + f.x^2;
+//   dL/dQ = -P (dx^2 / 2, dx dy, dy^2 / 2);  dL/do = f (G - g_min) / (1 - g_min);
+//   dL/dcolour = alpha T g.
+// Entries in the tile's LDS table add moments about the tile centre: with
+// (x, y) the pixel centre relative to it, sums 0-9 are f G (1, x, y, x^2, x y,
+// y^2), alpha T g (3) and f; the table's flush turns them into the planes with
+// the record's mean and shape (sum(f G dx) = sum(f G x) - mx sum(f G), ...),
+// which per pixel costs five products instead of eleven.  Entries past the
+// table add the nine plane values directly (sums 0-8, the constant factors
+// below applied after the reduction).
 __device__ inline float plane_scale(int v, float inv_1mg) {
     return v < 2 ? 1.38629436112f : v == 3 ? -1.f : (v == 2 || v == 4) ? -0.5f : v == 5 ? inv_1mg : 1.f;
 }
 
 // Tile-list positions pooled in LDS by the backward.  With 16x16 tiles a
-// block then takes 256 x 48 B of staging + 9 x 384 x 4 B of sums = 25.5 KiB,
-// so six blocks share a CU's 160 KiB of LDS.  (512 positions leave five
-// blocks and ran 5% slower; 256 send more sums to global atomics and ran
-// 16% slower.)
-constexpr int kTableCap = 384;
+// block then takes 256 x 48 B of staging + 10 x 352 x 4 B of sums = 25.8 KiB,
+// so six blocks share a CU's 160 KiB of LDS.  (Five blocks ran 5% slower; with
+// half the positions more sums go to global atomics, 16% slower.)
+constexpr int kTableCap = 352;
 
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
 // its pixels used down to the first.  Per pixel and contributor (reverse
@@ -593,11 +615,11 @@ constexpr int kTableCap = 384;
 // at the background, A <- alpha c + (1 - alpha) A; only A . g is carried);
 // then, unless alpha was clamped, the opacity gradient and dL/dp = -alpha_bar
 // o' G, which gives the mean gradient -dL/dp Q d and the conic gradient dL/dp
-// (dx^2/2, dx dy, dy^2/2).  The nine per-lane values of seven Gaussians are
-// summed over the wave in one transposed reduction and added, with one
-// 63-lane atomic instruction, to the tile's LDS sum table (positions below
-// its capacity) or straight to the per-Gaussian planes in HBM; the table is
-// added to the planes when the tile is done.
+// (dx^2/2, dx dy, dy^2/2).  The per-lane values of three Gaussians are summed
+// over the wave in one transposed reduction and added, with one atomic
+// instruction, to the tile's LDS sum table (positions below its capacity) or
+// straight to the per-Gaussian planes in HBM; the table is added to the planes
+// when the tile is done.
 //
 // kRecompute: the blend state (T after the last contributor, the bound on its position and
 // the per-batch contribution masks) is not read from memory but recomputed by
@@ -614,7 +636,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     // [waves][kVisCap] batch masks
     extern __shared__ Staged s_stage[];
     __shared__ uint32_t s_top[16];
-    __shared__ float s_q0[16][2];      // each wave's quad origin, read when staging
+    __shared__ float s_q0[16][2];      // the tile centre (same for every wave), read when staging
     const int nwaves = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -626,18 +648,25 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     const bool valid = wave_on && x < tg.W && y < tg.H;
     const float lx = (float)(lane & 7), ly = (float)(lane >> 3);   // pixel - first pixel of the quad
     const float qx0 = (float)x0 + 0.5f, qy0 = (float)y0 + 0.5f;
+    // The reverse pass measures from the tile centre (ox, oy): the moments the
+    // quads of a tile add to one table need one origin.  (cx, cy): this pixel's
+    // centre, (bx, by): the quad's first pixel centre, both relative to it.
+    const float ox = (float)(tg.tx * a.tile_w) + 0.5f * (float)a.tile_w;
+    const float oy = (float)(tg.ty * a.tile_h) + 0.5f * (float)a.tile_h;
+    const float bx = qx0 - ox, by = qy0 - oy;
+    const float cx = bx + lx, cy = by + ly;
     if (lane == 0) {
-        s_q0[w][0] = qx0;
-        s_q0[w][1] = qy0;
+        s_q0[w][0] = ox;
+        s_q0[w][1] = oy;
     }
     Staged *my = s_stage + w * 64;
-    // Per-tile sums, plane-major [9][tab_cap], indexed by tile-list position:
+    // Per-tile sums, plane-major [kSums][tab_cap], indexed by tile-list position:
     // the quads of a tile share most of their Gaussians, so their sums meet
     // here and leave the block with one global atomic per (Gaussian, plane).
     const int tab_cap = a.tab_cap;
     float *table = reinterpret_cast<float *>(s_stage + nwaves * 64);
     // kRecompute: per-wave batch masks after the table
-    uint64_t *s_vis = reinterpret_cast<uint64_t *>(table + 9 * tab_cap) + w * kVisCap;
+    uint64_t *s_vis = reinterpret_cast<uint64_t *>(table + kSums * tab_cap) + w * kVisCap;
 
     const uint32_t start = a.ranges[2 * tile];
     const uint32_t len = a.ranges[2 * tile + 1] - start;
@@ -681,7 +710,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     uint32_t top_block = 0;
     for (int i = 0; i < nwaves; ++i) top_block = max(top_block, s_top[i]);
     const int tab_n = (int)(top_block < (uint32_t)tab_cap ? top_block : (uint32_t)tab_cap);
-    for (int i = threadIdx.x; i < 9 * tab_n; i += blockDim.x) {
+    for (int i = threadIdx.x; i < kSums * tab_n; i += blockDim.x) {
         const int v = i / tab_n;
         table[v * tab_cap + (i - v * tab_n)] = 0.f;
     }
@@ -693,7 +722,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     // sum i; the even one stores it)
     const int my_o = lane >> 1;
     const bool my_store = (lane & 1) == 0;
-    const int my_v = my_o % 9, my_s = my_o / 9;
+    const int my_v = my_o % kSums, my_s = my_o / kSums;
     uint32_t slot_pos[kSlots];
 #pragma unroll
     for (int i = 0; i < kSlots; ++i) slot_pos[i] = 0;
@@ -744,7 +773,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                             const uint32_t id = a.ids[start + lo + lane];
                             Staged st;
                             const float *q0 = s_q0[w + opaque_zero()];
-                            hit = stage_entry<false>(a, id, q0[0], q0[1], st);
+                            hit = stage_entry_bwd(a, id, q0[0], q0[1], bx, by, st);
                             my[lane] = st;
                         }
                         vm = __ballot(hit) & in_list;
@@ -757,8 +786,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     clear_bit(mask, b);
                     const Staged st = my[b];
                     const uint32_t pos = lo + (uint32_t)b;
-                    const float dx = lx - st.m.x;
-                    const float dy = ly - st.m.y;
+                    const float dx = cx - st.m.x;
+                    const float dy = cy - st.m.y;
                     float u, w;
                     const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
                     const bool c = pos < nl && G > g_min;
@@ -774,49 +803,94 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     Ag = fmaf(al, e, Ag);
                     T = Tb;
                     const float f = shaped ? abar : 0.f;
-                    // P = -dL/dp; the planes' constant factors (plane_scale)
-                    // are applied to the sums after the reduction
                     const float fG = f * G;
-                    const float P = fG * st.q.w;
-                    const float Pdx = P * dx, Pdy = P * dy;
-                    acc[9 * s + 0] = P * fmaf(u, st.m.z, -w * st.q.y);   // d p2 / d dx / 2
-                    acc[9 * s + 1] = P * fmaf(u, st.m.w, w * st.q.x);    // d p2 / d dy / 2
-                    acc[9 * s + 2] = Pdx * dx;
-                    acc[9 * s + 3] = Pdx * dy;
-                    acc[9 * s + 4] = Pdy * dy;
-                    acc[9 * s + 5] = fmaf(-g_min, f, fG);        // f (G - g_min)
-                    acc[9 * s + 6] = wgt * g0;
-                    acc[9 * s + 7] = wgt * g1;
-                    acc[9 * s + 8] = wgt * g2;
+                    acc[kSums * s + 6] = wgt * g0;
+                    acc[kSums * s + 7] = wgt * g1;
+                    acc[kSums * s + 8] = wgt * g2;
+                    if (pos < (uint32_t)tab_cap) {
+                        // moments about the tile centre (wave-uniform branch)
+                        const float fGx = fG * cx, fGy = fG * cy;
+                        acc[kSums * s + 0] = fG;
+                        acc[kSums * s + 1] = fGx;
+                        acc[kSums * s + 2] = fGy;
+                        acc[kSums * s + 3] = fGx * cx;
+                        acc[kSums * s + 4] = fGx * cy;
+                        acc[kSums * s + 5] = fGy * cy;
+                        acc[kSums * s + 9] = f;
+                    } else {
+                        // the planes without their constant factors (plane_scale)
+                        const float P = fG * st.q.w;             // -dL/dp
+                        const float Pdx = P * dx, Pdy = P * dy;
+                        acc[kSums * s + 0] = P * fmaf(u, st.m.z, -w * st.q.y);
+                        acc[kSums * s + 1] = P * fmaf(u, st.m.w, w * st.q.x);
+                        acc[kSums * s + 2] = Pdx * dx;
+                        acc[kSums * s + 3] = Pdx * dy;
+                        acc[kSums * s + 4] = Pdy * dy;
+                        acc[kSums * s + 5] = fmaf(-g_min, f, fG);    // f (G - g_min)
+                        acc[kSums * s + 9] = 0.f;
+                    }
                     slot_pos[s] = pos;
                     filled = s + 1;
                 }
             }
         }
         if (filled == 0) break;
-        // the registers past 9 * kSlots feed only sums that are never stored:
-        // setting them here keeps them out of the registers live across the
-        // slot loop
+        // the registers past kSums * kSlots feed only sums that are never
+        // stored: setting them here keeps them out of the registers live
+        // across the slot loop
 #pragma unroll
-        for (int i = 9 * kSlots; i < kAcc; ++i) acc[i] = 0.f;
+        for (int i = kSums * kSlots; i < kAcc; ++i) acc[i] = 0.f;
         const float r = reduce_scatter32(acc, lane);
         uint32_t my_pos = slot_pos[0];
 #pragma unroll
         for (int i = 1; i < kSlots; ++i) my_pos = my_s == i ? slot_pos[i] : my_pos;
-        if (my_store && my_o < 9 * filled) {
+        if (my_store && my_s < filled) {
             if (my_pos < (uint32_t)tab_cap)
                 atomicAdd(&table[my_v * tab_cap + my_pos], r);
-            else
+            else if (my_v < kGradPlanes)
                 atomicAdd(a.d_gauss + (int64_t)my_v * ng + a.ids[start + my_pos],
                           r * plane_scale(my_v, inv_1mg));
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 9 * tab_n; i += blockDim.x) {
-        const int v = i / tab_n, p = i - v * tab_n;
-        const float val = table[v * tab_cap + p];
-        if (val != 0.f)
-            atomicAdd(a.d_gauss + (int64_t)v * ng + a.ids[start + p], val * plane_scale(v, inv_1mg));
+    // the table's moments to the nine planes, one position per thread
+    for (int p = threadIdx.x; p < tab_n; p += blockDim.x) {
+        float S[kSums];
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < kSums; ++v) {
+            S[v] = table[v * tab_cap + p];
+            any |= S[v] != 0.f;
+        }
+        if (!any) continue;
+        const uint32_t id = a.ids[start + p];
+        const float4 m = a.rec[3 * (int64_t)id];
+        const float4 q = a.rec[3 * (int64_t)id + 1];
+        const float mx = (m.x - ox) + m.z, my = (m.y - oy) + m.w;   // mean - tile centre
+        const float ex = kHalfLog2eSqrt * q.x, ey = kHalfLog2eSqrt * q.y;
+        const float fx = q.z * ex, fy = q.z * ey;
+        const float op = q.w * inv_1mg;
+        // sums over the tile's pixels of f G (dx, dy, dx^2, dx dy, dy^2), d = pixel - mean
+        const float sx = fmaf(-mx, S[0], S[1]), sy = fmaf(-my, S[0], S[2]);
+        const float sxx = fmaf(-mx, S[1] + sx, S[3]);
+        const float sxy = fmaf(-mx, sy, fmaf(-my, S[1], S[4]));
+        const float syy = fmaf(-my, S[2] + sy, S[5]);
+        const float A = fmaf(ex, ex, fy * fy), B = fmaf(ex, ey, -fx * fy),
+                    C = fmaf(ey, ey, fx * fx);
+        const float k2 = 1.38629436112f * op;        // 2 ln 2 o'
+        float out[kGradPlanes];
+        out[0] = k2 * fmaf(A, sx, B * sy);
+        out[1] = k2 * fmaf(B, sx, C * sy);
+        out[2] = -0.5f * op * sxx;
+        out[3] = -op * sxy;
+        out[4] = -0.5f * op * syy;
+        out[5] = fmaf(-g_min, S[9], S[0]) * inv_1mg;
+        out[6] = S[6];
+        out[7] = S[7];
+        out[8] = S[8];
+#pragma unroll
+        for (int v = 0; v < kGradPlanes; ++v)
+            if (out[v] != 0.f) atomicAdd(a.d_gauss + (int64_t)v * ng + id, out[v]);
     }
 }
 
@@ -1233,7 +1307,7 @@ hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
     a.n_gauss = n_gauss;
     int threads = o.tile_w * o.tile_h;
     a.tab_cap = kTableCap;
-    size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * 9 * (size_t)kTableCap;
+    size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * kSums * (size_t)kTableCap;
     if (st) {
         a.t_final = st->t_final;
         a.n_last = st->n_last;

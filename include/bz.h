@@ -100,7 +100,13 @@ typedef struct {
                                 kernels run as many workgroups as fit on the GPU at
                                 once, each taking tiles from a counter in
                                 bz_bins.workspace.  Results do not depend on it. */
-    int32_t reserved;
+    int32_t bin_sort;        /* tuning: 0 = automatic: with at most 65,536 tiles and
+                                fewer than 2^24 Gaussians, pairs are emitted straight
+                                into buckets of 256 consecutive tiles and sorted
+                                inside each bucket by one radix pass; otherwise, and
+                                with 1, the (tile, Gaussian) pairs take a two-pass
+                                radix sort on the tile.  Results do not depend on it;
+                                the workspace size does. */
     const bz_batch *batch;   /* NULL: one canvas of width x height with bg.  Else
                                 the canvases of the batch (host struct; width,
                                 height and bg above are then unused). */

@@ -38,7 +38,7 @@ class Opts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bg", C.c_float * 3),
                 ("rho", C.c_float), ("sigma0_sq", C.c_float), ("g_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32), ("persistent", C.c_int32), ("reserved", C.c_int32),
+                ("tile_h", C.c_int32), ("persistent", C.c_int32), ("bin_sort", C.c_int32),
                 ("batch", C.c_void_p)]
 
 
@@ -172,6 +172,9 @@ class RenderOptions:
     tile_w: int = 16
     tile_h: int = 16
     persistent: bool = False
+    # tile lists: False = automatic (bucketed emission when it applies), True =
+    # always the two-pass radix sort; the lists are the same either way
+    radix_bins: bool = False
 
     def as_dict(self):
         return dict(rho=self.rho, sigma0_sq=self.sigma0_sq, g_min=self.g_min,
@@ -187,6 +190,7 @@ def make_opts(width, height, bg, ro: RenderOptions) -> Opts:
     o.alpha_max, o.t_min = ro.alpha_max, ro.t_min
     o.tile_w, o.tile_h = int(ro.tile_w), int(ro.tile_h)
     o.persistent = int(bool(ro.persistent))
+    o.bin_sort = int(bool(ro.radix_bins))
     o.batch = None
     return o
 

@@ -56,6 +56,7 @@ bz_status check_opts(const bz_opts *o) {
     for (int c = 0; c < 3; ++c)
         if (!isfinite(o->bg[c])) return BZ_ERR_ARG;
     if (o->persistent != 0 && o->persistent != 1) return BZ_ERR_ARG;
+    if (o->bin_sort != 0 && o->bin_sort != 1) return BZ_ERR_ARG;
     if (o->batch) {
         const bz_batch *bt = o->batch;
         if (bt->n_canvas < 1 || !bt->canvas || bt->n_tiles < bt->n_canvas || bt->n_pixels < 1 ||

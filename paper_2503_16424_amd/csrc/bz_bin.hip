@@ -16,6 +16,15 @@
 //            draw order inside every tile.
 // 5. ranges: first/last position of every tile in the sorted list.
 //
+// With at most 65,536 tiles and fewer than 2^24 Gaussians (bin_fused) steps
+// 2-5 take a shorter route: the count also adds each Gaussian's pairs per
+// (bucket of 256 consecutive tile keys, emission block of kEmitBlock
+// Gaussians); the scan of those counts places every block's part of every
+// bucket; the emission writes the pairs straight into their bucket, in draw
+// order; and one stable radix pass on the low key byte inside each bucket
+// finishes the lists, whose ranges then follow from that pass's scanned digit
+// counts.  Same lists, one pass over the pairs fewer and no sorted keys.
+//
 // Sizes that depend on the data (the pair count) stay on the device: the
 // grids are sized for the capacity and idle blocks exit, so a call never
 // waits for the host.
@@ -58,6 +67,24 @@ __device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t *s_wave, uint64_
     return before + x - v;
 }
 
+// Exclusive prefix over the wave of one value per lane; total in *tot.
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+        if ((threadIdx.x & 63) >= d) x += y;
+    }
+    tot = (uint32_t)__shfl((int)x, 63, 64);
+    return x - v;
+}
+
+__device__ inline void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // canvas (W x H) of Gaussian g: the single canvas, or its batch canvas
 __device__ inline void gauss_canvas(const bz_canvas *cv, int n_canvas, int64_t g, int &W, int &H,
                                     int &tiles_x, uint32_t &tile_base) {
@@ -69,24 +96,52 @@ __device__ inline void gauss_canvas(const bz_canvas *cv, int n_canvas, int64_t g
     tile_base = (uint32_t)cv[c].tile_off;
 }
 
+// One thread per Gaussian; on the bucketed path (bucket != null) each wave is
+// one emission block, whose pairs per key bucket it adds up in LDS.
 __global__ __launch_bounds__(256) void k_count(const float4 *__restrict__ rec, int64_t n, int W,
-                                               int H, float inv_tw, float inv_th, int th,
-                                               float two_p,
+                                               int H, int tiles_x, float inv_tw, float inv_th,
+                                               int th, float two_p,
                                                const bz_canvas *__restrict__ cv, int n_canvas,
                                                uint32_t *__restrict__ counts,
-                                               ushort4 *__restrict__ rects, int64_t *status) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    int tiles_x_unused;
-    uint32_t base_unused;
-    gauss_canvas(cv, n_canvas, g, W, H, tiles_x_unused, base_unused);
-    ushort4 rc;
-    bool finite;
-    const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, inv_tw, inv_th, th, two_p,
-                                   rc, finite);
-    if (!finite) atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
-    counts[g] = cnt;
-    rects[g] = rc;
+                                               ushort4 *__restrict__ rects,
+                                               uint32_t *__restrict__ bucket, int nbk,
+                                               int64_t n_eblk, int64_t *status) {
+    static_assert(kEmitBlock == 64, "one emission block per wave");
+    __shared__ uint32_t s_hb[4][256];
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t *hb = s_hb[wv];
+    if (bucket) {
+        for (int i = lane; i < nbk; i += 64) hb[i] = 0u;
+        wave_lds_fence();
+    }
+    if (g < n) {
+        int txc = tiles_x;
+        uint32_t tbase = 0;
+        gauss_canvas(cv, n_canvas, g, W, H, txc, tbase);
+        ushort4 rc;
+        bool finite;
+        const uint32_t cnt = tile_rect(rec[3 * g], rec[3 * g + 1], W, H, inv_tw, inv_th, th,
+                                       two_p, rc, finite, [&](int ty, int c0, int c1) {
+                                           if (!bucket) return;
+                                           const uint32_t k0 = tbase + (uint32_t)ty * (uint32_t)txc +
+                                                               (uint32_t)c0;
+                                           for_key_buckets(k0, (uint32_t)(c1 - c0 + 1),
+                                                           [&](uint32_t h, uint32_t c) {
+                                                               atomicAdd(&hb[h], c);
+                                                           });
+                                       });
+        if (!finite)
+            atomicOr((unsigned long long *)&status[1], (unsigned long long)Status::kNonFinite);
+        if (counts) counts[g] = cnt;
+        rects[g] = rc;
+    }
+    if (bucket) {
+        wave_lds_fence();
+        const int64_t eb = g / kEmitBlock;
+        if (eb < n_eblk)
+            for (int i = lane; i < nbk; i += 64) bucket[(int64_t)i * n_eblk + eb] = hb[i];
+    }
 }
 
 // --- device-wide exclusive scan of uint32 (64-bit partials) ---------------
@@ -183,24 +238,6 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *part
 // every real tile and no range covers.
 constexpr int kEmitG = 64;        // Gaussians per wave
 constexpr int kRowChunk = 256;    // row items per round
-
-// Exclusive prefix over the wave of one value per lane; total in *tot.
-__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
-        if ((threadIdx.x & 63) >= d) x += y;
-    }
-    tot = (uint32_t)__shfl((int)x, 63, 64);
-    return x - v;
-}
-
-__device__ inline void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __global__ __launch_bounds__(64) void k_emit(const float4 *__restrict__ rec,
                                              const uint32_t *__restrict__ offs,
@@ -521,6 +558,362 @@ __global__ void k_set_count(int64_t *status, int64_t n) {
     }
 }
 
+// --- bucketed path ----------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Wave minimum and maximum of one value per lane.
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, 64));
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));
+    return v;
+}
+
+// Bucketed emission.  A bucket's pairs form one contiguous segment of the
+// packed array, emission block 0's first, then block 1's, ...: the scanned
+// (bucket, block) counts, bucket-major, give each block its place.  One wave
+// per emission block of kEmitBlock (= kEmitG = 64) Gaussians (kEmitWaves per
+// workgroup).  The pairs are generated as in k_emit: (Gaussian, row) items,
+// kRowChunk at a time, each row's span by support_row (the count's function
+// of the same record bits), and consecutive lanes on consecutive pairs of the
+// chunk (Gaussian-major, i.e. draw order), each finding its row by binary
+// search.  A pair's place inside its bucket is the wave's running count of
+// that bucket (LDS) plus the lanes of the round before it with the same
+// bucket, found with one ballot per bit of the bucket's index relative to the
+// block's first bucket (as the radix scatter ranks digits); so each bucket
+// keeps draw order, and a row whose keys straddle two buckets needs nothing
+// special.  A pair is packed as (key & 255) << 24 | Gaussian.  Every bucket's
+// total must equal the count's; otherwise the lists are marked invalid (never
+// expected), and no lane writes outside the block's part of a bucket.
+// Neighbouring blocks' parts of a bucket are neighbours in memory, so blocks
+// are dealt to the XCDs in contiguous runs (the dispatcher sends workgroup w to
+// XCD w % 8): the parts meet in one L2.
+constexpr int kEmitWaves = 1;
+
+__global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
+    const float4 *__restrict__ rec, const ushort4 *__restrict__ rects, int64_t n, int W, int H,
+    int tiles_x, float inv_tw, int th, float two_p, const bz_canvas *__restrict__ cv,
+    int n_canvas, const uint32_t *__restrict__ bucket, int nbk, int64_t n_eblk,
+    uint32_t *__restrict__ packed, int64_t *status) {
+    static_assert(kEmitBlock == kEmitG, "one emission block per wave");
+    __shared__ uint32_t s_rows[kEmitWaves][kEmitG + 1];   // exclusive prefix of tile rows
+    __shared__ Support s_sup[kEmitWaves][kEmitG];
+    __shared__ uint32_t s_key0[kEmitWaves][kEmitG];      // key of tile (first row, column 0)
+    __shared__ uint16_t s_ty0[kEmitWaves][kEmitG];
+    __shared__ int s_tx[kEmitWaves][kEmitG];
+    __shared__ uint32_t s_item_off[kEmitWaves][kRowChunk + 1];
+    __shared__ uint32_t s_item_key[kEmitWaves][kRowChunk];
+    __shared__ uint8_t s_item_g[kEmitWaves][kRowChunk];
+    __shared__ uint32_t s_base[kEmitWaves][256], s_cnt[kEmitWaves][256], s_run[kEmitWaves][256];
+    if (status[1] & Status::kOverflow) return;
+    const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t per = (n_eblk + 8 * kEmitWaves - 1) / (8 * kEmitWaves);   // workgroups per XCD
+    const int64_t eb = ((int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3)) * kEmitWaves + wv;
+    if (eb >= n_eblk) return;                        // whole wave
+    const int64_t g0 = eb * kEmitG;
+    const int nb = (int)(n - g0 < kEmitG ? n - g0 : kEmitG);
+    const uint32_t total = (uint32_t)status[0];
+    const int64_t nflat = (int64_t)nbk * n_eblk;
+    uint32_t my_rows = 0, hlo = 0xffffffffu, hhi = 0;
+    if (t < nb) {
+        const int64_t g = g0 + t;
+        const ushort4 rc = rects[g];
+        int Wc = W, Hc = H, txc = tiles_x;
+        uint32_t tbase = 0;
+        gauss_canvas(cv, n_canvas, g, Wc, Hc, txc, tbase);
+        Support sp;
+        bool finite;
+        if (rc.x <= rc.z && rc.y <= rc.w &&
+            support_of(rec[3 * g], rec[3 * g + 1], Wc, Hc, two_p, sp, finite)) {
+            my_rows = (uint32_t)(rc.w - rc.y + 1);
+            s_sup[wv][t] = sp;
+            s_key0[wv][t] = tbase + (uint32_t)rc.y * (uint32_t)txc;
+            s_ty0[wv][t] = rc.y;
+            s_tx[wv][t] = txc;
+            // the keys of its pairs lie in [key(first row, rc.x), key(last row, rc.z)]
+            hlo = (tbase + (uint32_t)rc.y * (uint32_t)txc + rc.x) >> 8;
+            hhi = (tbase + (uint32_t)rc.w * (uint32_t)txc + rc.z) >> 8;
+        }
+    }
+    uint32_t nrows;
+    s_rows[wv][t] = wave_excl_scan(my_rows, nrows);
+    if (t == 0) s_rows[wv][kEmitG] = nrows;
+    const uint32_t hl = wave_min_u32(hlo);
+    if (hl == 0xffffffffu) return;                   // no pairs in this block
+    const uint32_t span = wave_max_u32(my_rows ? hhi : 0u) - hl;   // buckets hl .. hl + span
+    int nbits = 0;
+    while (nbits < 8 && (1u << nbits) <= span) ++nbits;
+    // this block's part of each of its buckets (first position, size), stored
+    // in LDS once the first chunk's rows are done, which hides the loads
+    auto fetch_parts = [&]() {
+        for (uint32_t i = t; i <= span; i += 64) {
+            const int64_t fi = (int64_t)(hl + i) * n_eblk + eb;
+            const uint32_t a = bucket[fi];
+            s_base[wv][i] = a;
+            s_cnt[wv][i] = (fi + 1 < nflat ? bucket[fi + 1] : total) - a;
+            s_run[wv][i] = 0u;
+        }
+    };
+    const uint64_t lt = (t == 0) ? 0ull : (~0ull >> (64 - t));
+    const int th_ = th;
+    for (uint32_t c0 = 0; c0 < nrows; c0 += kRowChunk) {
+        const uint32_t ci = nrows - c0 < (uint32_t)kRowChunk ? nrows - c0 : (uint32_t)kRowChunk;
+        uint32_t wsum = 0;
+        uint32_t wid[kRowChunk / 64];
+#pragma unroll
+        for (int j = 0; j < kRowChunk / 64; ++j) {
+            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
+            wid[j] = 0;
+            if (it < ci) {
+                const uint32_t r = c0 + it;
+                int lo = 0;                    // last Gaussian whose first row <= r
+#pragma unroll
+                for (int step = kEmitG / 2; step >= 1; step >>= 1)
+                    if (lo + step < nb && s_rows[wv][lo + step] <= r) lo += step;
+                const int dr = (int)(r - s_rows[wv][lo]);
+                int cl, ch;
+                support_row(s_sup[wv][lo], (int)s_ty0[wv][lo] + dr, th_, inv_tw, cl, ch);
+                wid[j] = ch >= cl ? (uint32_t)(ch - cl + 1) : 0u;
+                s_item_key[wv][it] = s_key0[wv][lo] + (uint32_t)dr * (uint32_t)s_tx[wv][lo] + (uint32_t)cl;
+                s_item_g[wv][it] = (uint8_t)lo;
+                wsum += wid[j];
+            }
+        }
+        uint32_t cnt;
+        uint32_t ex = wave_excl_scan(wsum, cnt);
+#pragma unroll
+        for (int j = 0; j < kRowChunk / 64; ++j) {
+            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
+            if (it < ci) s_item_off[wv][it] = ex;
+            ex += wid[j];
+        }
+        if (t == 0) s_item_off[wv][ci] = cnt;
+        if (c0 == 0) fetch_parts();
+        wave_lds_fence();
+        // rounds of 64 consecutive pairs of the chunk, one per lane
+        for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
+            const uint32_t i = r0 + (uint32_t)t;
+            const bool valid = i < cnt;
+            uint32_t key = 0, gl = 0;
+            if (valid) {
+                int lo = 0;                    // last row item whose offset <= i
+#pragma unroll
+                for (int step = kRowChunk / 2; step >= 1; step >>= 1)
+                    if ((uint32_t)(lo + step) < ci && s_item_off[wv][lo + step] <= i) lo += step;
+                key = s_item_key[wv][lo] + (i - s_item_off[wv][lo]);
+                gl = s_item_g[wv][lo];
+            }
+            const uint32_t hr = valid ? (key >> 8) - hl : 0u;
+            const uint64_t peers = digit_peers(valid, hr, nbits);
+            // the wave's LDS accesses execute in order: this round reads the
+            // counts the previous round's group leaders wrote
+            const uint32_t before = valid ? s_run[wv][hr] : 0u;
+            const uint32_t rank = before + (uint32_t)__popcll(peers & lt);
+            if (valid && (peers & lt) == 0) s_run[wv][hr] = before + (uint32_t)__popcll(peers);
+            if (valid && rank < s_cnt[wv][hr])
+                packed[s_base[wv][hr] + rank] = ((key & 255u) << 24) | (uint32_t)(g0 + gl);
+        }
+        wave_lds_fence();
+    }
+    // every bucket of the block filled exactly
+    for (uint32_t i = t; i <= span; i += 64)
+        if (s_run[wv][i] != s_cnt[wv][i])
+            atomicOr((unsigned long long *)&status[1],
+                     (unsigned long long)(Status::kOverflow | Status::kListMismatch));
+}
+
+// Segment table of the in-bucket pass: seg[s] = first position of bucket s,
+// seg[nbk + 1 + s] = its first radix block (ceil(len / kTile) blocks per
+// bucket), entry nbk of each = the end.  One workgroup of kBlk threads.
+__global__ __launch_bounds__(256) void k_segments(const uint32_t *__restrict__ bucket, int nbk,
+                                                  int64_t n_eblk, const int64_t *status,
+                                                  uint32_t *__restrict__ seg) {
+    __shared__ uint64_t s_wave[kBlk / 64];
+    if (status[1] & Status::kOverflow) return;
+    const int t = threadIdx.x;
+    const uint32_t total = (uint32_t)status[0];
+    const uint32_t S = t < nbk ? bucket[(int64_t)t * n_eblk] : total;
+    const uint32_t S1 = t + 1 < nbk ? bucket[(int64_t)(t + 1) * n_eblk] : total;
+    const uint32_t nb = t < nbk ? (S1 - S + kTile - 1) / kTile : 0u;
+    uint64_t tot;
+    const uint32_t P = (uint32_t)block_excl_scan(nb, s_wave, tot);
+    if (t <= nbk) {
+        seg[t] = S;
+        seg[nbk + 1 + t] = P;
+    }
+    if (nbk == kBlk && t == kBlk - 1) {
+        seg[nbk] = total;
+        seg[2 * nbk + 1] = P + nb;
+    }
+}
+
+// Segment of radix block b (b < P[nbk]): the last s with P[s] <= b (buckets
+// without pairs own no block).
+__device__ inline int seg_find(const uint32_t *P, int nbk, uint32_t b) {
+    int lo = 0, hi = nbk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A radix block of the in-bucket pass: its segment, its first element and
+// count, and the index of its digit-0 count in hseg.
+struct SegBlock {
+    uint32_t pos0, cnt;
+    int64_t h0;        // hseg index of (segment, digit 0, this block)
+    uint32_t nbs;      // blocks of the segment (stride between digits)
+    bool real;
+};
+
+__device__ inline SegBlock seg_block(const uint32_t *s_S, const uint32_t *s_P, int nbk, uint32_t b) {
+    SegBlock r;
+    r.real = b < s_P[nbk];
+    if (!r.real) {
+        r.pos0 = r.cnt = r.nbs = 0;
+        r.h0 = (int64_t)b * kRadix;
+        return r;
+    }
+    const int s = seg_find(s_P, nbk, b);
+    const uint32_t j = b - s_P[s];
+    r.nbs = s_P[s + 1] - s_P[s];
+    r.pos0 = s_S[s] + j * (uint32_t)kTile;
+    r.cnt = min((uint32_t)kTile, s_S[s + 1] - r.pos0);
+    r.h0 = (int64_t)kRadix * s_P[s] + j;
+    return r;
+}
+
+__device__ inline void load_seg(const uint32_t *seg, int nbk, uint32_t *s_S, uint32_t *s_P) {
+    for (int i = threadIdx.x; i <= nbk; i += blockDim.x) {
+        s_S[i] = seg[i];
+        s_P[i] = seg[nbk + 1 + i];
+    }
+}
+
+// Digit counts of one radix block of the in-bucket pass (low key byte).
+__global__ __launch_bounds__(256) void k_seg_hist(const uint32_t *__restrict__ packed,
+                                                  const uint32_t *__restrict__ seg, int nbk,
+                                                  const int64_t *status,
+                                                  uint32_t *__restrict__ hseg) {
+    __shared__ uint32_t h[kRadix];
+    __shared__ uint32_t s_S[kRadix + 1], s_P[kRadix + 1];
+    if (status[1] & Status::kOverflow) return;
+    const int t = threadIdx.x;
+    load_seg(seg, nbk, s_S, s_P);
+    h[t] = 0u;
+    __syncthreads();
+    const SegBlock sb = seg_block(s_S, s_P, nbk, blockIdx.x);
+    // consecutive pairs of a bucket are mostly consecutive keys: no runs of
+    // equal digits to add at once, so one LDS atomic per pair
+    for (uint32_t i = t; i < sb.cnt; i += kBlk) atomicAdd(&h[packed[sb.pos0 + i] >> 24], 1u);
+    __syncthreads();
+    hseg[sb.h0 + (int64_t)t * (sb.real ? sb.nbs : 1u)] = h[t];
+}
+
+// The in-bucket pass's scatter: ranks as in k_radix_scatter (digit = key
+// byte), positions from the scanned hseg, and only the Gaussian leaves.
+__global__ __launch_bounds__(256) void k_seg_scatter(const uint32_t *__restrict__ packed,
+                                                     const uint32_t *__restrict__ seg, int nbk,
+                                                     const uint32_t *__restrict__ hseg,
+                                                     const int64_t *status,
+                                                     uint32_t *__restrict__ ids) {
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ uint32_t s_prefix[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_wrun[kBlk / 64][kRadix];
+    __shared__ uint64_t s_wave[kBlk / 64];
+    __shared__ uint32_t s_S[kRadix + 1], s_P[kRadix + 1];
+    if (status[1] & Status::kOverflow) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    load_seg(seg, nbk, s_S, s_P);
+#pragma unroll
+    for (int q = 0; q < kBlk / 64; ++q) s_wrun[q][tid] = 0;
+    __syncthreads();
+    const SegBlock sb = seg_block(s_S, s_P, nbk, blockIdx.x);
+    if (!sb.real) return;                      // uniform over the block
+    const int cnt = (int)sb.cnt;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t *run = s_wrun[w];
+    uint32_t key[kItems], rank[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int li = w * kWaveItems + j * 64 + lane;
+        key[j] = li < cnt ? packed[sb.pos0 + li] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int li = w * kWaveItems + j * 64 + lane;
+        const bool valid = li < cnt;
+        const uint32_t d = key[j] >> 24;
+        const uint64_t peers = digit_peers(valid, d, 8);
+        const uint32_t before = valid ? run[d] : 0u;
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0) run[d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        uint32_t tt = 0;
+#pragma unroll
+        for (int q = 0; q < kBlk / 64; ++q) {
+            const uint32_t c = s_wrun[q][tid];
+            s_wrun[q][tid] = tt;
+            tt += c;
+        }
+        uint64_t tot;
+        s_prefix[tid] = (uint32_t)block_excl_scan(tt, s_wave, tot);
+        s_gbase[tid] = hseg[sb.h0 + (int64_t)tid * sb.nbs];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int li = w * kWaveItems + j * 64 + lane;
+        if (li < cnt) {
+            const uint32_t d = key[j] >> 24;
+            s_keys[s_prefix[d] + run[d] + rank[j]] = key[j];
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt; i += kBlk) {
+        const uint32_t k = s_keys[i];
+        const uint32_t d = k >> 24;
+        ids[s_gbase[d] + (uint32_t)i - s_prefix[d]] = k & 0xffffffu;
+    }
+}
+
+// Ranges of the bucketed path: tile t = 256 s + d starts where (segment s,
+// digit d, first block) does in the scanned hseg and ends where digit d + 1
+// starts (the segment's end for d = 255); an empty tile gets (0, 0).
+__global__ void k_seg_ranges(const uint32_t *__restrict__ hseg, const uint32_t *__restrict__ seg,
+                             int nbk, uint32_t n_tiles, const int64_t *status,
+                             uint32_t *__restrict__ ranges) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    uint32_t a = 0, e = 0;
+    if (!(status[1] & Status::kOverflow)) {
+        const uint32_t s = t >> 8, d = t & 255u;
+        const uint32_t P = seg[nbk + 1 + s], nbs = seg[nbk + 2 + s] - P;
+        if (nbs == 0) {
+            a = e = seg[s];
+        } else {
+            const int64_t h0 = (int64_t)kRadix * P;
+            a = hseg[h0 + (int64_t)d * nbs];
+            e = d < 255u ? hseg[h0 + (int64_t)(d + 1) * nbs] : seg[s + 1];
+        }
+        if (a == e) a = e = 0u;      // an empty tile: (0, 0), as the radix path leaves it
+    }
+    ranges[2 * (int64_t)t] = a;
+    ranges[2 * (int64_t)t + 1] = e;
+}
+
 }  // namespace
 
 int64_t sort_hist_blocks(int64_t n) { return cdiv(n > 0 ? n : 1, kTile); }
@@ -566,6 +959,31 @@ hipError_t sort_pairs_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint3
 BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
     BinLayout L;
     L.n_tiles = num_tiles(o);
+    L.fused = bin_fused(o, n_gauss, L.n_tiles);
+    if (L.fused) {
+        const int64_t ng = n_gauss > 0 ? n_gauss : 1, cp = cap > 0 ? cap : 1;
+        L.n_buckets = cdiv(L.n_tiles > 0 ? L.n_tiles : 1, 256);
+        L.n_eblk = cdiv(ng, kEmitBlock);
+        L.seg_blocks = cdiv(cp, kTile) + L.n_buckets;
+        int64_t off = 0;
+        L.off_counters = off;             // first, so that its place needs no sizes
+        off = align256(off + 4 * 4);
+        L.off_rects = off;
+        off = align256(off + 8 * ng);
+        L.off_bucket = off;
+        off = align256(off + 4 * L.n_buckets * L.n_eblk);
+        L.off_packed = off;
+        off = align256(off + 4 * cp);
+        L.off_seg = off;
+        off = align256(off + 4 * 2 * (L.n_buckets + 1));
+        L.off_hseg = off;
+        off = align256(off + 4 * kRadix * L.seg_blocks);
+        L.off_part = off;
+        const int64_t pa = cdiv(L.n_buckets * L.n_eblk, kTile), pb = cdiv(kRadix * L.seg_blocks, kTile);
+        off = align256(off + 8 * (pa > pb ? pa : pb));
+        L.total = off;
+        return L;
+    }
     int bits = 0;
     while ((int64_t(1) << bits) <= L.n_tiles) ++bits;   // keys 0 .. n_tiles
     if (bits == 0) bits = 1;
@@ -597,19 +1015,29 @@ BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap) {
 
 namespace {
 
-// The binning workspace's arrays.
+// The binning workspace's arrays (the path's own; the others are null).
 struct BinBufs {
     BinLayout L;
     uint32_t *counts;
     ushort4 *rects;
     uint32_t *keys_a, *keys_b, *vals_b, *hist;
     uint64_t *part;
+    uint32_t *bucket, *packed, *seg, *hseg;
 };
 
 BinBufs bin_bufs(const bz_opts &o, int64_t n, const bz_bins &b) {
-    BinBufs u;
+    BinBufs u = {};
     u.L = bin_layout(o, n, b.cap_pairs);
     char *ws = (char *)b.workspace;
+    if (u.L.fused) {
+        u.rects = (ushort4 *)(ws + u.L.off_rects);
+        u.bucket = (uint32_t *)(ws + u.L.off_bucket);
+        u.packed = (uint32_t *)(ws + u.L.off_packed);
+        u.seg = (uint32_t *)(ws + u.L.off_seg);
+        u.hseg = (uint32_t *)(ws + u.L.off_hseg);
+        u.part = (uint64_t *)(ws + u.L.off_part);
+        return u;
+    }
     u.counts = (uint32_t *)(ws + u.L.off_counts);
     u.rects = (ushort4 *)(ws + u.L.off_rects);
     u.keys_a = (uint32_t *)(ws + u.L.off_keys_a);
@@ -622,11 +1050,48 @@ BinBufs bin_bufs(const bz_opts &o, int64_t n, const bz_bins &b) {
 
 float support_two_p(const bz_opts &o) { return 2.0f * (-logf(o.g_min)); }
 
-// Status and ranges cleared: before anything of the call writes a flag.
+// Status and ranges cleared: before anything of the call writes a flag.  The
+// bucketed path's counts start at zero (they are added to).
 void bin_prepare(const BinBufs &u, const bz_bins &b, hipStream_t s) {
     const int64_t nr = 2 * u.L.n_tiles;
     hipLaunchKernelGGL(k_bin_clear, dim3(cdiv(nr > 2 ? nr : 2, 256)), dim3(256), 0, s, b.status,
                        b.ranges, nr);
+    if (u.L.fused) {
+        const int64_t nf = u.L.n_buckets * u.L.n_eblk;
+        hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(nf, 256)), dim3(256), 0, s, u.bucket, nf, 0u);
+    }
+}
+
+// Bucketed path, after the counts per (bucket, emission block): positions,
+// emission into the buckets, the in-bucket radix pass, ranges.
+hipError_t bin_finish_fused(const float *rec, const BinBufs &u, int64_t n, const bz_opts &o,
+                            const bz_bins &b, hipStream_t s) {
+    const BinLayout &L = u.L;
+    const int nbk = (int)L.n_buckets;
+    const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
+    const int ncv = o.batch ? o.batch->n_canvas : 0;
+    hipError_t e = scan_u32(u.bucket, u.bucket, L.n_buckets * L.n_eblk, u.part, b.status,
+                            b.cap_pairs, b.status, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_segments, dim3(1), dim3(kBlk), 0, s, (const uint32_t *)u.bucket, nbk,
+                       L.n_eblk, (const int64_t *)b.status, u.seg);
+    hipLaunchKernelGGL(k_emit_bucketed, dim3(8 * cdiv(L.n_eblk, 8 * kEmitWaves)),
+                       dim3(64 * kEmitWaves), 0, s,
+                       (const float4 *)rec, (const ushort4 *)u.rects, n, o.width, o.height,
+                       (int)tiles_x(o), 1.0f / o.tile_w, o.tile_h, support_two_p(o), cv, ncv,
+                       (const uint32_t *)u.bucket, nbk, L.n_eblk, u.packed, b.status);
+    hipLaunchKernelGGL(k_seg_hist, dim3(L.seg_blocks), dim3(kBlk), 0, s,
+                       (const uint32_t *)u.packed, (const uint32_t *)u.seg, nbk,
+                       (const int64_t *)b.status, u.hseg);
+    e = scan_u32(u.hseg, u.hseg, kRadix * L.seg_blocks, u.part, nullptr, 0, b.status, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_scatter, dim3(L.seg_blocks), dim3(kBlk), 0, s,
+                       (const uint32_t *)u.packed, (const uint32_t *)u.seg, nbk,
+                       (const uint32_t *)u.hseg, (const int64_t *)b.status, b.ids);
+    hipLaunchKernelGGL(k_seg_ranges, dim3(cdiv(L.n_tiles, 256)), dim3(256), 0, s,
+                       (const uint32_t *)u.hseg, (const uint32_t *)u.seg, nbk,
+                       (uint32_t)L.n_tiles, (const int64_t *)b.status, b.ranges);
+    return hipGetLastError();
 }
 
 // From the per-Gaussian tile counts and rectangles: offsets, pairs, sort, ranges.
@@ -676,9 +1141,10 @@ hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_
     const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
     const int ncv = o.batch ? o.batch->n_canvas : 0;
     hipLaunchKernelGGL(k_count, dim3(cdiv(n, 256)), dim3(256), 0, s, (const float4 *)rec_f, n,
-                       o.width, o.height, 1.0f / o.tile_w, 1.0f / o.tile_h, o.tile_h,
-                       support_two_p(o), cv, ncv, u.counts, u.rects, b.status);
-    return bin_finish(rec_f, u, n, o, b, s);
+                       o.width, o.height, (int)tiles_x(o), 1.0f / o.tile_w, 1.0f / o.tile_h,
+                       o.tile_h, support_two_p(o), cv, ncv, u.counts, u.rects, u.bucket,
+                       (int)u.L.n_buckets, u.L.n_eblk, b.status);
+    return u.L.fused ? bin_finish_fused(rec_f, u, n, o, b, s) : bin_finish(rec_f, u, n, o, b, s);
 }
 
 hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, const bz_bins &b,
@@ -688,10 +1154,11 @@ hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, c
     bin_prepare(u, b, s);
     if (n == 0) return hipGetLastError();
     const BinCount bc = {u.counts, u.rects, b.status, 1.0f / o.tile_w, 1.0f / o.tile_h, o.tile_h,
-                         support_two_p(o)};
+                         support_two_p(o), u.bucket, u.L.n_eblk, (int)u.L.n_buckets,
+                         (int)tiles_x(o)};
     hipError_t e = launch_sample(c, o, rec, &bc, s);
     if (e != hipSuccess) return e;
-    return bin_finish(rec, u, n, o, b, s);
+    return u.L.fused ? bin_finish_fused(rec, u, n, o, b, s) : bin_finish(rec, u, n, o, b, s);
 }
 
 }  // namespace bz

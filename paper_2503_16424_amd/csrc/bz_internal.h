@@ -113,8 +113,25 @@ struct BinLayout {
     int64_t off_part = 0;         // uint64 partial sums of the scans
     int64_t off_counters = 0;     // uint32 [4] at offset 0: tile counters of the persistent
                                   // blend kernels ([0] forward, [1] backward)
+    // Bucketed path (fused): pairs are emitted straight into buckets of 256
+    // consecutive tile keys, then sorted inside each bucket by the low key byte.
+    bool fused = false;
+    int64_t n_buckets = 0;        // ceil(n_tiles / 256)
+    int64_t n_eblk = 0;           // emission blocks of kEmitBlock Gaussians
+    int64_t seg_blocks = 0;       // radix blocks of the in-bucket pass: cap / 4096 + n_buckets
+    int64_t off_bucket = 0;       // uint32 [n_buckets][n_eblk] pairs -> first position
+    int64_t off_packed = 0;       // uint32 [cap] low key byte << 24 | Gaussian, bucket by bucket
+    int64_t off_seg = 0;          // uint32 [2][n_buckets + 1] bucket starts, first radix block
+    int64_t off_hseg = 0;         // uint32 [seg_blocks][256] digit counts -> positions
     int64_t total = 0;
 };
+// Gaussians per emission block of the bucketed path (one workgroup).
+constexpr int kEmitBlock = 64;
+// The bucketed path's limits: bucket indices fit a byte (n_tiles <= 2^16) and
+// a Gaussian index fits the 24 bits below the key byte.
+inline bool bin_fused(const bz_opts &o, int64_t n_gauss, int64_t n_tiles) {
+    return o.bin_sort == 0 && n_tiles <= 65536 && n_gauss < (int64_t(1) << 24);
+}
 BinLayout bin_layout(const bz_opts &o, int64_t n_gauss, int64_t cap_pairs);
 
 inline int64_t tiles_x(const bz_opts &o) { return (o.width + o.tile_w - 1) / o.tile_w; }
@@ -254,10 +271,12 @@ __device__ inline void support_row(const Support &s, int ty, int th, float inv_t
 // number of (tile, Gaussian) pairs: the sum over the rectangle's tile rows of
 // the tile columns the support itself reaches there (support_row), which
 // leaves out the corners of the box that an elongated, rotated Gaussian never
-// touches.  finite: the record is finite.
+// touches.  finite: the record is finite.  on_row(ty, c0, c1) receives every
+// row whose span is not empty.
+template <typename F>
 __device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv_tw,
                                      float inv_th, int th, float two_p, ushort4 &rc,
-                                     bool &finite) {
+                                     bool &finite, F on_row) {
     Support s;
     rc = make_ushort4(1, 1, 0, 0);
     if (!support_of(m, q, W, H, two_p, s, finite)) return 0u;
@@ -267,22 +286,49 @@ __device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv
     for (int ty = ty0; ty <= ty1; ++ty) {
         int c0, c1;
         support_row(s, ty, th, inv_tw, c0, c1);
-        n += c1 >= c0 ? (uint32_t)(c1 - c0 + 1) : 0u;
+        if (c1 >= c0) {
+            n += (uint32_t)(c1 - c0 + 1);
+            on_row(ty, c0, c1);
+        }
     }
     return n;
+}
+__device__ inline uint32_t tile_rect(float4 m, float4 q, int W, int H, float inv_tw,
+                                     float inv_th, int th, float two_p, ushort4 &rc,
+                                     bool &finite) {
+    return tile_rect(m, q, W, H, inv_tw, inv_th, th, two_p, rc, finite, [](int, int, int) {});
 }
 
 // Where sampling writes the tile counts and rectangles for the binning that
 // follows it (bz_sample_bin): the binning workspace's arrays, the tile shape
 // and the support constant.
 struct BinCount {
-    uint32_t *counts;
+    uint32_t *counts;      // per-Gaussian tile counts (two-pass radix path), or null
     ushort4 *rects;
     int64_t *status;
     float inv_tw, inv_th;
     int th;
     float two_p;
+    // bucketed path: pairs per (key bucket, emission block), added to
+    // bucket[h * n_eblk + g / kEmitBlock]; null on the radix path
+    uint32_t *bucket;
+    int64_t n_eblk;
+    int n_buckets;
+    int tiles_x;           // tiles per row of the canvas (single canvas)
 };
+
+// The key buckets (key >> 8) a tile-row span of keys [k0, k0 + w) falls in,
+// with the part in each: f(h, count).
+template <typename F>
+__device__ inline void for_key_buckets(uint32_t k0, uint32_t w, F f) {
+    const uint32_t k1 = k0 + w;
+    for (uint32_t k = k0; k < k1;) {
+        const uint32_t h = k >> 8;
+        const uint32_t e = min(k1, (h + 1u) << 8);
+        f(h, e - k);
+        k = e;
+    }
+}
 
 // Visit masks: one plane per 8x8 quad of a tile; a plane holds, for every tile,
 // ceil(len/64) words starting at word start/64 + tile (see visit_word).

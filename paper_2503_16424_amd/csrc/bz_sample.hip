@@ -11,7 +11,10 @@
 // and writes them as three contiguous 1 KB stores.  With kBin the kernel also
 // does the binning's counting pass (Sec. 3.4): each Gaussian's tile rectangle
 // and count, from the record values it stores, so the binning need not read
-// the records back.
+// the records back; on the bucketed path, instead of the count, the pairs per
+// (bucket of 256 tile keys, emission block): a wave's 64 Gaussians fall in at
+// most two emission blocks, so it adds its pairs up in LDS and sends each
+// non-zero sum with one global atomic.
 #include "bz_geom.h"
 
 namespace bz {
@@ -44,11 +47,20 @@ __global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8
     const float *opa = c.opacity + c.opa_off[v.id];
     const float cid = __int_as_float(v.id);
     const int n = v.rows * v.K;
+    int txc = bc.tiles_x;
+    uint32_t tbase = 0;
     if (kBin && cv) {   // the canvas holding the curve (and all its Gaussians)
         const int ci = batch_find(cv, n_canvas, v.g0, [](const bz_canvas &r) { return r.gauss_off; });
         W = cv[ci].width;
         H = cv[ci].height;
+        txc = cv[ci].tiles_x;
+        tbase = (uint32_t)cv[ci].tile_off;
     }
+    // bucketed path: the wave's pairs per (emission block of the round's first
+    // Gaussian + part, bucket) at hbw[part * n_buckets + bucket], in the dynamic
+    // LDS after the boundary rows
+    const bool bucketed = kBin && bc.bucket != nullptr;
+    const int nbk = bc.n_buckets;
     bool nonfinite = false;
     // A wave emits 64 consecutive Gaussians per round: their 48-byte records
     // meet in the wave's LDS slice and leave as three 1 KB contiguous stores
@@ -56,8 +68,14 @@ __global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8
     __shared__ float4 s_rec[kCurveThreads / 64][3 * 64];
     const int w = lane >> 6, l = lane & 63;
     float4 *my = s_rec[w];
+    uint32_t *hbw = reinterpret_cast<uint32_t *>(lds_xy + 2 * c.max_k) + w * 2 * nbk;
     for (int base = 64 * w; base < n; base += kCurveThreads) {
         const int idx = base + l;
+        const int64_t eb0 = (v.g0 + base) / kEmitBlock;
+        if (bucketed) {
+            for (int i = l; i < 2 * nbk; i += 64) hbw[i] = 0u;
+            wave_sync_lds();
+        }
         if (idx < n) {
             int r = idx / v.K, k = idx - r * v.K;
             Geom g;
@@ -77,11 +95,30 @@ __global__ __launch_bounds__(kCurveThreads) __attribute__((amdgpu_waves_per_eu(8
             if (kBin) {
                 ushort4 rc;
                 bool finite;
-                const uint32_t cnt = tile_rect(m, q, W, H, bc.inv_tw, bc.inv_th, bc.th,
-                                               bc.two_p, rc, finite);
-                bc.counts[v.g0 + idx] = cnt;
+                // bucketed path: each row's span of keys to its buckets
+                uint32_t *hb = hbw + (int)((v.g0 + idx) / kEmitBlock - eb0) * nbk;
+                const uint32_t cnt = tile_rect(
+                    m, q, W, H, bc.inv_tw, bc.inv_th, bc.th, bc.two_p, rc, finite,
+                    [&](int ty, int c0, int c1) {
+                        if (!bucketed) return;
+                        const uint32_t k0 = tbase + (uint32_t)ty * (uint32_t)txc + (uint32_t)c0;
+                        for_key_buckets(k0, (uint32_t)(c1 - c0 + 1),
+                                        [&](uint32_t h, uint32_t c) { atomicAdd(&hb[h], c); });
+                    });
+                if (bc.counts) bc.counts[v.g0 + idx] = cnt;
                 bc.rects[v.g0 + idx] = rc;
                 nonfinite |= !finite;
+            }
+        }
+        if (bucketed) {
+            wave_sync_lds();
+            for (int i = l; i < 2 * nbk; i += 64) {
+                const uint32_t c = hbw[i];
+                if (c) {
+                    const int part = i >= nbk ? 1 : 0;
+                    const int h = i - part * nbk;
+                    atomicAdd(&bc.bucket[(int64_t)h * bc.n_eblk + eb0 + part], c);
+                }
             }
         }
         wave_sync_lds();
@@ -100,6 +137,8 @@ hipError_t launch_sample(const bz_curves &c, const bz_opts &o, float *rec, const
                          hipStream_t s) {
     if (c.n_curves == 0) return hipSuccess;
     size_t lds = 2 * sizeof(double2) * (size_t)c.max_k;
+    if (bc && bc->bucket)      // per wave: two emission blocks' bucket sums
+        lds += sizeof(uint32_t) * 2 * (size_t)bc->n_buckets * (kCurveThreads / 64);
     double rho = (double)o.rho;
     const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
     const int ncv = o.batch ? o.batch->n_canvas : 0;

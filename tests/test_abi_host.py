@@ -138,9 +138,16 @@ def test_workspace_size_monotone():
         b = C.c_int64(0)
         assert lib.bz_workspace_size(C.byref(o), 5000, cap, C.byref(b)) == bz.BZ_OK
         sizes.append(b.value)
-    assert sizes == sorted(sizes) and sizes[-1] > 3 * 4 * 10 ** 7
+    # bucketed lists: the packed pairs (4 bytes each) and their digit counts
+    assert sizes == sorted(sizes) and 4 * 10 ** 7 < sizes[-1] < 5 * 10 ** 7
     b = C.c_int64(0)
     assert lib.bz_workspace_size(C.byref(o), 5000, 1 << 32, C.byref(b)) == bz.BZ_ERR_ARG
+    # the two-pass radix sort keeps keys, a second key array and a second id array
+    o.bin_sort = 1
+    assert lib.bz_workspace_size(C.byref(o), 5000, 10 ** 7, C.byref(b)) == bz.BZ_OK
+    assert b.value > 3 * 4 * 10 ** 7
+    o.bin_sort = 2
+    assert lib.bz_workspace_size(C.byref(o), 5000, 10 ** 7, C.byref(b)) == bz.BZ_ERR_ARG
 
 
 def test_device_calls_reject_null_arguments_before_launch():
@@ -340,10 +347,11 @@ def test_static_sample_bin_checks_arguments_and_size_on_host():
     small_cap = bz.Gaussians(8, 0, 4096)
     assert lib.bz_sample_bin_static(C.byref(_fake_curves()), C.byref(o), C.byref(small_cap),
                                     C.byref(_fake_bins()), None) == bz.BZ_ERR_CAPACITY
-    # a pair capacity whose workspace exceeds BZ_STATIC_SCRATCH_BYTES (12 bytes a pair)
-    big = bz.Bins(4 << 20, 4096, 4096, 0, 0, 4096)
+    # a pair capacity whose workspace exceeds BZ_STATIC_SCRATCH_BYTES (about 4.3
+    # bytes a pair on the bucketed path)
+    big = bz.Bins(9 << 20, 4096, 4096, 0, 0, 4096)
     need = C.c_int64(0)
-    assert lib.bz_workspace_size(C.byref(o), 16, 4 << 20, C.byref(need)) == bz.BZ_OK
+    assert lib.bz_workspace_size(C.byref(o), 16, 9 << 20, C.byref(need)) == bz.BZ_OK
     assert need.value > bz.STATIC_SCRATCH_BYTES
     assert lib.bz_sample_bin_static(C.byref(_fake_curves()), C.byref(o), C.byref(g), C.byref(big),
                                     None) == bz.BZ_ERR_CAPACITY

@@ -33,9 +33,9 @@ def torch_cuda():
     return torch
 
 
-def _rast(scene, tile=(16, 16), **kw):
+def _rast(scene, tile=(16, 16), radix=False, **kw):
     from paper_2503_16424_amd import bz
-    ro = bz.RenderOptions(tile_w=tile[0], tile_h=tile[1])
+    ro = bz.RenderOptions(tile_w=tile[0], tile_h=tile[1], radix_bins=radix)
     return bz.Rasterizer(scene, ro, **kw)
 
 
@@ -106,12 +106,13 @@ def _support_tiles(mu, conic, W, H, tw, th, g_min):
     return out
 
 
+@pytest.mark.parametrize("radix", [False, True])
 @pytest.mark.parametrize("name", ["tiny_128", "mixed_small_b", "mixed_R20"])
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
-def test_tile_lists_valid_and_complete(torch_cuda, name, tile):
+def test_tile_lists_valid_and_complete(torch_cuda, name, tile, radix):
     sc = SCENES[name]()
-    _note(f"tile lists {name} tile={tile}")
-    r = _rast(sc, tile)
+    _note(f"tile lists {name} tile={tile} radix={radix}")
+    r = _rast(sc, tile, radix)
     r.sample()
     r.bin()
     assert not r.ensure_capacity()
@@ -531,21 +532,23 @@ def test_forward_fused_with_l2_matches_separate_calls(torch_cuda, name, state, p
         assert rel_l2(getattr(r, k).cpu().numpy(), o[k]) <= GRAD_TOL, k
 
 
+@pytest.mark.parametrize("radix", [False, True])
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
 @pytest.mark.parametrize("name", ["tiny_128", "mixed_small_b", "mixed_R20", "size_split"])
-def test_sample_bin_matches_separate_calls(torch_cuda, name, tile):
+def test_sample_bin_matches_separate_calls(torch_cuda, name, tile, radix):
     torch = torch_cuda
     from paper_2503_16424_amd import bz
     from tests.helpers import sample_bin_matches_separate, size_split_scene
     sc = size_split_scene() if name == "size_split" else SCENES[name]()
-    _note(f"sample+bin {name} tile {tile}")
-    r = _rast(sc, tile)
+    _note(f"sample+bin {name} tile {tile} radix={radix}")
+    r = _rast(sc, tile, radix)
     r.render()                                  # sizes the pair buffer
     assert sample_bin_matches_separate(torch, r) > 0
     assert not r.flags() & bz.STATUS_OVERFLOW
 
 
-def test_sample_bin_overflow_and_non_finite_flags(torch_cuda):
+@pytest.mark.parametrize("radix", [False, True])
+def test_sample_bin_overflow_and_non_finite_flags(torch_cuda, radix):
     """Too small a pair buffer and a NaN control point: bz_sample_bin raises
     the same status bits and counts the same pairs as the two calls."""
     torch = torch_cuda
@@ -555,7 +558,7 @@ def test_sample_bin_overflow_and_non_finite_flags(torch_cuda):
     pts = np.array(sc.ctrl, copy=True)
     pts[int(sc.ctrl_off[3])] = np.nan
     sc.ctrl = pts
-    r = _rast(sc, cap_pairs=64)
+    r = _rast(sc, radix=radix, cap_pairs=64)
     need = sample_bin_matches_separate(torch, r)
     assert need > 64
     assert r.flags() & bz.STATUS_OVERFLOW and r.flags() & bz.STATUS_NONFINITE

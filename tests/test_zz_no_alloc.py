@@ -82,7 +82,7 @@ def test_static_sample_bin_rejects_what_does_not_fit():
     import torch
     from paper_2503_16424_amd import bz
     sc = scenes.open_512(0)
-    r = bz.Rasterizer(sc, bz.RenderOptions(tile_w=16, tile_h=16), cap_pairs=4 << 20)
+    r = bz.Rasterizer(sc, bz.RenderOptions(tile_w=16, tile_h=16), cap_pairs=9 << 20)
     r.status.fill_(-7)
     torch.cuda.synchronize()
     with pytest.raises(bz.BzError) as e:

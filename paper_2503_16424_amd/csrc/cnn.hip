@@ -189,6 +189,40 @@ __device__ inline void gather_b(const GemmArgs &g, int64_t n, int64_t k0, int64_
     }
 }
 
+// Filter gradient, B without vector loads (input channels not a multiple of
+// 8): B[k .. k+7][n] = the input channel of n at the pixel that output pixels
+// k .. k+7 read through the tap of n.  The output pixels are consecutive, so
+// the first one's (image, row, column) is divided out once and the others
+// follow by stepping along the row (gather_b's element path divides for each).
+__device__ inline void gather_b_wgrad(const GemmArgs &g, int64_t n, int64_t k0, int64_t kend,
+                                      uint16_t (&v)[8]) {
+    const Shape &S = g.S;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = 0;
+    if (n >= g.N || k0 >= kend) return;
+    const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
+    const int ky = tap / S.r, kx = tap - (tap / S.r) * S.r;
+    const int64_t hw = (int64_t)S.ho * S.wo;
+    int64_t b = k0 / hw;
+    const int rem = (int)(k0 - b * hw);
+    int oy = rem / S.wo, ox = rem - (rem / S.wo) * S.wo;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (k0 + j < kend) {
+            const int iy = oy * S.s - S.p + ky, ix = ox * S.s - S.p + kx;
+            if (iy >= 0 && ix >= 0 && iy < S.h && ix < S.w)
+                v[j] = g.x[((b * S.h + iy) * S.w + ix) * S.c + ci];
+        }
+        if (++ox == S.wo) {
+            ox = 0;
+            if (++oy == S.ho) {
+                oy = 0;
+                ++b;
+            }
+        }
+    }
+}
+
 // 8 bf16 from a 16-byte aligned address, or zeros.
 __device__ inline void load8_bf16(const uint16_t *p, bool ok, uint16_t (&v)[8]) {
     uint4 q = make_uint4(0, 0, 0, 0);
@@ -272,6 +306,10 @@ __device__ inline void load_tiles(const GemmArgs &g, int64_t m0, int64_t n0, int
         load8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, v);
 #pragma unroll
         for (int j = 0; j < 8; ++j) sB[tc + j][tk] = v[j];
+    } else if (MODE == kBwdWeight) {
+        gather_b_wgrad(g, n0 + lrow, k0 + lk, kend, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
     } else {
         gather_b<MODE>(g, n0 + lrow, k0 + lk, kend, v);
 #pragma unroll

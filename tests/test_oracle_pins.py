@@ -498,3 +498,84 @@ def test_rejects_bad_scenes():
     bad.k_samples[0] = 1                             # K >= 2 is required
     with pytest.raises(ValueError):
         oracle.sample(bad)
+
+
+# --- decision margins and tile depth (the parity report's diagnostics) -------
+
+def test_margin_is_the_threshold_shift_that_flips_the_support_test():
+    """One Gaussian, no clamp (alpha_max = 1 > every raw alpha) and no stop
+    (t_min = 0): a pixel's only binding decision is the support test G > g_min.
+    Moving g_min by 1.01x the reported margin towards G flips the pixel's
+    contribution; by 0.99x it does not."""
+    W, H = 40, 32
+    g = gauss_set([20.3, 15.7], [0.05, 0.012, 0.11], [0.5], [0.2, 0.4, 0.6])
+    base = dict(t_min=0.0, alpha_max=1.0)
+    gm = oracle.DEFAULTS["g_min"]
+    r = oracle.render(g, W, H, (1.0, 1.0, 1.0), opts=dict(base, g_min=gm))
+    m, inside = r["margin"], r["n_contrib"] > 0
+    sel = np.argwhere((m < 0.4) & (m > 1e-9))
+    assert len(sel) > 40, "too few pixels near the support boundary"
+    for s in (0.99, 1.01):
+        for y, x in sel[:: max(1, len(sel) // 40)]:
+            # G = gm (1 + m) inside, gm (1 - m) outside: shift g_min towards it
+            gm2 = gm * (1.0 + s * m[y, x]) if inside[y, x] else gm * (1.0 - s * m[y, x])
+            r2 = oracle.render(g, W, H, (1.0, 1.0, 1.0), opts=dict(base, g_min=gm2),
+                               rows=(int(y), int(y) + 1))
+            flipped = (r2["n_contrib"][y, x] > 0) != inside[y, x]
+            assert flipped == (s > 1.0), (y, x, m[y, x], s)
+
+
+def test_margin_is_zero_at_a_threshold_and_positive_elsewhere():
+    """A pixel whose G equals g_min to rounding has margin ~0; the margin is
+    never negative and infinite only where no Gaussian was evaluated."""
+    gm = oracle.DEFAULTS["g_min"]
+    # isotropic Gaussian, Q = I / s2, pixel (0, 0) at d = (0.5 - mx, 0.5 - my):
+    # put it on the support boundary 1/2 |d|^2 / s2 = -ln gm
+    s2 = 4.0
+    r0 = math.sqrt(-2.0 * s2 * math.log(gm))
+    mx, my = 0.5 + r0 / math.sqrt(2.0), 0.5 + r0 / math.sqrt(2.0)
+    g = gauss_set([mx, my], [1.0 / s2, 0.0, 1.0 / s2], [0.5], [0.1, 0.1, 0.1])
+    r = oracle.render(g, 32, 32, (1.0, 1.0, 1.0), opts=dict(t_min=0.0, alpha_max=1.0))
+    assert r["margin"][0, 0] < 1e-12
+    assert np.all(r["margin"][np.isfinite(r["margin"])] >= 0.0)
+    assert np.all(r["margin"][1:, 1:] > 0.0)
+
+
+def test_tile_depth_equals_brute_force_counts():
+    """Without early stops every Gaussian with G > g_min at a pixel contributes
+    there, so a tile's contributing-curve count is the number of curves with
+    such a Gaussian at one of its pixels (brute force in numpy); the
+    reaching-curve count lies between that and the curves whose Gaussians'
+    support boxes (the exact ellipse's extent, padded by 2 px) meet the tile."""
+    sc = to_f64(scenes.small_mixed(21, W=56, H=40, n_closed=4, n_open=6, K=8, R=3))
+    g = oracle.sample(sc)
+    W, H, tw, th = sc.width, sc.height, 16, 8
+    opts = dict(t_min=0.0)
+    d = oracle.tile_depth(g, sc.n_curves, W, H, (tw, th), opts=opts)
+    gm = oracle.DEFAULTS["g_min"]
+    ys, xs = np.mgrid[0:H, 0:W]
+    px, py = xs.ravel() + 0.5, ys.ravel() + 0.5
+    dx = px[None, :] - g["mu"][:, 0:1]
+    dy = py[None, :] - g["mu"][:, 1:2]
+    q = g["conic"]
+    G = np.exp(-0.5 * (q[:, 0:1] * dx * dx + 2 * q[:, 1:2] * dx * dy + q[:, 2:3] * dy * dy))
+    hit = G > gm                                       # [gauss, pixel]
+    tile_of_px = (ys.ravel() // th) * (-(-W // tw)) + xs.ravel() // tw
+    nt = (-(-W // tw)) * (-(-H // th))
+    det = q[:, 0] * q[:, 2] - q[:, 1] ** 2
+    hx = np.sqrt(-2 * math.log(gm) * q[:, 2] / det) + 2.0
+    hy = np.sqrt(-2 * math.log(gm) * q[:, 0] / det) + 2.0
+    for t in range(nt):
+        cols = tile_of_px == t
+        gs = np.nonzero(hit[:, cols].any(axis=1))[0]
+        want = len(set(g["curve"][gs].tolist()))
+        assert d["contrib"][t] == want, (t, d["contrib"][t], want)
+        ty, tx = divmod(t, -(-W // tw))
+        x0, x1, y0, y1 = tx * tw, min(W, tx * tw + tw), ty * th, min(H, ty * th + th)
+        near = (g["mu"][:, 0] + hx > x0) & (g["mu"][:, 0] - hx < x1) & \
+               (g["mu"][:, 1] + hy > y0) & (g["mu"][:, 1] - hy < y1)
+        upper = len(set(g["curve"][near].tolist()))
+        assert want <= d["support"][t] <= upper, (t, want, d["support"][t], upper)
+    # with the paper's stop, no tile gains contributors
+    d2 = oracle.tile_depth(g, sc.n_curves, W, H, (tw, th))
+    assert np.all(d2["contrib"] <= d["contrib"])

@@ -4,7 +4,7 @@ The committed weights (trained on the GPU by the project's own BF16
 kernels) propose the curves of a held-out synthetic 512x512 target (a seed
 outside the training and evaluation sets).  Under the learning rates of Sec.
 4.1 the learned start must begin far above the uniform random start, reach
-the random start's 300-step PSNR in well under the 300 steps, and end above
+the random start's 300-step PSNR in at most 40% of the 300 steps, and end above
 it.
 """
 import os
@@ -39,7 +39,7 @@ def test_learned_start_beats_random_start(net):
           f"{lrn['steps_to_random_final']}", flush=True)
     assert lrn["psnr_initial"] >= rnd["psnr_initial"] + 5.0
     assert lrn["steps_to_random_final"] is not None
-    assert lrn["fraction_of_steps"] <= 0.6
+    assert lrn["fraction_of_steps"] <= 0.4
     assert lrn["psnr_final"] > rnd["psnr_final"]
 
 

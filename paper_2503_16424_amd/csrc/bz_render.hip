@@ -803,20 +803,23 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     Ag = fmaf(al, e, Ag);
                     T = Tb;
                     const float f = shaped ? abar : 0.f;
-                    const float fG = f * G;
+                    // f G and f straight into their moment registers (the
+                    // positions past the table overwrite the first and
+                    // ignore the tenth), so neither needs a copy
+                    acc[kSums * s + 0] = f * G;
+                    acc[kSums * s + 9] = f;
+                    const float fG = acc[kSums * s + 0];
                     acc[kSums * s + 6] = wgt * g0;
                     acc[kSums * s + 7] = wgt * g1;
                     acc[kSums * s + 8] = wgt * g2;
                     if (pos < (uint32_t)tab_cap) {
                         // moments about the tile centre (wave-uniform branch)
                         const float fGx = fG * cx, fGy = fG * cy;
-                        acc[kSums * s + 0] = fG;
                         acc[kSums * s + 1] = fGx;
                         acc[kSums * s + 2] = fGy;
                         acc[kSums * s + 3] = fGx * cx;
                         acc[kSums * s + 4] = fGx * cy;
                         acc[kSums * s + 5] = fGy * cy;
-                        acc[kSums * s + 9] = f;
                     } else {
                         // the planes without their constant factors (plane_scale)
                         const float P = fG * st.q.w;             // -dL/dp
@@ -827,7 +830,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                         acc[kSums * s + 3] = Pdx * dy;
                         acc[kSums * s + 4] = Pdy * dy;
                         acc[kSums * s + 5] = fmaf(-g_min, f, fG);    // f (G - g_min)
-                        acc[kSums * s + 9] = 0.f;
+                        // acc[kSums * s + 9] is not stored for these
+                        // positions: the reduction sums each index on its own
                     }
                     slot_pos[s] = pos;
                     filled = s + 1;

@@ -301,10 +301,12 @@ __global__ __launch_bounds__(64) void k_emit(const float4 *__restrict__ rec,
             wid[j] = 0;
             if (it < ci) {
                 const uint32_t r = c0 + it;
-                int lo = 0;                    // last Gaussian whose first row <= r
+                // last Gaussian whose first row <= r (lanes past nb hold
+                // nrows > r, so the search needs no bound)
+                int lo = 0;
 #pragma unroll
                 for (int step = kEmitG / 2; step >= 1; step >>= 1)
-                    if (lo + step < nb && s_rows[lo + step] <= r) lo += step;
+                    if (s_rows[lo + step] <= r) lo += step;
                 const int dr = (int)(r - s_rows[lo]);
                 int cl, ch;
                 support_row(s_sup[lo], (int)s_ty0[lo] + dr, th, inv_tw, cl, ch);
@@ -322,7 +324,9 @@ __global__ __launch_bounds__(64) void k_emit(const float4 *__restrict__ rec,
             if (it < ci) s_item_off[it] = ex;
             ex += wid[j];
         }
-        if (t == 0) s_item_off[ci] = cnt;
+        // the slots past the chunk's last row hold cnt (> every pair index),
+        // so the pair search below needs no bound
+        for (uint32_t it = ci + t; it <= (uint32_t)kRowChunk; it += 64) s_item_off[it] = cnt;
         wave_lds_fence();
 #pragma unroll
         for (int j = 0; j < kRowChunk / 64; ++j) {
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(64) void k_emit(const float4 *__restrict__ rec,
             int lo = 0;                        // last row item whose offset <= i
 #pragma unroll
             for (int step = kRowChunk / 2; step >= 1; step >>= 1)
-                if ((uint32_t)(lo + step) < ci && s_item_off[lo + step] <= i) lo += step;
+                if (s_item_off[lo + step] <= i) lo += step;
             const uint32_t o = out + i;
             const int gl = s_item_g[lo];
             // only inside the Gaussian's own range (the counts agree, so this holds)
@@ -651,6 +655,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     const uint32_t span = wave_max_u32(my_rows ? hhi : 0u) - hl;   // buckets hl .. hl + span
     int nbits = 0;
     while (nbits < 8 && (1u << nbits) <= span) ++nbits;
+    nbits = __builtin_amdgcn_readfirstlane(nbits);     // wave-uniform: a scalar loop
     // this block's part of each of its buckets (first position, size), stored
     // in LDS once the first chunk's rows are done, which hides the loads
     auto fetch_parts = [&]() {
@@ -674,10 +679,12 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
             wid[j] = 0;
             if (it < ci) {
                 const uint32_t r = c0 + it;
-                int lo = 0;                    // last Gaussian whose first row <= r
+                // last Gaussian whose first row <= r (lanes past nb hold
+                // nrows > r, so the search needs no bound)
+                int lo = 0;
 #pragma unroll
                 for (int step = kEmitG / 2; step >= 1; step >>= 1)
-                    if (lo + step < nb && s_rows[wv][lo + step] <= r) lo += step;
+                    if (s_rows[wv][lo + step] <= r) lo += step;
                 const int dr = (int)(r - s_rows[wv][lo]);
                 int cl, ch;
                 support_row(s_sup[wv][lo], (int)s_ty0[wv][lo] + dr, th_, inv_tw, cl, ch);
@@ -695,7 +702,9 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
             if (it < ci) s_item_off[wv][it] = ex;
             ex += wid[j];
         }
-        if (t == 0) s_item_off[wv][ci] = cnt;
+        // the slots past the chunk's last row hold cnt (> every pair index),
+        // so the pair search below needs no bound
+        for (uint32_t it = ci + t; it <= (uint32_t)kRowChunk; it += 64) s_item_off[wv][it] = cnt;
         if (c0 == 0) fetch_parts();
         wave_lds_fence();
         // rounds of 64 consecutive pairs of the chunk, one per lane
@@ -707,7 +716,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
                 int lo = 0;                    // last row item whose offset <= i
 #pragma unroll
                 for (int step = kRowChunk / 2; step >= 1; step >>= 1)
-                    if ((uint32_t)(lo + step) < ci && s_item_off[wv][lo + step] <= i) lo += step;
+                    if (s_item_off[wv][lo + step] <= i) lo += step;
                 key = s_item_key[wv][lo] + (i - s_item_off[wv][lo]);
                 gl = s_item_g[wv][lo];
             }

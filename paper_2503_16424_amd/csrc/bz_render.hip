@@ -605,7 +605,12 @@ __device__ inline float plane_scale(int v, float inv_1mg) {
 // Tile-list positions pooled in LDS by the backward.  With 16x16 tiles a
 // block then takes 256 x 48 B of staging + 10 x 352 x 4 B of sums = 25.8 KiB,
 // so six blocks share a CU's 160 KiB of LDS.  (Five blocks ran 5% slower; with
-// half the positions more sums go to global atomics, 16% slower.)
+// half the positions more sums go to global atomics, 16% slower; a table sized
+// to each tile shape's occupancy ran 8x8 and 16x8 tiles 4-9% slower and 16x32
+// tiles 12% slower.)  The recomputing backward also keeps its batch masks in
+// LDS; its table gives up their bytes (table_cap), so both forms hold the
+// same LDS per block: 240 positions at 16x16, 6% faster than 352 at five
+// blocks per CU.
 constexpr int kTableCap = 352;
 
 // Backward stage 1.  Each wave walks its tile list from the last entry any of
@@ -1296,6 +1301,15 @@ hipError_t launch_fwd(const float *rec, const bz_bins &b, const bz_opts &o, floa
     return hipGetLastError();
 }
 
+// Sum-table positions of a backward block whose batch masks take vis_bytes of
+// LDS (0 for the stored blend state): kTableCap less those bytes, in whole
+// multiples of 16 positions, at least 128.
+int table_cap(size_t vis_bytes) {
+    const int64_t per16 = (int64_t)(sizeof(float) * kSums * 16);
+    const int64_t cut = ((int64_t)vis_bytes + per16 - 1) / per16 * 16;
+    return kTableCap - cut < 128 ? 128 : (int)(kTableCap - cut);
+}
+
 hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
                             const bz_opts &o, const float *d_image, const bz_pixstate *st,
                             float *d_gauss, hipStream_t s) {
@@ -1310,15 +1324,15 @@ hipError_t launch_bwd_gauss(const float *rec, int64_t n_gauss, const bz_bins &b,
     a.d_gauss = d_gauss;
     a.n_gauss = n_gauss;
     int threads = o.tile_w * o.tile_h;
-    a.tab_cap = kTableCap;
-    size_t lds = sizeof(Staged) * (size_t)threads + sizeof(float) * kSums * (size_t)kTableCap;
+    const size_t vis = st ? 0 : sizeof(uint64_t) * kVisCap * (size_t)(threads / 64);
+    a.tab_cap = table_cap(vis);
+    size_t lds = sizeof(Staged) * (size_t)threads + vis + sizeof(float) * kSums * (size_t)a.tab_cap;
     if (st) {
         a.t_final = st->t_final;
         a.n_last = st->n_last;
         a.visit = st->visit;
         launch_tiles(k_bwd_tiles<false>, a, b, o, 1, threads, lds, s);
     } else {
-        lds += sizeof(uint64_t) * kVisCap * (size_t)(threads / 64);
         launch_tiles(k_bwd_tiles<true>, a, b, o, 1, threads, lds, s);
     }
     return hipGetLastError();

@@ -254,10 +254,10 @@ def evaluate(net, size: int = 1024, steps: int = 1000, seed: int = 77, log_every
 def main(argv=None):
     ap = argparse.ArgumentParser(description="learned curve initialiser")
     ap.add_argument("cmd", choices=["all", "eval"])
-    ap.add_argument("--canvases", type=int, default=40)
+    ap.add_argument("--canvases", type=int, default=320)
     ap.add_argument("--fit-steps", type=int, default=600)
-    ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--render-epochs", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=80)
+    ap.add_argument("--render-epochs", type=int, default=60)
     ap.add_argument("--eval-size", type=int, default=1024)
     ap.add_argument("--eval-steps", type=int, default=1000)
     ap.add_argument("--eval-seeds", default="77,78,79")

@@ -476,6 +476,177 @@ __global__ __launch_bounds__(256) void k_bias_grad4(const float *__restrict__ dy
     }
 }
 
+// Filter and bias gradients of the first layer's shape: 3 x 3 filters, stride
+// 1, padding 1, at most 3 input channels, 64 output channels, rows of 32
+// pixels.  The generic split-K path spends most of its time in float atomics
+// there (1,728 outputs per 256 output pixels, all meeting on 54 lines).
+//
+// One workgroup per image.  The image (h x 32 x C BF16) goes into LDS three
+// times, shifted by kx = 0, 1, 2 columns and stored channel-planar with a zero
+// border, so the 8 consecutive output pixels a lane feeds the matrix core
+// through tap (ky, kx) and channel ci are one aligned 16-byte LDS read.  A
+// wave takes whole output rows: a row of 32 pixels is one k step of
+// C[co][(tap, ci)] += dy_row^T x shifted input row (4 x 2 blocks of
+// v_mfma_f32_16x16x32_bf16), with the next row's dy loads in flight, and the
+// bias gradient sums the same dy values in FP32.  The waves meet in LDS; one
+// float atomic per output adds the image's share (dw and db are cleared
+// first): 1,792 atomics per 1,024 pixels.
+constexpr int kWg0Waves = 8;
+
+inline bool wgrad_first_shape(const bz_conv &c) {
+    return c.r == 3 && c.stride == 1 && c.pad == 1 && c.c >= 1 && c.c <= 3 && c.k == 64 &&
+           c.w == 32 && c.h >= 1 && c.h <= 64;
+}
+
+inline size_t wgrad_first_lds(const bz_conv &c) {
+    return (size_t)3 * (c.h + 2) * c.c * 32 * sizeof(uint16_t);
+}
+
+// dy of output row oy, pixels 8q .. 8q + 7, channels 16 mb + r (mb = 0..3)
+__device__ inline void wgrad_first_row(const float *__restrict__ dy, int64_t row, int q, int r,
+                                       float (&v)[4][8]) {
+    const float *p = dy + (row * 32 + 8 * q) * 64 + r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) v[mb][j] = p[j * 64 + 16 * mb];
+}
+
+// Rows a wave has in flight at once (its rows are wave, wave + 8, ...).
+constexpr int kWg0Rows = 4;
+
+template <int C>
+__global__ __launch_bounds__(64 * kWg0Waves) void k_wgrad_first(const float *__restrict__ dy,
+                                                                const uint16_t *__restrict__ x,
+                                                                int h, float *dw, float *db) {
+    extern __shared__ __align__(16) uint16_t s_img[];    // [kx][h + 2][C][32]
+    // each wave's result blocks, lane-major (the waves meet by plain sums:
+    // LDS float atomics from eight waves took longer than the rows)
+    __shared__ floatx4 s_part[kWg0Waves][8][64];
+    __shared__ float s_bpart[kWg0Waves][64];
+    constexpr int kThreads = 64 * kWg0Waves, kPitch = C * 32, kN = 9 * C;
+    const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int rows = h + 2, plane = rows * kPitch;
+    const int r = lane & 15, q = lane >> 4;
+    // the first kWg0Rows rows of dy go in flight before the image is staged
+    float v[kWg0Rows][4][8];
+#pragma unroll
+    for (int i = 0; i < kWg0Rows; ++i)
+        if (wave + kWg0Waves * i < h) wgrad_first_row(dy, (int64_t)b * h + wave + kWg0Waves * i, q, r, v[i]);
+    // clear the copies (their borders stay zero) and the sums
+    for (int i = t; i < 3 * plane / 8; i += kThreads)
+        reinterpret_cast<uint4 *>(s_img)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    // s_img[kx][iy + 1][ci][ix + 1 - kx] = x[b][iy][ix][ci]: the image is
+    // 64 h C bytes (a multiple of 16, as is its offset), 8 elements per load
+    const uint4 *src = reinterpret_cast<const uint4 *>(x + (int64_t)b * h * 32 * C);
+    for (int i = t; i < 4 * h * C; i += kThreads) {
+        const uint4 u = src[i];
+        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = 8 * i + j;                        // (iy * 32 + ix) * C + ci
+            const int px = e / C, ci = e - px * C;
+            const int iy = px >> 5, ix = px & 31;
+            const uint16_t u16 = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
+            uint16_t *d = s_img + (iy + 1) * kPitch + ci * 32 + ix + 1;
+            if (ix < 31) d[0] = u16;                        // kx = 0
+            d[plane - 1] = u16;                             // kx = 1
+            if (ix > 0) d[2 * plane - 2] = u16;             // kx = 2
+        }
+    }
+    __syncthreads();
+    // B column n = 16 nb + r is (tap, ci) = (n / C, n mod C); lane q feeds
+    // output pixels 8q .. 8q + 7 of the row.  Offset of row oy = 0, or -1
+    // for the padding columns n >= 9C.
+    int boff[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const int n = 16 * nb + r;
+        boff[nb] = -1;
+        if (n < kN) {
+            const int tap = n / C, ci = n - tap * C, ky = tap / 3, kx = tap - 3 * ky;
+            boff[nb] = (kx * rows + ky) * kPitch + ci * 32 + 8 * q;
+        }
+    }
+    floatx4 acc[4][2];
+    float bsum[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        bsum[mb] = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int oy0 = wave; oy0 < h; oy0 += kWg0Waves * kWg0Rows) {
+#pragma unroll
+        for (int i = 0; i < kWg0Rows; ++i) {
+            const int oy = oy0 + kWg0Waves * i;
+            if (oy >= h) break;
+            bf16x8 bv[2];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                bf16x8 z;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) z[j] = bf_bits(0);
+                bv[nb] = boff[nb] >= 0
+                             ? *reinterpret_cast<const bf16x8 *>(s_img + boff[nb] + oy * kPitch)
+                             : z;
+            }
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                bf16x8 a;
+                float sm = 0.f;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    a[j] = (__bf16)v[i][mb][j];             // v_cvt_pk_bf16_f32, nearest even
+                    sm += v[i][mb][j];
+                }
+                bsum[mb] += sm;
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[mb][nb] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv[nb], acc[mb][nb], 0, 0, 0);
+            }
+            // refill the slot with the row kWg0Rows ahead (images taller than
+            // kWg0Waves * kWg0Rows rows)
+            const int on = oy + kWg0Waves * kWg0Rows;
+            if (on < h) wgrad_first_row(dy, (int64_t)b * h + on, q, r, v[i]);
+        }
+    }
+    // lane holds C[16 mb + 4q + e][16 nb + r] in acc[mb][nb][e]
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) s_part[wave][2 * mb + nb][lane] = acc[mb][nb];
+        float sm = bsum[mb];
+        sm += __shfl_xor(sm, 16);
+        sm += __shfl_xor(sm, 32);
+        if (q == 0) s_bpart[wave][16 * mb + r] = sm;
+    }
+    __syncthreads();
+    for (int o = t; o < 64 * kN + 64; o += kThreads) {
+        float sum = 0.f;
+        if (o < 64 * kN) {
+            const int m = o / kN, n = o - m * kN;
+            const int blk = 2 * (m >> 4) + (n >> 4), ln = 16 * ((m >> 2) & 3) + (n & 15), e = m & 3;
+#pragma unroll
+            for (int w = 0; w < kWg0Waves; ++w) sum += s_part[w][blk][ln][e];
+            atomicAdd(&dw[o], sum);
+        } else if (db) {
+#pragma unroll
+            for (int w = 0; w < kWg0Waves; ++w) sum += s_bpart[w][o - 64 * kN];
+            atomicAdd(&db[o - 64 * kN], sum);
+        }
+    }
+}
+
+template <int C>
+void launch_wgrad_first(const bz_conv &c, const float *dy, const uint16_t *x, float *dw,
+                        float *db, hipStream_t s) {
+    hipLaunchKernelGGL(k_wgrad_first<C>, dim3((unsigned)c.n), dim3(64 * kWg0Waves),
+                       wgrad_first_lds(c), s, dy, x, c.h, dw, db);
+}
+
 __global__ void k_to_bf16(const float *src, uint16_t *dst, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -563,6 +734,14 @@ hipError_t launch_conv_bwd_weight(const bz_conv &c, const float *dy, const uint1
     const int64_t nz = g.M * g.N;
     hipLaunchKernelGGL(k_fill0, dim3((unsigned)cdiv(nz, 256) < 4096 ? (unsigned)cdiv(nz, 256) : 4096),
                        dim3(256), 0, s, dw, nz);
+    if (wgrad_first_shape(c) && ((uintptr_t)x & 15) == 0) {     // 16-byte image loads
+        if (db)
+            hipLaunchKernelGGL(k_fill0, dim3(1), dim3(256), 0, s, db, (int64_t)c.k);
+        if (c.c == 1) launch_wgrad_first<1>(c, dy, x, dw, db, s);
+        else if (c.c == 2) launch_wgrad_first<2>(c, dy, x, dw, db, s);
+        else launch_wgrad_first<3>(c, dy, x, dw, db, s);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), (unsigned)cdiv(g.K, g.k_chunk));
     // A: 8 output channels of dy (k % 8); B: 8 input channels of a shifted pixel (c % 8)
     launch_igemm<kBwdWeight>(g, c.k % 8 == 0, c.c % 8 == 0, grid, s);

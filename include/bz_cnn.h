@@ -36,7 +36,7 @@ typedef struct {
 } bz_conv;
 
 /* Host: validate the sizes and set ho, wo.  BZ_ERR_ARG for non-positive
- * sizes, an empty output or a bad filter; BZ_ERR_UNSUPPORTED beyond 2^31
+ * sizes, an empty output or a bad filter; BZ_ERR_UNSUPPORTED from 2^30
  * elements per tensor. */
 bz_status bz_conv_shape(bz_conv *cv);
 

@@ -58,9 +58,9 @@ struct Shape {
 };
 
 // Input pixel read by output pixel m through filter tap `tap`, or -1 (padding).
-__device__ inline int64_t in_pixel(const Shape &S, int64_t m, int tap) {
-    const int64_t hw = (int64_t)S.ho * S.wo;
-    const int64_t b = m / hw;
+__device__ inline int in_pixel(const Shape &S, int m, int tap) {
+    const int hw = (int)S.ho * S.wo;
+    const int b = m / hw;
     const int rem = (int)(m - b * hw);
     const int oy = rem / S.wo, ox = rem - (rem / S.wo) * S.wo;
     const int ky = tap / S.r, kx = tap - (tap / S.r) * S.r;
@@ -70,9 +70,9 @@ __device__ inline int64_t in_pixel(const Shape &S, int64_t m, int tap) {
 }
 
 // Output pixel that input pixel m feeds through tap `tap`, or -1.
-__device__ inline int64_t out_pixel(const Shape &S, int64_t m, int tap) {
-    const int64_t hw = (int64_t)S.h * S.w;
-    const int64_t b = m / hw;
+__device__ inline int out_pixel(const Shape &S, int m, int tap) {
+    const int hw = (int)S.h * S.w;
+    const int b = m / hw;
     const int rem = (int)(m - b * hw);
     const int iy = rem / S.w, ix = rem - (rem / S.w) * S.w;
     const int ky = tap / S.r, kx = tap - (tap / S.r) * S.r;
@@ -87,7 +87,7 @@ enum Mode { kFwd = 0, kBwdData = 1, kBwdWeight = 2 };
 
 struct GemmArgs {
     Shape S;
-    int64_t M, N, K;          // GEMM sizes
+    int M, N, K;          // GEMM sizes
     const uint16_t *x;        // input activations (bf16)
     const uint16_t *w;        // filters (bf16)
     const float *dy;          // output gradients (f32)
@@ -96,7 +96,7 @@ struct GemmArgs {
     int relu;
     float *out_f;             // fwd y, bwd-data dx, bwd-weight dw
     uint16_t *out_b;          // fwd y in bf16
-    int64_t k_chunk;          // bwd weight: k range per workgroup
+    int k_chunk;          // bwd weight: k range per workgroup
     // bwd data, one parity class: rows are the input pixels (iy, ix) with
     // iy = cy, ix = cx (mod stride), hq x wq of them per image; only taps
     // ky = ky0, kx = kx0 (mod stride) reach them, nkx of them along x
@@ -104,10 +104,10 @@ struct GemmArgs {
 };
 
 // Input pixel of class row m (input gradient).
-__device__ inline int64_t cls_pixel(const GemmArgs &g, int64_t m) {
+__device__ inline int cls_pixel(const GemmArgs &g, int m) {
     if (g.S.s == 1) return m;                   // one class: every pixel
-    const int64_t hw = (int64_t)g.hq * g.wq;
-    const int64_t b = m / hw;
+    const int hw = (int)g.hq * g.wq;
+    const int b = m / hw;
     const int rem = (int)(m - b * hw);
     const int qy = rem / g.wq, qx = rem - (rem / g.wq) * g.wq;
     return (b * g.S.h + qy * g.S.s + g.cy) * g.S.w + qx * g.S.s + g.cx;
@@ -127,8 +127,8 @@ __device__ inline void set_class(GemmArgs &g, int z) {
     const int nky = g.ky0 < S.r ? (S.r - g.ky0 + st - 1) / st : 0;
     const int nkx = g.kx0 < S.r ? (S.r - g.kx0 + st - 1) / st : 0;
     g.nkx = nkx > 0 ? nkx : 1;                  // no taps: K = 0, the class gets zeros
-    g.M = (int64_t)S.n * g.hq * g.wq;
-    g.K = (int64_t)nky * nkx * S.k;
+    g.M = (int)S.n * g.hq * g.wq;
+    g.K = (int)nky * nkx * S.k;
 }
 
 // Filter tap of the class's j-th (ky, kx) pair (input gradient).
@@ -138,26 +138,51 @@ __device__ inline int cls_tap(const GemmArgs &g, int j) {
     return (g.ky0 + a * g.S.s) * g.S.r + g.kx0 + b * g.S.s;
 }
 
-// A[m][k .. k+7] and B[k .. k+7][n] for each mode (zeros outside the GEMM).
+// Operand slices travel in two halves so that one k step's loads are in
+// flight while the previous step multiplies: fetch_* issues the global loads
+// into 8 raw 32-bit registers per thread, put_tiles converts them to BF16 and
+// writes LDS after the next barrier.  Raw forms: BF16 vector (4 words of 2
+// elements), FP32 (8 float bit patterns, rounded at put), BF16 element (8
+// zero-extended halves).
+enum RawKind { kRawBf16Vec = 0, kRawF32 = 1, kRawBf16 = 2 };
+
+__device__ inline void raw_to_bf16(int kind, const uint32_t (&r)[8], uint16_t (&v)[8]) {
+    if (kind == kRawBf16Vec) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = (uint16_t)r[i];
+            v[2 * i + 1] = (uint16_t)(r[i] >> 16);
+        }
+    } else if (kind == kRawF32) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = f_to_bf(__uint_as_float(r[j]));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (uint16_t)r[j];
+    }
+}
+
+// A[m][k .. k+7] and B[k .. k+7][n] for each mode, element by element (zeros
+// outside the GEMM); FP32 output gradients stay FP32 (raw) until put.
 template <int MODE>
-__device__ inline void gather_a(const GemmArgs &g, int64_t m, int64_t k0, int64_t kend,
-                                uint16_t (&v)[8]) {
+__device__ inline void gather_a(const GemmArgs &g, int m, int k0, int kend,
+                                uint32_t (&v)[8]) {
     const Shape &S = g.S;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int64_t k = k0 + j;
-        uint16_t u = 0;
+        const int k = k0 + j;
+        uint32_t u = 0;
         if (m < g.M && k < kend) {
             if (MODE == kFwd) {
-                const int tap = (int)(k / S.c), ci = (int)(k - (int64_t)tap * S.c);
-                const int64_t px = in_pixel(S, m, tap);
+                const int tap = (int)(k / S.c), ci = (int)(k - (int)tap * S.c);
+                const int px = in_pixel(S, m, tap);
                 if (px >= 0) u = g.x[px * S.c + ci];
             } else if (MODE == kBwdData) {
-                const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
-                const int64_t px = out_pixel(S, cls_pixel(g, m), cls_tap(g, j));
-                if (px >= 0) u = f_to_bf(g.dy[px * S.k + co]);
+                const int j = (int)(k / S.k), co = (int)(k - (int)j * S.k);
+                const int px = out_pixel(S, cls_pixel(g, m), cls_tap(g, j));
+                if (px >= 0) u = __float_as_uint(g.dy[px * S.k + co]);
             } else {   // m = out channel, k = output pixel
-                u = f_to_bf(g.dy[k * S.k + m]);
+                u = __float_as_uint(g.dy[k * S.k + m]);
             }
         }
         v[j] = u;
@@ -165,23 +190,23 @@ __device__ inline void gather_a(const GemmArgs &g, int64_t m, int64_t k0, int64_
 }
 
 template <int MODE>
-__device__ inline void gather_b(const GemmArgs &g, int64_t n, int64_t k0, int64_t kend,
-                                uint16_t (&v)[8]) {
+__device__ inline void gather_b(const GemmArgs &g, int n, int k0, int kend,
+                                uint32_t (&v)[8]) {
     const Shape &S = g.S;
-    const int64_t kf = (int64_t)S.r * S.r * S.c;     // filter length per output channel
+    const int kf = (int)S.r * S.r * S.c;     // filter length per output channel
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int64_t k = k0 + j;
-        uint16_t u = 0;
+        const int k = k0 + j;
+        uint32_t u = 0;
         if (n < g.N && k < kend) {
             if (MODE == kFwd) {
                 u = g.w[n * kf + k];
             } else if (MODE == kBwdData) {        // n = in channel, k = (tap, out channel)
-                const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
-                u = g.w[(int64_t)co * kf + (int64_t)cls_tap(g, j) * S.c + n];
+                const int j = (int)(k / S.k), co = (int)(k - (int)j * S.k);
+                u = g.w[(int)co * kf + (int)cls_tap(g, j) * S.c + n];
             } else {                              // n = (tap, in channel), k = output pixel
-                const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
-                const int64_t px = in_pixel(S, k, tap);
+                const int tap = (int)(n / S.c), ci = (int)(n - (int)tap * S.c);
+                const int px = in_pixel(S, k, tap);
                 if (px >= 0) u = g.x[px * S.c + ci];
             }
         }
@@ -194,16 +219,16 @@ __device__ inline void gather_b(const GemmArgs &g, int64_t n, int64_t k0, int64_
 // k .. k+7 read through the tap of n.  The output pixels are consecutive, so
 // the first one's (image, row, column) is divided out once and the others
 // follow by stepping along the row (gather_b's element path divides for each).
-__device__ inline void gather_b_wgrad(const GemmArgs &g, int64_t n, int64_t k0, int64_t kend,
-                                      uint16_t (&v)[8]) {
+__device__ inline void gather_b_wgrad(const GemmArgs &g, int n, int k0, int kend,
+                                      uint32_t (&v)[8]) {
     const Shape &S = g.S;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = 0;
     if (n >= g.N || k0 >= kend) return;
-    const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
+    const int tap = (int)(n / S.c), ci = (int)(n - (int)tap * S.c);
     const int ky = tap / S.r, kx = tap - (tap / S.r) * S.r;
-    const int64_t hw = (int64_t)S.ho * S.wo;
-    int64_t b = k0 / hw;
+    const int hw = (int)S.ho * S.wo;
+    int b = k0 / hw;
     const int rem = (int)(k0 - b * hw);
     int oy = rem / S.wo, ox = rem - (rem / S.wo) * S.wo;
 #pragma unroll
@@ -223,95 +248,113 @@ __device__ inline void gather_b_wgrad(const GemmArgs &g, int64_t n, int64_t k0, 
     }
 }
 
-// 8 bf16 from a 16-byte aligned address, or zeros.
-__device__ inline void load8_bf16(const uint16_t *p, bool ok, uint16_t (&v)[8]) {
+// 8 bf16 from a 16-byte aligned address (4 raw words), or zeros.
+__device__ inline void fetch8_bf16(const uint16_t *p, bool ok, uint32_t (&r)[8]) {
     uint4 q = make_uint4(0, 0, 0, 0);
     if (ok) q = *reinterpret_cast<const uint4 *>(p);
-    v[0] = (uint16_t)q.x; v[1] = (uint16_t)(q.x >> 16);
-    v[2] = (uint16_t)q.y; v[3] = (uint16_t)(q.y >> 16);
-    v[4] = (uint16_t)q.z; v[5] = (uint16_t)(q.z >> 16);
-    v[6] = (uint16_t)q.w; v[7] = (uint16_t)(q.w >> 16);
+    r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
+    r[4] = r[5] = r[6] = r[7] = 0;
 }
 
-// 8 floats from a 32-byte aligned address rounded to bf16, or zeros.
-__device__ inline void load8_f32(const float *p, bool ok, uint16_t (&v)[8]) {
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+// 8 floats from a 32-byte aligned address (raw bits), or zeros.
+__device__ inline void fetch8_f32(const float *p, bool ok, uint32_t (&r)[8]) {
+    uint4 a = make_uint4(0, 0, 0, 0), b = a;
     if (ok) {
-        a = reinterpret_cast<const float4 *>(p)[0];
-        b = reinterpret_cast<const float4 *>(p)[1];
+        a = reinterpret_cast<const uint4 *>(p)[0];
+        b = reinterpret_cast<const uint4 *>(p)[1];
     }
-    v[0] = f_to_bf(a.x); v[1] = f_to_bf(a.y); v[2] = f_to_bf(a.z); v[3] = f_to_bf(a.w);
-    v[4] = f_to_bf(b.x); v[5] = f_to_bf(b.y); v[6] = f_to_bf(b.z); v[7] = f_to_bf(b.w);
+    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
+    r[4] = b.x; r[5] = b.y; r[6] = b.z; r[7] = b.w;
 }
 
-// Operand slices of one k step into LDS (k contiguous in sA[m][.], sB[n][.]).
-// VA / VB: the operand's contiguous dimension holds whole groups of 8, so a
-// thread moves 8 neighbours with one vector load: along k for operands stored
-// k-contiguous (forward input and filters, input-gradient output gradients),
-// along m or n otherwise (written transposed).  Else the element gather.
+// How each operand of a mode moves.  VA / VB: the operand's contiguous
+// dimension holds whole groups of 8, so a thread moves 8 neighbours with one
+// vector load: along k for operands stored k-contiguous (forward input and
+// filters, input-gradient output gradients), along m or n otherwise (written
+// transposed, "mn-major").  Else the element gather, k-major.
+template <int MODE, bool VA>
+struct OpA {
+    static constexpr bool kMn = MODE == kBwdWeight && VA;
+    static constexpr int kKind = (MODE == kFwd) ? (VA ? kRawBf16Vec : kRawBf16) : kRawF32;
+};
+template <int MODE, bool VB>
+struct OpB {
+    static constexpr bool kMn = (MODE == kBwdData || MODE == kBwdWeight) && VB;
+    static constexpr int kKind = VB ? kRawBf16Vec : kRawBf16;
+};
+
+// Global loads of one k step's slices into registers.
 template <int MODE, bool VA, bool VB>
-__device__ inline void load_tiles(const GemmArgs &g, int64_t m0, int64_t n0, int64_t k0,
-                                  int64_t kend, uint16_t (*sA)[kLdsK], uint16_t (*sB)[kLdsK]) {
+__device__ inline void fetch_tiles(const GemmArgs &g, int m0, int n0, int k0,
+                                   int kend, uint32_t (&ra)[8], uint32_t (&rb)[8]) {
     const Shape &S = g.S;
     const int t = threadIdx.x;
     const int lrow = t >> 2, lk = (t & 3) * 8;          // k-major slot: row, 8 k
     const int tk = t >> 3, tc = (t & 7) * 8;            // mn-major slot: k, 8 rows
-    const int64_t kf = (int64_t)S.r * S.r * S.c;
-    uint16_t v[8];
+    const int kf = (int)S.r * S.r * S.c;
     // ---- A ----
     if (MODE == kFwd && VA) {
-        const int64_t m = m0 + lrow, k = k0 + lk;
-        const int tap = (int)(k / S.c), ci = (int)(k - (int64_t)tap * S.c);
-        const int64_t px = (m < g.M && k < kend) ? in_pixel(S, m, tap) : -1;
-        load8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+        const int m = m0 + lrow, k = k0 + lk;
+        const int tap = (int)(k / S.c), ci = (int)(k - (int)tap * S.c);
+        const int px = (m < g.M && k < kend) ? in_pixel(S, m, tap) : -1;
+        fetch8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, ra);
     } else if (MODE == kBwdData && VA) {
-        const int64_t m = m0 + lrow, k = k0 + lk;
-        const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
-        const int64_t px =
+        const int m = m0 + lrow, k = k0 + lk;
+        const int j = (int)(k / S.k), co = (int)(k - (int)j * S.k);
+        const int px =
             (m < g.M && k < kend) ? out_pixel(S, cls_pixel(g, m), cls_tap(g, j)) : -1;
-        load8_f32(g.dy + (px >= 0 ? px * S.k + co : 0), px >= 0, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+        fetch8_f32(g.dy + (px >= 0 ? px * S.k + co : 0), px >= 0, ra);
     } else if (MODE == kBwdWeight && VA) {              // A[co][pixel] = dy[pixel][co]
-        const int64_t k = k0 + tk, m = m0 + tc;
+        const int k = k0 + tk, m = m0 + tc;
         const bool ok = k < kend && m < g.M;
-        load8_f32(g.dy + (ok ? k * S.k + m : 0), ok, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sA[tc + j][tk] = v[j];
+        fetch8_f32(g.dy + (ok ? k * S.k + m : 0), ok, ra);
     } else {
-        gather_a<MODE>(g, m0 + lrow, k0 + lk, kend, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+        gather_a<MODE>(g, m0 + lrow, k0 + lk, kend, ra);
     }
     // ---- B ----
     if (MODE == kFwd && VB) {
-        const int64_t n = n0 + lrow, k = k0 + lk;
+        const int n = n0 + lrow, k = k0 + lk;
         const bool ok = n < g.N && k < kend;
-        load8_bf16(g.w + (ok ? n * kf + k : 0), ok, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
+        fetch8_bf16(g.w + (ok ? n * kf + k : 0), ok, rb);
     } else if (MODE == kBwdData && VB) {                // B[(tap, co)][ci] = w[co][tap][ci]
-        const int64_t k = k0 + tk, n = n0 + tc;
-        const int j = (int)(k / S.k), co = (int)(k - (int64_t)j * S.k);
+        const int k = k0 + tk, n = n0 + tc;
+        const int j = (int)(k / S.k), co = (int)(k - (int)j * S.k);
         const bool ok = k < kend && n < g.N;
-        load8_bf16(g.w + (ok ? (int64_t)co * kf + (int64_t)cls_tap(g, j) * S.c + n : 0), ok, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sB[tc + j][tk] = v[j];
+        fetch8_bf16(g.w + (ok ? (int)co * kf + (int)cls_tap(g, j) * S.c + n : 0), ok, rb);
     } else if (MODE == kBwdWeight && VB) {              // B[pixel][(tap, ci)] = x[shifted pixel][ci]
-        const int64_t k = k0 + tk, n = n0 + tc;
-        const int tap = (int)(n / S.c), ci = (int)(n - (int64_t)tap * S.c);
-        const int64_t px = (k < kend && n < g.N) ? in_pixel(S, k, tap) : -1;
-        load8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, v);
+        const int k = k0 + tk, n = n0 + tc;
+        const int tap = (int)(n / S.c), ci = (int)(n - (int)tap * S.c);
+        const int px = (k < kend && n < g.N) ? in_pixel(S, k, tap) : -1;
+        fetch8_bf16(g.x + (px >= 0 ? px * S.c + ci : 0), px >= 0, rb);
+    } else if (MODE == kBwdWeight) {
+        gather_b_wgrad(g, n0 + lrow, k0 + lk, kend, rb);
+    } else {
+        gather_b<MODE>(g, n0 + lrow, k0 + lk, kend, rb);
+    }
+}
+
+// The fetched slices, rounded to BF16, into LDS (k contiguous in sA[m][.],
+// sB[n][.]).
+template <int MODE, bool VA, bool VB>
+__device__ inline void put_tiles(const uint32_t (&ra)[8], const uint32_t (&rb)[8],
+                                 uint16_t (*sA)[kLdsK], uint16_t (*sB)[kLdsK]) {
+    const int t = threadIdx.x;
+    const int lrow = t >> 2, lk = (t & 3) * 8;
+    const int tk = t >> 3, tc = (t & 7) * 8;
+    uint16_t v[8];
+    raw_to_bf16(OpA<MODE, VA>::kKind, ra, v);
+    if (OpA<MODE, VA>::kMn) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[tc + j][tk] = v[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[lrow][lk + j] = v[j];
+    }
+    raw_to_bf16(OpB<MODE, VB>::kKind, rb, v);
+    if (OpB<MODE, VB>::kMn) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) sB[tc + j][tk] = v[j];
-    } else if (MODE == kBwdWeight) {
-        gather_b_wgrad(g, n0 + lrow, k0 + lk, kend, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
     } else {
-        gather_b<MODE>(g, n0 + lrow, k0 + lk, kend, v);
 #pragma unroll
         for (int j = 0; j < 8; ++j) sB[lrow][lk + j] = v[j];
     }
@@ -324,11 +367,11 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs args) {
     GemmArgs g = args;
     if (MODE == kBwdData) set_class(g, (int)blockIdx.z);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * kBN;
+    const int m0 = (int)blockIdx.x * kBM, n0 = (int)blockIdx.y * kBN;
     if (m0 >= g.M) return;                            // this class has fewer rows
-    int64_t kbeg = 0, kend = g.K;
+    int kbeg = 0, kend = g.K;
     if (MODE == kBwdWeight) {
-        kbeg = (int64_t)blockIdx.z * g.k_chunk;
+        kbeg = (int)blockIdx.z * g.k_chunk;
         kend = kbeg + g.k_chunk < g.K ? kbeg + g.k_chunk : g.K;
     }
     const int wm = wave >> 1, wn = wave & 1;
@@ -337,10 +380,15 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs args) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+    uint32_t ra[8], rb[8];
+    fetch_tiles<MODE, VA, VB>(g, m0, n0, kbeg, kend, ra, rb);
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
         __syncthreads();                              // previous step's reads are done
-        load_tiles<MODE, VA, VB>(g, m0, n0, k0, kend, sA, sB);
+        put_tiles<MODE, VA, VB>(ra, rb, sA, sB);
         __syncthreads();
+        // the next step's loads fly while this one multiplies (past kend
+        // they are masked off and give zeros)
+        fetch_tiles<MODE, VA, VB>(g, m0, n0, k0 + kBK, kend, ra, rb);
         const int r16 = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -364,8 +412,8 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs args) {
         for (int jn = 0; jn < 2; ++jn)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t m = m0 + wm * 32 + i * 16 + rq + e;
-                const int64_t n = n0 + wn * 32 + jn * 16 + col;
+                const int m = m0 + wm * 32 + i * 16 + rq + e;
+                const int n = n0 + wn * 32 + jn * 16 + col;
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][jn][e];
                 if (MODE == kFwd) {
@@ -374,7 +422,7 @@ __global__ __launch_bounds__(256) void k_igemm(GemmArgs args) {
                     if (g.out_f) g.out_f[m * g.N + n] = v;
                     if (g.out_b) g.out_b[m * g.N + n] = f_to_bf(v);
                 } else if (MODE == kBwdData) {
-                    const int64_t px = cls_pixel(g, m);
+                    const int px = cls_pixel(g, m);
                     if (g.mask && !(bf_to_f(g.mask[px * g.N + n]) > 0.f)) v = 0.f;
                     g.out_f[px * g.N + n] = v;
                 } else {
@@ -799,7 +847,7 @@ bz_status bz_conv_shape(bz_conv *cv) {
     if ((int64_t)cv->h + 2 * cv->pad < cv->r || (int64_t)cv->w + 2 * cv->pad < cv->r || ho < 1 ||
         wo < 1)
         return BZ_ERR_ARG;
-    const int64_t lim = int64_t(1) << 31;
+    const int64_t lim = int64_t(1) << 30;      // index arithmetic stays in 32 bits
     if ((int64_t)cv->n * cv->h * cv->w * cv->c >= lim || (int64_t)cv->n * ho * wo * cv->k >= lim ||
         (int64_t)cv->k * cv->r * cv->r * cv->c >= lim)
         return BZ_ERR_UNSUPPORTED;

@@ -308,6 +308,11 @@ def test_conv_shape_validation():
         assert lib.bz_conv_shape(C.byref(cnn.ConvDesc(*bad, 0, 0))) == bz.BZ_ERR_ARG, bad
     big = cnn.ConvDesc(1 << 15, 256, 256, 64, 64, 3, 1, 1, 0, 0)
     assert lib.bz_conv_shape(C.byref(big)) == bz.BZ_ERR_UNSUPPORTED
+    # tensors stay below 2^30 elements (32-bit index arithmetic in the kernels)
+    edge = cnn.ConvDesc(1 << 14, 256, 256, 1, 1, 1, 1, 0, 0, 0)
+    assert lib.bz_conv_shape(C.byref(edge)) == bz.BZ_ERR_UNSUPPORTED
+    below = cnn.ConvDesc((1 << 14) - 1, 256, 256, 1, 1, 1, 1, 0, 0, 0)
+    assert lib.bz_conv_shape(C.byref(below)) == bz.BZ_OK
     # a descriptor whose output size was not set by bz_conv_shape is rejected
     d2 = cnn.ConvDesc(2, 32, 32, 3, 64, 3, 2, 1, 15, 16)
     assert lib.bz_conv_fwd(C.byref(d2), 1, 1, None, 0, 1, None, None) == bz.BZ_ERR_ARG

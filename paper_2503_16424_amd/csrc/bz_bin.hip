@@ -588,8 +588,9 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 // workgroup).  The pairs are generated as in k_emit: (Gaussian, row) items,
 // kRowChunk at a time, each row's span by support_row (the count's function
 // of the same record bits), and consecutive lanes on consecutive pairs of the
-// chunk (Gaussian-major, i.e. draw order), each finding its row by binary
-// search.  A pair's place inside its bucket is the wave's running count of
+// chunk (Gaussian-major, i.e. draw order), each finding its row by counting
+// the marked first pairs of the rows at or before it (a bitmap per chunk; a
+// binary search in chunks of more than kStartBits pairs).  A pair's place inside its bucket is the wave's running count of
 // that bucket (LDS) plus the lanes of the round before it with the same
 // bucket, found with one ballot per bit of the bucket's index relative to the
 // block's first bucket (as the radix scatter ranks digits); so each bucket
@@ -601,6 +602,7 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 // are dealt to the XCDs in contiguous runs (the dispatcher sends workgroup w to
 // XCD w % 8): the parts meet in one L2.
 constexpr int kEmitWaves = 1;
+constexpr int kStartBits = 2048;   // pairs of a chunk whose rows a bitmap marks
 
 __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     const float4 *__restrict__ rec, const ushort4 *__restrict__ rects, int64_t n, int W, int H,
@@ -616,6 +618,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     __shared__ uint32_t s_item_off[kEmitWaves][kRowChunk + 1];
     __shared__ uint32_t s_item_key[kEmitWaves][kRowChunk];
     __shared__ uint8_t s_item_g[kEmitWaves][kRowChunk];
+    __shared__ __align__(8) uint32_t s_start[kEmitWaves][kStartBits / 32];
     __shared__ uint32_t s_base[kEmitWaves][256], s_cnt[kEmitWaves][256], s_run[kEmitWaves][256];
     if (status[1] & Status::kOverflow) return;
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -671,12 +674,14 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     const int th_ = th;
     for (uint32_t c0 = 0; c0 < nrows; c0 += kRowChunk) {
         const uint32_t ci = nrows - c0 < (uint32_t)kRowChunk ? nrows - c0 : (uint32_t)kRowChunk;
-        uint32_t wsum = 0;
-        uint32_t wid[kRowChunk / 64];
+        uint32_t wsum = 0, nzc = 0;
+        uint32_t wid[kRowChunk / 64], ikey[kRowChunk / 64], ig[kRowChunk / 64];
 #pragma unroll
         for (int j = 0; j < kRowChunk / 64; ++j) {
             const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
             wid[j] = 0;
+            ikey[j] = 0;
+            ig[j] = 0;
             if (it < ci) {
                 const uint32_t r = c0 + it;
                 // last Gaussian whose first row <= r (lanes past nb hold
@@ -689,34 +694,61 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
                 int cl, ch;
                 support_row(s_sup[wv][lo], (int)s_ty0[wv][lo] + dr, th_, inv_tw, cl, ch);
                 wid[j] = ch >= cl ? (uint32_t)(ch - cl + 1) : 0u;
-                s_item_key[wv][it] = s_key0[wv][lo] + (uint32_t)dr * (uint32_t)s_tx[wv][lo] + (uint32_t)cl;
-                s_item_g[wv][it] = (uint8_t)lo;
+                ikey[j] = s_key0[wv][lo] + (uint32_t)dr * (uint32_t)s_tx[wv][lo] + (uint32_t)cl;
+                ig[j] = (uint32_t)lo;
                 wsum += wid[j];
+                nzc += wid[j] != 0u;
             }
         }
-        uint32_t cnt;
+        uint32_t cnt, nnz;
         uint32_t ex = wave_excl_scan(wsum, cnt);
+        uint32_t rk = wave_excl_scan(nzc, nnz);
+        // Rows with pairs, compacted in order (rank rk): their first key,
+        // Gaussian and first pair.  A chunk of at most kStartBits pairs also
+        // marks each such row's first pair in a bitmap, so a pair's row is
+        // the number of marks at or before it, minus one; longer chunks
+        // binary-search the first pairs.
+        const bool use_bits = cnt <= (uint32_t)kStartBits;
+        const uint32_t nwords = 2 * ((cnt + 63) / 64);
+        if (use_bits)
+            for (uint32_t q = t; q < nwords; q += 64) s_start[wv][q] = 0u;
+        wave_lds_fence();
 #pragma unroll
         for (int j = 0; j < kRowChunk / 64; ++j) {
-            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
-            if (it < ci) s_item_off[wv][it] = ex;
+            if (wid[j] != 0u) {
+                s_item_key[wv][rk] = ikey[j];
+                s_item_g[wv][rk] = (uint8_t)ig[j];
+                s_item_off[wv][rk] = ex;
+                if (use_bits) atomicOr(&s_start[wv][ex >> 5], 1u << (ex & 31));
+                ++rk;
+            }
             ex += wid[j];
         }
         // the slots past the chunk's last row hold cnt (> every pair index),
         // so the pair search below needs no bound
-        for (uint32_t it = ci + t; it <= (uint32_t)kRowChunk; it += 64) s_item_off[wv][it] = cnt;
+        for (uint32_t it = nnz + t; it <= (uint32_t)kRowChunk; it += 64) s_item_off[wv][it] = cnt;
         if (c0 == 0) fetch_parts();
         wave_lds_fence();
         // rounds of 64 consecutive pairs of the chunk, one per lane
+        uint32_t seen = 0;                 // row marks before the round
         for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
             const uint32_t i = r0 + (uint32_t)t;
             const bool valid = i < cnt;
-            uint32_t key = 0, gl = 0;
-            if (valid) {
-                int lo = 0;                    // last row item whose offset <= i
+            int lo = 0;                        // row of pair i (compacted)
+            if (use_bits) {
+                // marks of pairs r0 .. r0 + 63 (words past the chunk are zero)
+                const uint64_t m = *reinterpret_cast<const uint64_t *>(&s_start[wv][r0 >> 5]);
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                lo = (int)(seen + below + (uint32_t)((m >> t) & 1ull)) - 1;
+                seen += (uint32_t)__popcll(m);
+            } else {
 #pragma unroll
                 for (int step = kRowChunk / 2; step >= 1; step >>= 1)
                     if (s_item_off[wv][lo + step] <= i) lo += step;
+            }
+            uint32_t key = 0, gl = 0;
+            if (valid) {
                 key = s_item_key[wv][lo] + (i - s_item_off[wv][lo]);
                 gl = s_item_g[wv][lo];
             }

@@ -930,8 +930,10 @@ __global__ void k_zero(float *p, int64_t n) {
 // it (the exact inverse of the stencil's index rules), so no atomics are
 // needed and the result is deterministic.  The sample-point gradients then go
 // to the control points: X[r][k] = sum_j B_j(t_k) ((1-tau_r) A_{3s+j} + tau_r B_{3s+j}).
-// Sample points and their differences are double precision (coordinates of
-// thousands of pixels, differences of a pixel); the chain itself is float.
+// The boundary samples are evaluated in double precision (coordinates of
+// thousands of pixels) and only their differences along each boundary and
+// from boundary A to B are kept, rounded to float (differences of a pixel):
+// a row's differences are blends of those, and the chain itself is float.
 //
 // NT threads per curve.  Two launches split the curves by size: those of at
 // most kSmallCurve Gaussians (open strokes) run as one-wave workgroups with
@@ -957,8 +959,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int lane = threadIdx.x;          // thread of the curve's workgroup
     CurveView v = load_curve_view(c, p);
     stage_tau(v, s_tau, lane, NT);
-    double2 *XA = lds_xy;
-    double2 *XB = lds_xy + lk;
+    // [K] column differences of the boundary samples: DA[k] = XA[k+1] - XA[k],
+    // DB[k] likewise, and W[k] = XB[k] - XA[k] (closed), in the boundary
+    // samples' space (2 x double2 per column)
+    float2 *DA = reinterpret_cast<float2 *>(lds_xy);
+    float2 *DB = DA + lk;
+    float2 *Wd = DB + lk;
     float4 *Bw = reinterpret_cast<float4 *>(lds_xy + 2 * lk);          // [K] Bernstein weights
     int *Bs = reinterpret_cast<int *>(Bw + lk);                        // [K] segment of column k
     float2 *Tm = reinterpret_cast<float2 *>(reinterpret_cast<char *>(lds_xy) +
@@ -967,7 +973,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     float2 *Th = Tf + lg;                                              // across-row term
     float2 *Tv = Th + lg;                                              // tangent term
     float2 *Xbar = Tm;                                                 // [rows*K]
-    boundary_samples(v, XA, XB, lane, NT);
+    const bool closed = v.kind == BZ_CLOSED;
     for (int k = lane; k < v.K; k += NT) {
         int s;
         double t, B[4];
@@ -975,6 +981,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         bernstein3(t, B);
         Bw[k] = make_float4((float)B[0], (float)B[1], (float)B[2], (float)B[3]);
         Bs[k] = s;
+        // samples k and k + 1 of each boundary in double precision; their
+        // differences rounded once
+        const double2 a0 = boundary_point(v, false, k);
+        const double2 a1 = k + 1 < v.K ? boundary_point(v, false, k + 1) : a0;
+        DA[k] = make_float2((float)(a1.x - a0.x), (float)(a1.y - a0.y));
+        if (closed) {
+            const double2 b0 = boundary_point(v, true, k);
+            const double2 b1 = k + 1 < v.K ? boundary_point(v, true, k + 1) : b0;
+            DB[k] = make_float2((float)(b1.x - b0.x), (float)(b1.y - b0.y));
+            Wd[k] = make_float2((float)(b0.x - a0.x), (float)(b0.y - a0.y));
+        }
     }
     const int n = v.rows * v.K;
     __syncthreads();
@@ -982,7 +999,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     float wbar = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
     float ob[kMaxSeg] = {0.f, 0.f, 0.f, 0.f};
     const float rho2f = (float)inv_rho2;
-    const bool closed = v.kind == BZ_CLOSED;
     const int K = v.K, R1 = v.R + 1;
     // (r, k) of idx = lane + i*NT advance by (NT / K, NT % K) per pass.
     const int rstep = NT / K, kstep = NT - rstep * K;
@@ -991,28 +1007,44 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         float dg[kGradPlanes];
 #pragma unroll
         for (int q = 0; q < kGradPlanes; ++q) dg[q] = d_gauss[q * ng + v.g0 + idx];
-        // stencil (Eq. sigma with nearest-neighbour ends, Eq. rotation)
-        const int ka = k < K - 1 ? k + 1 : K - 1, kb = k < K - 1 ? k : K - 2;
-        const int kp = k + 1 < K ? k + 1 : K - 1, km = k > 0 ? k - 1 : 0;
-        const double2 Xa = sample_at(v, XA, XB, r, ka), Xb = sample_at(v, XA, XB, r, kb);
-        const double2 Xp = sample_at(v, XA, XB, r, kp), Xm = sample_at(v, XA, XB, r, km);
-        const float dax = (float)(Xa.x - Xb.x), day = (float)(Xa.y - Xb.y);
-        const float vx = (float)(Xp.x - Xm.x), vy = (float)(Xp.y - Xm.y);
-        const float sx2 = (dax * dax + day * day) * rho2f + (float)s0;
+        // stencil (Eq. sigma with nearest-neighbour ends, Eq. rotation).  Row
+        // r's samples are (1 - tau_r) XA + tau_r XB, so its differences along
+        // the row are the same blend of DA and DB, and across rows
+        // (tau_ra - tau_rb) W.
+        const int kb = k < K - 1 ? k : K - 2;              // ka = kb + 1
+        const int km = k > 0 ? k - 1 : 0;                  // kp = km + 1 or km + 2
+        const bool two = k > 0 && k < K - 1;
+        const float tr = closed ? v.tau[r] : 0.f, t1 = 1.f - tr;
+        float dax = DA[kb].x, day = DA[kb].y;
+        float vx = DA[km].x, vy = DA[km].y;
+        if (two) {
+            vx += DA[km + 1].x;
+            vy += DA[km + 1].y;
+        }
         float dyx = 0.f, dyy = 0.f, sy2;
         if (closed) {
+            float bx = DB[km].x, by = DB[km].y;
+            if (two) {
+                bx += DB[km + 1].x;
+                by += DB[km + 1].y;
+            }
+            vx = fmaf(tr, bx, t1 * vx);
+            vy = fmaf(tr, by, t1 * vy);
+            dax = fmaf(tr, DB[kb].x, t1 * dax);
+            day = fmaf(tr, DB[kb].y, t1 * day);
             const int ra = r < R1 ? r + 1 : R1, rb = r < R1 ? r : R1 - 1;
-            const double2 Ya = sample_at(v, XA, XB, ra, k), Yb = sample_at(v, XA, XB, rb, k);
-            dyx = (float)(Ya.x - Yb.x);
-            dyy = (float)(Ya.y - Yb.y);
+            const float dt = v.tau[ra] - v.tau[rb];
+            dyx = dt * Wd[k].x;
+            dyy = dt * Wd[k].y;
             sy2 = (dyx * dyx + dyy * dyy) * rho2f + (float)s0;
         } else {
             sy2 = v.width * v.width + (float)s0;
         }
+        const float sx2 = (dax * dax + day * day) * rho2f + (float)s0;
         const float nv2 = vx * vx + vy * vy;
         const float inv_nv = nv2 > 0.f ? __frsqrt_rn(nv2) : 0.f;
         const float cs = nv2 > 0.f ? vx * inv_nv : 1.f, sn = nv2 > 0.f ? vy * inv_nv : 0.f;
-        const float ia = 1.f / sx2, ib = 1.f / sy2;
+        const float ia = __builtin_amdgcn_rcpf(sx2), ib = __builtin_amdgcn_rcpf(sy2);
         const float qxx = dg[2], qxy = dg[3], qyy = dg[4];
         const float abar = qxx * cs * cs + qxy * cs * sn + qyy * sn * sn;
         const float bbar = qxx * sn * sn - qxy * cs * sn + qyy * cs * cs;

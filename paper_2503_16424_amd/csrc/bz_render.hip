@@ -288,6 +288,24 @@ __device__ inline float uniform_f32(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// A staged record as three 16-byte LDS reads (the compiler splits the read
+// around fields the sweep leaves unused, five LDS instructions), waited for
+// in the same block.  p is a pointer into LDS: the low 32 bits of its flat
+// address are its LDS offset.  The outputs are early-clobber: the address
+// register must not be shared with a destination while later reads use it.
+__device__ inline Staged read_staged(const Staged *p) {
+    const uint32_t off = (uint32_t)(uintptr_t)p;
+    float4 m, q, c;
+    asm volatile("ds_read_b128 %0, %3\n\t"
+                 "ds_read_b128 %1, %3 offset:16\n\t"
+                 "ds_read_b128 %2, %3 offset:32\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(m), "=&v"(q), "=&v"(c)       // early clobber: off is read by all three
+                 : "v"(off)
+                 : "memory");
+    return Staged{m, q, c};
+}
+
 // Result of a front-to-back sweep for one pixel.
 struct Sweep {
     float T, C0, C1, C2;   // transmittance after the last contributor, colour sum
@@ -334,7 +352,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
         while (mask) {
             const int b = __builtin_ctzll(mask);
             clear_bit(mask, b);
-            const Staged st = my[b];
+            const Staged st = read_staged(my + b);
             const float G = __builtin_amdgcn_exp2f(-exponent2_sweep(st, lx, ly));
             // contributors: inside the support and not stopped, as a lane mask
             const uint64_t cm = __builtin_amdgcn_ballot_w64(G > g_min) & ~stopped;
@@ -789,7 +807,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                 if (mask != 0) {
                     const int b = 63 - __builtin_clzll(mask);
                     clear_bit(mask, b);
-                    const Staged st = my[b];
+                    const Staged st = read_staged(my + b);
                     const uint32_t pos = lo + (uint32_t)b;
                     const float dx = cx - st.m.x;
                     const float dy = cy - st.m.y;

@@ -347,7 +347,9 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
             my[lane] = st;
         }
         uint64_t mask = __ballot(hit);
-        uint64_t vbits = 0;
+        // the batch's entries that change a pixel: every hit, less the
+        // (rarer) ones that change none
+        uint64_t vbits = mask;
         wave_lds_sync();
         while (mask) {
             const int b = __builtin_ctzll(mask);
@@ -369,7 +371,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
                 _Pragma("clang fp contract(off)") r.T = r.T - wgt;
             }
             if (kCount) r.cnt = select_lanes_u32(cm, r.cnt + 1u, r.cnt);
-            if (cm) vbits |= 1ull << b;
+            if (__builtin_expect(cm == 0, 0)) clear_bit(vbits, b);
             const uint64_t now = __builtin_amdgcn_ballot_w64(r.T < tmin);
             if (__builtin_expect(now != stopped, 0)) {     // some pixel stopped here
                 r.last = select_lanes_u32(now & ~stopped, k * 64 + b + 1, r.last);

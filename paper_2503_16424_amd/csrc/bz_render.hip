@@ -290,11 +290,10 @@ __device__ inline float uniform_f32(float v) {
 
 // A staged record as three 16-byte LDS reads (the compiler splits the read
 // around fields the sweep leaves unused, five LDS instructions), waited for
-// in the same block.  p is a pointer into LDS: the low 32 bits of its flat
-// address are its LDS offset.  The outputs are early-clobber: the address
+// in the same block; off is the record's LDS byte offset (the low 32 bits
+// of a flat address into LDS).  The outputs are early-clobber: the address
 // register must not be shared with a destination while later reads use it.
-__device__ inline Staged read_staged(const Staged *p) {
-    const uint32_t off = (uint32_t)(uintptr_t)p;
+__device__ inline Staged read_staged_at(uint32_t off) {
     float4 m, q, c;
     asm volatile("ds_read_b128 %0, %3\n\t"
                  "ds_read_b128 %1, %3 offset:16\n\t"
@@ -304,6 +303,24 @@ __device__ inline Staged read_staged(const Staged *p) {
                  : "v"(off)
                  : "memory");
     return Staged{m, q, c};
+}
+
+// LDS offset of entry b of a wave's staged slice (base: the slice's offset,
+// held in a vector register) as one VALU multiply-add from the scalar index:
+// the compiler's scalar multiply, add and move to a vector register cost two
+// scalar instructions more per visited entry.
+// The slice's offset in a vector register, produced once: an inline-asm
+// value is kept in its register rather than moved back from a scalar one
+// inside the loop.
+__device__ inline uint32_t vector_copy(uint32_t v) {
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+    return r;
+}
+__device__ inline uint32_t staged_off(uint32_t base, int b) {
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, 48, %2" : "=v"(r) : "s"(b), "v"(base));
+    return r;
 }
 
 // Result of a front-to-back sweep for one pixel.
@@ -338,6 +355,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
     const float g_min = a.g_min, amax = a.alpha_max, tmin = a.t_min;
     uint64_t stopped = __builtin_amdgcn_ballot_w64(r.T < tmin);
     uint32_t k = 0, k_used = 0;
+    const uint32_t my_off = vector_copy((uint32_t)(uintptr_t)my);   // LDS offset of the slice
     for (uint32_t base = start; base < end; base += 64, ++k) {
         const uint32_t j = base + lane;
         bool hit = false;
@@ -354,7 +372,7 @@ __device__ inline Sweep fwd_sweep(const TileArgs &a, Staged *my, uint32_t start,
         while (mask) {
             const int b = __builtin_ctzll(mask);
             clear_bit(mask, b);
-            const Staged st = read_staged(my + b);
+            const Staged st = read_staged_at(staged_off(my_off, b));
             const float G = __builtin_amdgcn_exp2f(-exponent2_sweep(st, lx, ly));
             // contributors: inside the support and not stopped, as a lane mask
             const uint64_t cm = __builtin_amdgcn_ballot_w64(G > g_min) & ~stopped;
@@ -685,6 +703,10 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
         s_q0[w][1] = oy;
     }
     Staged *my = s_stage + w * 64;
+    // LDS offset of the slice (the recomputing form, short of registers,
+    // leaves its address arithmetic to the compiler)
+    const uint32_t my_off = kRecompute ? (uint32_t)(uintptr_t)my
+                                       : vector_copy((uint32_t)(uintptr_t)my);
     // Per-tile sums, plane-major [kSums][tab_cap], indexed by tile-list position:
     // the quads of a tile share most of their Gaussians, so their sums meet
     // here and leave the block with one global atomic per (Gaussian, plane).
@@ -809,7 +831,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                 if (mask != 0) {
                     const int b = 63 - __builtin_clzll(mask);
                     clear_bit(mask, b);
-                    const Staged st = read_staged(my + b);
+                    const Staged st = kRecompute ? read_staged_at(my_off + 48u * (uint32_t)b)
+                                                 : read_staged_at(staged_off(my_off, b));
                     const uint32_t pos = lo + (uint32_t)b;
                     const float dx = cx - st.m.x;
                     const float dy = cy - st.m.y;

@@ -790,8 +790,9 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
         int filled = 0;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            if (s == filled) {
-                while (mask == 0 && k > 0) {
+            if (mask == 0) {
+                // the next batch with entries to visit, walking down
+                while (k > 0) {
                     --k;
                     lo = (uint32_t)k * 64;
                     // only entries of this tile's list can be visited
@@ -827,63 +828,65 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                         wave_lds_sync();
                     }
                     mask = vm;
+                    if (mask != 0) break;
                 }
-                if (mask != 0) {
-                    const int b = 63 - __builtin_clzll(mask);
-                    clear_bit(mask, b);
-                    const Staged st = kRecompute ? read_staged_at(my_off + 48u * (uint32_t)b)
-                                                 : read_staged_at(staged_off(my_off, b));
-                    const uint32_t pos = lo + (uint32_t)b;
-                    const float dx = cx - st.m.x;
-                    const float dy = cy - st.m.y;
-                    float u, w;
-                    const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
-                    const bool c = pos < nl && G > g_min;
-                    const float araw = fmaf(st.q.w, G, -st.c.w);
-                    const bool shaped = c && araw <= amax;       // alpha not clamped
-                    const float acl = min_amax(araw, amax);
-                    const float al = c ? acl : 0.f;
-                    const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
-                    const float wgt = al * Tb;
-                    const float cg = fmaf(st.c.x, g0, fmaf(st.c.y, g1, st.c.z * g2));
-                    const float e = cg - Ag;                     // (c - A) . g
-                    const float abar = c ? Tb * e : 0.f;
-                    Ag = fmaf(al, e, Ag);
-                    T = Tb;
-                    const float f = shaped ? abar : 0.f;
-                    // f G and f straight into their moment registers (the
-                    // positions past the table overwrite the first and
-                    // ignore the tenth), so neither needs a copy
-                    acc[kSums * s + 0] = f * G;
-                    acc[kSums * s + 9] = f;
-                    const float fG = acc[kSums * s + 0];
-                    acc[kSums * s + 6] = wgt * g0;
-                    acc[kSums * s + 7] = wgt * g1;
-                    acc[kSums * s + 8] = wgt * g2;
-                    if (pos < (uint32_t)tab_cap) {
-                        // moments about the tile centre (wave-uniform branch)
-                        const float fGx = fG * cx, fGy = fG * cy;
-                        acc[kSums * s + 1] = fGx;
-                        acc[kSums * s + 2] = fGy;
-                        acc[kSums * s + 3] = fGx * cx;
-                        acc[kSums * s + 4] = fGx * cy;
-                        acc[kSums * s + 5] = fGy * cy;
-                    } else {
-                        // the planes without their constant factors (plane_scale)
-                        const float P = fG * st.q.w;             // -dL/dp
-                        const float Pdx = P * dx, Pdy = P * dy;
-                        acc[kSums * s + 0] = P * fmaf(u, st.m.z, -w * st.q.y);
-                        acc[kSums * s + 1] = P * fmaf(u, st.m.w, w * st.q.x);
-                        acc[kSums * s + 2] = Pdx * dx;
-                        acc[kSums * s + 3] = Pdx * dy;
-                        acc[kSums * s + 4] = Pdy * dy;
-                        acc[kSums * s + 5] = fmaf(-g_min, f, fG);    // f (G - g_min)
-                        // acc[kSums * s + 9] is not stored for these
-                        // positions: the reduction sums each index on its own
-                    }
-                    slot_pos[s] = pos;
-                    filled = s + 1;
+                if (mask == 0) break;      // the list is done: the slots from s stay empty
+            }
+            {
+                const int b = 63 - __builtin_clzll(mask);
+                clear_bit(mask, b);
+                const Staged st = kRecompute ? read_staged_at(my_off + 48u * (uint32_t)b)
+                                             : read_staged_at(staged_off(my_off, b));
+                const uint32_t pos = lo + (uint32_t)b;
+                const float dx = cx - st.m.x;
+                const float dy = cy - st.m.y;
+                float u, w;
+                const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
+                const bool c = pos < nl && G > g_min;
+                const float araw = fmaf(st.q.w, G, -st.c.w);
+                const bool shaped = c && araw <= amax;       // alpha not clamped
+                const float acl = min_amax(araw, amax);
+                const float al = c ? acl : 0.f;
+                const float Tb = T * __builtin_amdgcn_rcpf(1.f - al);
+                const float wgt = al * Tb;
+                const float cg = fmaf(st.c.x, g0, fmaf(st.c.y, g1, st.c.z * g2));
+                const float e = cg - Ag;                     // (c - A) . g
+                const float abar = c ? Tb * e : 0.f;
+                Ag = fmaf(al, e, Ag);
+                T = Tb;
+                const float f = shaped ? abar : 0.f;
+                // f G and f straight into their moment registers (the
+                // positions past the table overwrite the first and
+                // ignore the tenth), so neither needs a copy
+                acc[kSums * s + 0] = f * G;
+                acc[kSums * s + 9] = f;
+                const float fG = acc[kSums * s + 0];
+                acc[kSums * s + 6] = wgt * g0;
+                acc[kSums * s + 7] = wgt * g1;
+                acc[kSums * s + 8] = wgt * g2;
+                if (pos < (uint32_t)tab_cap) {
+                    // moments about the tile centre (wave-uniform branch)
+                    const float fGx = fG * cx, fGy = fG * cy;
+                    acc[kSums * s + 1] = fGx;
+                    acc[kSums * s + 2] = fGy;
+                    acc[kSums * s + 3] = fGx * cx;
+                    acc[kSums * s + 4] = fGx * cy;
+                    acc[kSums * s + 5] = fGy * cy;
+                } else {
+                    // the planes without their constant factors (plane_scale)
+                    const float P = fG * st.q.w;             // -dL/dp
+                    const float Pdx = P * dx, Pdy = P * dy;
+                    acc[kSums * s + 0] = P * fmaf(u, st.m.z, -w * st.q.y);
+                    acc[kSums * s + 1] = P * fmaf(u, st.m.w, w * st.q.x);
+                    acc[kSums * s + 2] = Pdx * dx;
+                    acc[kSums * s + 3] = Pdx * dy;
+                    acc[kSums * s + 4] = Pdy * dy;
+                    acc[kSums * s + 5] = fmaf(-g_min, f, fG);    // f (G - g_min)
+                    // acc[kSums * s + 9] is not stored for these
+                    // positions: the reduction sums each index on its own
                 }
+                slot_pos[s] = pos;
+                filled = s + 1;
             }
         }
         if (filled == 0) break;

@@ -375,15 +375,20 @@ __global__ __launch_bounds__(64) void k_emit(const float4 *__restrict__ rec,
 
 constexpr int kWaveItems = kItems * 64;
 
-// Lanes of the wave whose digit equals this lane's (valid lanes only).
+// Lanes of the wave whose digit equals this lane's (valid lanes only).  Per
+// bit, a lane keeps the lanes whose bit agrees with its own: with m all ones
+// where the bit is set, peers &= ~(ballot ^ m) on each 32-bit half, one
+// three-input bit operation (v_bitop3_b32) per half.
 __device__ inline uint64_t digit_peers(bool valid, uint32_t d, int nbits) {
-    uint64_t peers = __ballot(valid);
+    const uint64_t vb = __ballot(valid);
+    uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
     for (int b = 0; b < nbits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+        const uint32_t m = 0u - ((d >> b) & 1u);
+        const uint64_t bal = __ballot(m != 0u);
+        lo &= ~((uint32_t)bal ^ m);
+        hi &= ~((uint32_t)(bal >> 32) ^ m);
     }
-    return valid ? peers : 0ull;
+    return valid ? (((uint64_t)hi << 32) | lo) : 0ull;
 }
 
 // Per-block digit counts in LDS (atomics: cheaper here than grouping the lanes
@@ -703,6 +708,9 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         uint32_t cnt, nnz;
         uint32_t ex = wave_excl_scan(wsum, cnt);
         uint32_t rk = wave_excl_scan(nzc, nnz);
+        // wave-uniform: the round loop and its branches run on the scalar unit
+        cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)cnt);
+        nnz = (uint32_t)__builtin_amdgcn_readfirstlane((int)nnz);
         // Rows with pairs, compacted in order (rank rk): their first key,
         // Gaussian and first pair.  A chunk of at most kStartBits pairs also
         // marks each such row's first pair in a bitmap, so a pair's row is

@@ -103,15 +103,16 @@ struct TileArgs {
 // exact for any Gaussian near the quad, so the relative mean m' is rounded
 // once, and a pixel's offset is its place in the quad l (0..7 in x and y)
 // minus m'.
-// - The front-to-back sweep (kSweep) needs u and w only: with u0 = e' . m'
-//   and w0 = f x m' staged, u = e' . l - u0 and w = f x l - w0 cost two FMAs
-//   each and no offsets.
-// - The reverse pass also needs the offsets (conic gradient) and stages m',
-//   taken relative to the tile centre instead (the origin the per-tile sums
-//   of every quad share).
+// - With u0 = e' . m' and w0 = f x m' staged, u = e' . l - u0 and
+//   w = f x l - w0 cost two FMAs each and no offsets.
+// - The reverse pass stages the same form relative to the tile centre (the
+//   origin the per-tile sums of every quad share), with l the pixel centre
+//   from it.  The conic gradient of entries past the tile's sum table needs
+//   the offset d itself: d = M^-1 (u, w), M = [e'.x e'.y; -f.y f.x], whose
+//   determinant e' . f = k |e'|^2 the record gives; 1 / det is staged.
 struct Staged {
-    float4 m;   // kSweep: -u0, -w0, e'.x, e'.y;  else: m'.x, m'.y, e'.x, e'.y
-    float4 q;   // f.x, f.y, (unused), o' = o / (1 - g_min)
+    float4 m;   // -u0, -w0, e'.x, e'.y
+    float4 q;   // f.x, f.y, 1 / (e' . f) (reverse pass), o' = o / (1 - g_min)
     float4 c;   // r, g, b, o' * g_min
 };
 
@@ -130,14 +131,10 @@ __device__ inline void stage_record(const TileArgs &a, uint32_t id, float qx0, f
     const float ex = kHalfLog2eSqrt * q.x, ey = kHalfLog2eSqrt * q.y;
     const float fx = q.z * ex, fy = q.z * ey;
     const float mx = (m.x - qx0) + m.z, my = (m.y - qy0) + m.w;
-    if (kSweep) {
-        const float nu0 = -fmaf(ex, mx, ey * my);      // -(e' . m')
-        const float nw0 = -fmaf(fx, my, -fy * mx);     // -(f x m')
-        st.m = make_float4(nu0, nw0, ex, ey);
-    } else {
-        st.m = make_float4(mx, my, ex, ey);
-    }
-    st.q = make_float4(fx, fy, 0.f, op);
+    const float nu0 = -fmaf(ex, mx, ey * my);      // -(e' . m')
+    const float nw0 = -fmaf(fx, my, -fy * mx);     // -(f x m')
+    st.m = make_float4(nu0, nw0, ex, ey);
+    st.q = make_float4(fx, fy, kSweep ? 0.f : 1.f / fmaf(ex, fx, ey * fy), op);
     st.c = make_float4(c.x, c.y, c.z, op * a.g_min);
 }
 
@@ -162,27 +159,26 @@ __device__ inline bool stage_entry_bwd(const TileArgs &a, uint32_t id, float ox,
                                        float bx, float by, Staged &st) {
     float4 q;
     stage_record<false>(a, id, ox, oy, st, q);
-    const float x0 = bx - st.m.x, y0 = by - st.m.y;
+    const float4 m = a.rec[3 * (int64_t)id];
+    const float x0 = bx - ((m.x - ox) + m.z), y0 = by - ((m.y - oy) + m.w);
     float qxx, qxy, qyy;
     shape_conic(q.x, q.y, q.z, qxx, qxy, qyy);
     return box_hit(x0, x0 + 7.f, y0, y0 + 7.f, qxx, qxy, qyy, a.box_thr);
 }
 
-// Base-2 exponent p2 = (e' . d)^2 + (f x d)^2 of an entry staged for the
-// reverse pass, at offset (dx, dy); u = e' . d and w = f x d are returned for
-// the gradient.
-__device__ inline float exponent2(const Staged &st, float dx, float dy, float &u, float &w) {
-    u = fmaf(st.m.z, dx, st.m.w * dy);
-    w = fmaf(st.q.x, dy, -st.q.y * dx);
+// Base-2 exponent p2 = (e' . d)^2 + (f x d)^2 of a staged entry at the
+// pixel centre (lx, ly) from the staging origin; u = e' . d and w = f x d are
+// returned for the gradient.
+__device__ inline float exponent2(const Staged &st, float lx, float ly, float &u, float &w) {
+    u = fmaf(st.m.z, lx, fmaf(st.m.w, ly, st.m.x));
+    w = fmaf(st.q.x, ly, fmaf(-st.q.y, lx, st.m.y));
     return fmaf(u, u, w * w);
 }
 
-// The same for an entry staged for the front-to-back sweep, at the pixel's
-// place (lx, ly) in the quad.
+// The same without u and w (the front-to-back sweep).
 __device__ inline float exponent2_sweep(const Staged &st, float lx, float ly) {
-    const float u = fmaf(st.m.z, lx, fmaf(st.m.w, ly, st.m.x));
-    const float w = fmaf(st.q.x, ly, fmaf(-st.q.y, lx, st.m.y));
-    return fmaf(u, u, w * w);
+    float u, w;
+    return exponent2(st, lx, ly, u, w);
 }
 
 // Word of the visit mask of batch k of tile t inside one quad plane: tile t's
@@ -838,10 +834,8 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                 const Staged st = kRecompute ? read_staged_at(my_off + 48u * (uint32_t)b)
                                              : read_staged_at(staged_off(my_off, b));
                 const uint32_t pos = lo + (uint32_t)b;
-                const float dx = cx - st.m.x;
-                const float dy = cy - st.m.y;
                 float u, w;
-                const float G = __builtin_amdgcn_exp2f(-exponent2(st, dx, dy, u, w));
+                const float G = __builtin_amdgcn_exp2f(-exponent2(st, cx, cy, u, w));
                 const bool c = pos < nl && G > g_min;
                 const float araw = fmaf(st.q.w, G, -st.c.w);
                 const bool shaped = c && araw <= amax;       // alpha not clamped
@@ -873,7 +867,10 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
                     acc[kSums * s + 4] = fGx * cy;
                     acc[kSums * s + 5] = fGy * cy;
                 } else {
-                    // the planes without their constant factors (plane_scale)
+                    // the planes without their constant factors (plane_scale);
+                    // the offset d = M^-1 (u, w)
+                    const float dx = (st.q.x * u - st.m.w * w) * st.q.z;
+                    const float dy = fmaf(st.q.y, u, st.m.z * w) * st.q.z;
                     const float P = fG * st.q.w;             // -dL/dp
                     const float Pdx = P * dx, Pdy = P * dy;
                     acc[kSums * s + 0] = P * fmaf(u, st.m.z, -w * st.q.y);

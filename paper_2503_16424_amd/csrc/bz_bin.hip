@@ -68,14 +68,23 @@ __device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t *s_wave, uint64_
 }
 
 // Exclusive prefix over the wave of one value per lane; total in *tot.
+// Inclusive scan with DPP: within each 16-lane row by shifts of 1, 2, 4 and
+// 8 lanes (zeros shifted in), then row 0's total into row 1 and row 2's into
+// row 3 (row_bcast:15), then lane 31's (rows 0-1) into rows 2 and 3
+// (row_bcast:31); lanes a row mask leaves out add the old value 0.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ inline uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, BOUND);
+}
 __device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
     uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
-        if ((threadIdx.x & 63) >= d) x += y;
-    }
-    tot = (uint32_t)__shfl((int)x, 63, 64);
+    x += dpp_u32<0x111, 0xF, true>(x);     // row_shr:1
+    x += dpp_u32<0x112, 0xF, true>(x);     // row_shr:2
+    x += dpp_u32<0x114, 0xF, true>(x);     // row_shr:4
+    x += dpp_u32<0x118, 0xF, true>(x);     // row_shr:8
+    x += dpp_u32<0x142, 0xA, false>(x);    // row_bcast:15 into rows 1 and 3
+    x += dpp_u32<0x143, 0xC, false>(x);    // row_bcast:31 into rows 2 and 3
+    tot = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
     return x - v;
 }
 

@@ -486,10 +486,22 @@ __global__ __launch_bounds__(1024) void k_fwd(TileArgs a) {
     for_tiles(a, [&](int tile) { fwd_tile<kState, kCount, false>(a, tile, unused); });
 }
 
+// Sum over the wave's 64 lanes, wave-uniform: an inclusive DPP scan (row
+// shifts of 1, 2, 4, 8 lanes with zeros shifted in, then row_bcast 15 and 31
+// across rows), whose last lane holds the total.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ inline float dpp_f32(float x) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, BOUND));
+}
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    v += dpp_f32<0x111, 0xF, true>(v);
+    v += dpp_f32<0x112, 0xF, true>(v);
+    v += dpp_f32<0x114, 0xF, true>(v);
+    v += dpp_f32<0x118, 0xF, true>(v);
+    v += dpp_f32<0x142, 0xA, false>(v);
+    v += dpp_f32<0x143, 0xC, false>(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // The forward with the L2 loss gradient.  Every lane sums its squared errors

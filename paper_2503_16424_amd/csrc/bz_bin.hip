@@ -583,17 +583,6 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Wave minimum and maximum of one value per lane.
-__device__ inline uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, 64));
-    return v;
-}
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));
-    return v;
-}
 
 // Bucketed emission.  A bucket's pairs form one contiguous segment of the
 // packed array, emission block 0's first, then block 1's, ...: the scanned

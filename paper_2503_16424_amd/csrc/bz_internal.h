@@ -17,6 +17,29 @@ constexpr int kGradPlanes = 9;
 // Wave size of gfx950.
 constexpr int kWave = 64;
 
+// Wave minimum and maximum of one unsigned value per lane, wave-uniform: an
+// inclusive DPP scan (row shifts of 1, 2, 4 and 8 lanes, then row_bcast 15
+// and 31 across rows) with the operation's identity where a lane has no
+// source, read from the last lane.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_or_u32(uint32_t identity, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <bool kMax>
+__device__ inline uint32_t wave_extreme_u32(uint32_t v) {
+    const uint32_t id = kMax ? 0u : 0xffffffffu;
+    auto op = [](uint32_t a, uint32_t b) { return kMax ? (a > b ? a : b) : (a < b ? a : b); };
+    v = op(v, dpp_or_u32<0x111, 0xF>(id, v));
+    v = op(v, dpp_or_u32<0x112, 0xF>(id, v));
+    v = op(v, dpp_or_u32<0x114, 0xF>(id, v));
+    v = op(v, dpp_or_u32<0x118, 0xF>(id, v));
+    v = op(v, dpp_or_u32<0x142, 0xA>(id, v));
+    v = op(v, dpp_or_u32<0x143, 0xC>(id, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ inline uint32_t wave_min_u32(uint32_t v) { return wave_extreme_u32<false>(v); }
+__device__ inline uint32_t wave_max_u32(uint32_t v) { return wave_extreme_u32<true>(v); }
+
 // Quads: every wave owns one 8x8 block of pixels; tiles are made of quads.
 constexpr int kQuad = 8;
 

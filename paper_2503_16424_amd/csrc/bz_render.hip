@@ -755,10 +755,7 @@ __device__ inline void bwd_tile(const TileArgs &a, int tile) {
     // gradient only through A . g, so that scalar is what the pass carries:
     // A <- alpha c + (1 - alpha) A gives A.g <- alpha (c.g) + (1 - alpha) A.g.
     float Ag = fmaf(tg.bg0, g0, fmaf(tg.bg1, g1, tg.bg2 * g2));
-    uint32_t top = nl;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, d, 64));
-    top = (uint32_t)__builtin_amdgcn_readfirstlane((int)top);   // equal in all lanes
+    uint32_t top = wave_max_u32(nl);   // wave-uniform
     top = top < len ? top : len;
     if (lane == 0) s_top[w] = top;
     __syncthreads();

@@ -622,6 +622,8 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     __shared__ uint32_t s_item_key[kEmitWaves][kRowChunk];
     __shared__ uint8_t s_item_g[kEmitWaves][kRowChunk];
     __shared__ __align__(8) uint32_t s_start[kEmitWaves][kStartBits / 32];
+    __shared__ uint8_t s_nzg[kEmitWaves][kEmitG];        // Gaussians with rows, in order
+    __shared__ uint32_t s_gstart[kEmitWaves][kRowChunk / 32], s_gpref[kEmitWaves][kRowChunk / 32];
     __shared__ uint32_t s_base[kEmitWaves][256], s_cnt[kEmitWaves][256], s_run[kEmitWaves][256];
     if (status[1] & Status::kOverflow) return;
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -654,8 +656,16 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         }
     }
     uint32_t nrows;
-    s_rows[wv][t] = wave_excl_scan(my_rows, nrows);
+    const uint32_t row0 = wave_excl_scan(my_rows, nrows);   // this lane's first row item
+    s_rows[wv][t] = row0;
     if (t == 0) s_rows[wv][kEmitG] = nrows;
+    // the Gaussians with rows, compacted in order
+    const bool has_rows = my_rows != 0u;
+    const uint64_t nzm = __ballot(has_rows);
+    if (has_rows)
+        s_nzg[wv][__builtin_amdgcn_mbcnt_hi((uint32_t)(nzm >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)nzm, 0u))] =
+            (uint8_t)t;
     const uint32_t hl = wave_min_u32(hlo);
     if (hl == 0xffffffffu) return;                   // no pairs in this block
     const uint32_t span = wave_max_u32(my_rows ? hhi : 0u) - hl;   // buckets hl .. hl + span
@@ -677,22 +687,40 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     const int th_ = th;
     for (uint32_t c0 = 0; c0 < nrows; c0 += kRowChunk) {
         const uint32_t ci = nrows - c0 < (uint32_t)kRowChunk ? nrows - c0 : (uint32_t)kRowChunk;
+        // A row item's Gaussian: mark the first items of the Gaussians with
+        // rows that start in the chunk; the item's Gaussian is the
+        // (carry + marks at or before it)-th of them, carry the number that
+        // start before the chunk.
+        if (t < kRowChunk / 32) s_gstart[wv][t] = 0u;
+        wave_lds_fence();
+        if (has_rows && row0 >= c0 && row0 - c0 < (uint32_t)kRowChunk)
+            atomicOr(&s_gstart[wv][(row0 - c0) >> 5], 1u << ((row0 - c0) & 31));
+        const uint32_t carry = (uint32_t)__popcll(__ballot(has_rows && row0 < c0));
+        wave_lds_fence();
+        {
+            const uint32_t pc = t < kRowChunk / 32 ? (uint32_t)__popc(s_gstart[wv][t]) : 0u;
+            uint32_t tot_pc;
+            const uint32_t pref = wave_excl_scan(pc, tot_pc);
+            if (t < kRowChunk / 32) s_gpref[wv][t] = pref;
+        }
+        wave_lds_fence();
+        // this lane's kRowChunk / 64 items share one word of the marks
+        const uint32_t it0 = (uint32_t)t * (kRowChunk / 64);
+        const uint32_t mword = s_gstart[wv][it0 >> 5];
+        const uint32_t mbase = carry + s_gpref[wv][it0 >> 5] - 1u;
         uint32_t wsum = 0, nzc = 0;
         uint32_t wid[kRowChunk / 64], ikey[kRowChunk / 64], ig[kRowChunk / 64];
 #pragma unroll
         for (int j = 0; j < kRowChunk / 64; ++j) {
-            const uint32_t it = (uint32_t)t * (kRowChunk / 64) + j;
+            const uint32_t it = it0 + j;
             wid[j] = 0;
             ikey[j] = 0;
             ig[j] = 0;
             if (it < ci) {
                 const uint32_t r = c0 + it;
-                // last Gaussian whose first row <= r (lanes past nb hold
-                // nrows > r, so the search needs no bound)
-                int lo = 0;
-#pragma unroll
-                for (int step = kEmitG / 2; step >= 1; step >>= 1)
-                    if (s_rows[wv][lo + step] <= r) lo += step;
+                // the last Gaussian with rows whose first row <= r
+                const uint32_t upto = (2u << (it & 31)) - 1u;    // marks at or before it
+                const int lo = s_nzg[wv][mbase + (uint32_t)__popc(mword & upto)];
                 const int dr = (int)(r - s_rows[wv][lo]);
                 int cl, ch;
                 support_row(s_sup[wv][lo], (int)s_ty0[wv][lo] + dr, th_, inv_tw, cl, ch);

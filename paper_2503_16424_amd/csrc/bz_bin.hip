@@ -392,7 +392,7 @@ __device__ inline uint64_t digit_peers(bool valid, uint32_t d, int nbits) {
     const uint64_t vb = __ballot(valid);
     uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
     for (int b = 0; b < nbits; ++b) {
-        const uint32_t m = 0u - ((d >> b) & 1u);
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // bit b, sign-extended
         const uint64_t bal = __ballot(m != 0u);
         lo &= ~((uint32_t)bal ^ m);
         hi &= ~((uint32_t)(bal >> 32) ^ m);

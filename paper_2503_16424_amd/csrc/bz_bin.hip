@@ -781,16 +781,16 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
                 for (int step = kRowChunk / 2; step >= 1; step >>= 1)
                     if (s_item_off[wv][lo + step] <= i) lo += step;
             }
-            uint32_t key = 0, gl = 0;
-            if (valid) {
-                key = s_item_key[wv][lo] + (i - s_item_off[wv][lo]);
-                gl = s_item_g[wv][lo];
-            }
+            // lo is a row of the chunk for every lane (lanes past the last
+            // pair too), so the reads need no guard; those lanes' values are
+            // not used
+            const uint32_t key = s_item_key[wv][lo] + (i - s_item_off[wv][lo]);
+            const uint32_t gl = s_item_g[wv][lo];
             const uint32_t hr = valid ? (key >> 8) - hl : 0u;
             const uint64_t peers = digit_peers(valid, hr, nbits);
             // the wave's LDS accesses execute in order: this round reads the
             // counts the previous round's group leaders wrote
-            const uint32_t before = valid ? s_run[wv][hr] : 0u;
+            const uint32_t before = s_run[wv][hr];
             const uint32_t rank = before + (uint32_t)__popcll(peers & lt);
             if (valid && (peers & lt) == 0) s_run[wv][hr] = before + (uint32_t)__popcll(peers);
             if (valid && rank < s_cnt[wv][hr])

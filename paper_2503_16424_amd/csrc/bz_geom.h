@@ -181,15 +181,21 @@ __device__ inline void gauss_geom(const CurveView &v, const double2 *XA, const d
     int K = v.K;
     double t;
     column_param(k, K, v.S, g.seg, t);
+    // The stencils use at most the point, its row neighbours and one row
+    // neighbour: each is evaluated once (the same values as evaluating them
+    // per use).
     g.mu = sample_at(v, XA, XB, r, k);
+    const double2 Xl = k > 0 ? sample_at(v, XA, XB, r, k - 1) : g.mu;
+    const double2 Xr = k < K - 1 ? sample_at(v, XA, XB, r, k + 1) : g.mu;
     if (k < K - 1) { g.ka = k + 1; g.kb = k; } else { g.ka = K - 1; g.kb = K - 2; }
-    double2 A = sample_at(v, XA, XB, r, g.ka), B = sample_at(v, XA, XB, r, g.kb);
+    const double2 A = k < K - 1 ? Xr : g.mu, B = k < K - 1 ? g.mu : Xl;   // X[r][ka], X[r][kb]
     g.d_along = make_double2(A.x - B.x, A.y - B.y);
     g.sx2 = (g.d_along.x * g.d_along.x + g.d_along.y * g.d_along.y) * inv_rho2 + s0;
     if (v.kind == BZ_CLOSED) {
         int R1 = v.R + 1;
         if (r < R1) { g.ra = r + 1; g.rb = r; } else { g.ra = R1; g.rb = R1 - 1; }
-        double2 P = sample_at(v, XA, XB, g.ra, k), Q = sample_at(v, XA, XB, g.rb, k);
+        const double2 Y = sample_at(v, XA, XB, r < R1 ? r + 1 : r - 1, k);
+        const double2 P = r < R1 ? Y : g.mu, Q = r < R1 ? g.mu : Y;      // X[ra][k], X[rb][k]
         g.d_across = make_double2(P.x - Q.x, P.y - Q.y);
         g.sy2 = (g.d_across.x * g.d_across.x + g.d_across.y * g.d_across.y) * inv_rho2 + s0;
     } else {
@@ -200,7 +206,7 @@ __device__ inline void gauss_geom(const CurveView &v, const double2 *XA, const d
     }
     g.kp = k + 1 < K ? k + 1 : K - 1;
     g.km = k > 0 ? k - 1 : 0;
-    double2 Pp = sample_at(v, XA, XB, r, g.kp), Pm = sample_at(v, XA, XB, r, g.km);
+    const double2 Pp = k + 1 < K ? Xr : g.mu, Pm = k > 0 ? Xl : g.mu;   // X[r][kp], X[r][km]
     g.v = make_double2(Pp.x - Pm.x, Pp.y - Pm.y);
     const double nv2 = g.v.x * g.v.x + g.v.y * g.v.y;
     if (nv2 > 0.0) {

@@ -593,7 +593,9 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 // of the same record bits), and consecutive lanes on consecutive pairs of the
 // chunk (Gaussian-major, i.e. draw order), each finding its row by counting
 // the marked first pairs of the rows at or before it (a bitmap per chunk; a
-// binary search in chunks of more than kStartBits pairs).  A pair's place inside its bucket is the wave's running count of
+// binary search in chunks of more than kStartBits pairs); a row item finds
+// its Gaussian the same way from the Gaussians' first items.  A pair's place
+// inside its bucket is the wave's running count of
 // that bucket (LDS) plus the lanes of the round before it with the same
 // bucket, found with one ballot per bit of the bucket's index relative to the
 // block's first bucket (as the radix scatter ranks digits); so each bucket

@@ -7,9 +7,9 @@
 // quad (exact minimum of the quadratic form over the quad's pixel centres),
 // and writes the derived per-Gaussian constants into the wave's LDS slice.
 // A ballot of the test gives the batch's mask; the wave then iterates only
-// over the surviving entries, reading each one's constants as an LDS
-// broadcast, so pixels never spend ALU on Gaussians that cannot reach their
-// quad.  A wave stops when all 64 of its pixels have terminated.  (In the
+// over the surviving entries, every lane reading the entry's constants from
+// the same LDS address (three 16-byte reads), so pixels never spend ALU on
+// Gaussians that cannot reach their quad.  A wave stops when all 64 of its pixels have terminated.  (In the
 // backward the quads of a tile also share a sum table in LDS, so its waves
 // meet at the tile's start and end.)
 //

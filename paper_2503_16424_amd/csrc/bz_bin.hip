@@ -589,7 +589,7 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 // (bucket, block) counts, bucket-major, give each block its place.  One wave
 // per emission block of kEmitBlock (= kEmitG = 64) Gaussians (kEmitWaves per
 // workgroup).  The pairs are generated as in k_emit: (Gaussian, row) items,
-// kRowChunk at a time, each row's span by support_row (the count's function
+// kBkChunk at a time, each row's span by support_row (the count's function
 // of the same record bits), and consecutive lanes on consecutive pairs of the
 // chunk (Gaussian-major, i.e. draw order), each finding its row by counting
 // the marked first pairs of the rows at or before it (a bitmap per chunk; a
@@ -608,7 +608,10 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 // XCD w % 8): the parts meet in one L2.
 constexpr int kEmitWaves = 1;
 constexpr int kStartBits = 2048;   // pairs of a chunk whose rows a bitmap marks
+constexpr int kBkChunk = 128;   // row items per chunk
 
+// kMaxBk: at least the number of buckets (the LDS of a wave's bucket parts)
+template <int kMaxBk>
 __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     const float4 *__restrict__ rec, const ushort4 *__restrict__ rects, int64_t n, int W, int H,
     int tiles_x, float inv_tw, int th, float two_p, const bz_canvas *__restrict__ cv,
@@ -619,14 +622,15 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     __shared__ Support s_sup[kEmitWaves][kEmitG];
     __shared__ uint32_t s_key0[kEmitWaves][kEmitG];      // key of tile (first row, column 0)
     __shared__ uint16_t s_ty0[kEmitWaves][kEmitG];
-    __shared__ int s_tx[kEmitWaves][kEmitG];
-    __shared__ uint32_t s_item_off[kEmitWaves][kRowChunk + 1];
-    __shared__ uint32_t s_item_key[kEmitWaves][kRowChunk];
-    __shared__ uint8_t s_item_g[kEmitWaves][kRowChunk];
+    __shared__ uint16_t s_tx[kEmitWaves][kEmitG];
+    __shared__ uint32_t s_item_off[kEmitWaves][kBkChunk + 1];
+    __shared__ uint32_t s_item_key[kEmitWaves][kBkChunk];
+    __shared__ uint8_t s_item_g[kEmitWaves][kBkChunk];
     __shared__ __align__(8) uint32_t s_start[kEmitWaves][kStartBits / 32];
     __shared__ uint8_t s_nzg[kEmitWaves][kEmitG];        // Gaussians with rows, in order
-    __shared__ uint32_t s_gstart[kEmitWaves][kRowChunk / 32], s_gpref[kEmitWaves][kRowChunk / 32];
-    __shared__ uint32_t s_base[kEmitWaves][256], s_cnt[kEmitWaves][256], s_run[kEmitWaves][256];
+    __shared__ uint32_t s_gstart[kEmitWaves][kBkChunk / 32], s_gpref[kEmitWaves][kBkChunk / 32];
+    // a bucket's next position in this block's part, and the part's end
+    __shared__ uint32_t s_pos[kEmitWaves][kMaxBk], s_end[kEmitWaves][kMaxBk];
     if (status[1] & Status::kOverflow) return;
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t per = (n_eblk + 8 * kEmitWaves - 1) / (8 * kEmitWaves);   // workgroups per XCD
@@ -651,7 +655,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
             s_sup[wv][t] = sp;
             s_key0[wv][t] = tbase + (uint32_t)rc.y * (uint32_t)txc;
             s_ty0[wv][t] = rc.y;
-            s_tx[wv][t] = txc;
+            s_tx[wv][t] = (uint16_t)txc;
             // the keys of its pairs lie in [key(first row, rc.x), key(last row, rc.z)]
             hlo = (tbase + (uint32_t)rc.y * (uint32_t)txc + rc.x) >> 8;
             hhi = (tbase + (uint32_t)rc.w * (uint32_t)txc + rc.z) >> 8;
@@ -680,40 +684,39 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         for (uint32_t i = t; i <= span; i += 64) {
             const int64_t fi = (int64_t)(hl + i) * n_eblk + eb;
             const uint32_t a = bucket[fi];
-            s_base[wv][i] = a;
-            s_cnt[wv][i] = (fi + 1 < nflat ? bucket[fi + 1] : total) - a;
-            s_run[wv][i] = 0u;
+            s_pos[wv][i] = a;
+            s_end[wv][i] = fi + 1 < nflat ? bucket[fi + 1] : total;
         }
     };
     const uint64_t lt = (t == 0) ? 0ull : (~0ull >> (64 - t));
     const int th_ = th;
-    for (uint32_t c0 = 0; c0 < nrows; c0 += kRowChunk) {
-        const uint32_t ci = nrows - c0 < (uint32_t)kRowChunk ? nrows - c0 : (uint32_t)kRowChunk;
+    for (uint32_t c0 = 0; c0 < nrows; c0 += kBkChunk) {
+        const uint32_t ci = nrows - c0 < (uint32_t)kBkChunk ? nrows - c0 : (uint32_t)kBkChunk;
         // A row item's Gaussian: mark the first items of the Gaussians with
         // rows that start in the chunk; the item's Gaussian is the
         // (carry + marks at or before it)-th of them, carry the number that
         // start before the chunk.
-        if (t < kRowChunk / 32) s_gstart[wv][t] = 0u;
+        if (t < kBkChunk / 32) s_gstart[wv][t] = 0u;
         wave_lds_fence();
-        if (has_rows && row0 >= c0 && row0 - c0 < (uint32_t)kRowChunk)
+        if (has_rows && row0 >= c0 && row0 - c0 < (uint32_t)kBkChunk)
             atomicOr(&s_gstart[wv][(row0 - c0) >> 5], 1u << ((row0 - c0) & 31));
         const uint32_t carry = (uint32_t)__popcll(__ballot(has_rows && row0 < c0));
         wave_lds_fence();
         {
-            const uint32_t pc = t < kRowChunk / 32 ? (uint32_t)__popc(s_gstart[wv][t]) : 0u;
+            const uint32_t pc = t < kBkChunk / 32 ? (uint32_t)__popc(s_gstart[wv][t]) : 0u;
             uint32_t tot_pc;
             const uint32_t pref = wave_excl_scan(pc, tot_pc);
-            if (t < kRowChunk / 32) s_gpref[wv][t] = pref;
+            if (t < kBkChunk / 32) s_gpref[wv][t] = pref;
         }
         wave_lds_fence();
-        // this lane's kRowChunk / 64 items share one word of the marks
-        const uint32_t it0 = (uint32_t)t * (kRowChunk / 64);
+        // this lane's kBkChunk / 64 items share one word of the marks
+        const uint32_t it0 = (uint32_t)t * (kBkChunk / 64);
         const uint32_t mword = s_gstart[wv][it0 >> 5];
         const uint32_t mbase = carry + s_gpref[wv][it0 >> 5] - 1u;
         uint32_t wsum = 0, nzc = 0;
-        uint32_t wid[kRowChunk / 64], ikey[kRowChunk / 64], ig[kRowChunk / 64];
+        uint32_t wid[kBkChunk / 64], ikey[kBkChunk / 64], ig[kBkChunk / 64];
 #pragma unroll
-        for (int j = 0; j < kRowChunk / 64; ++j) {
+        for (int j = 0; j < kBkChunk / 64; ++j) {
             const uint32_t it = it0 + j;
             wid[j] = 0;
             ikey[j] = 0;
@@ -750,7 +753,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
             for (uint32_t q = t; q < nwords; q += 64) s_start[wv][q] = 0u;
         wave_lds_fence();
 #pragma unroll
-        for (int j = 0; j < kRowChunk / 64; ++j) {
+        for (int j = 0; j < kBkChunk / 64; ++j) {
             if (wid[j] != 0u) {
                 s_item_key[wv][rk] = ikey[j];
                 s_item_g[wv][rk] = (uint8_t)ig[j];
@@ -762,7 +765,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         }
         // the slots past the chunk's last row hold cnt (> every pair index),
         // so the pair search below needs no bound
-        for (uint32_t it = nnz + t; it <= (uint32_t)kRowChunk; it += 64) s_item_off[wv][it] = cnt;
+        for (uint32_t it = nnz + t; it <= (uint32_t)kBkChunk; it += 64) s_item_off[wv][it] = cnt;
         if (c0 == 0) fetch_parts();
         wave_lds_fence();
         // rounds of 64 consecutive pairs of the chunk, one per lane
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
                 seen += (uint32_t)__popcll(m);
             } else {
 #pragma unroll
-                for (int step = kRowChunk / 2; step >= 1; step >>= 1)
+                for (int step = kBkChunk / 2; step >= 1; step >>= 1)
                     if (s_item_off[wv][lo + step] <= i) lo += step;
             }
             // lo is a row of the chunk for every lane (lanes past the last
@@ -792,17 +795,17 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
             const uint64_t peers = digit_peers(valid, hr, nbits);
             // the wave's LDS accesses execute in order: this round reads the
             // counts the previous round's group leaders wrote
-            const uint32_t before = s_run[wv][hr];
-            const uint32_t rank = before + (uint32_t)__popcll(peers & lt);
-            if (valid && (peers & lt) == 0) s_run[wv][hr] = before + (uint32_t)__popcll(peers);
-            if (valid && rank < s_cnt[wv][hr])
-                packed[s_base[wv][hr] + rank] = ((key & 255u) << 24) | (uint32_t)(g0 + gl);
+            const uint32_t before = s_pos[wv][hr];
+            const uint32_t pos = before + (uint32_t)__popcll(peers & lt);
+            if (valid && (peers & lt) == 0) s_pos[wv][hr] = before + (uint32_t)__popcll(peers);
+            if (valid && pos < s_end[wv][hr])
+                packed[pos] = ((key & 255u) << 24) | (uint32_t)(g0 + gl);
         }
         wave_lds_fence();
     }
     // every bucket of the block filled exactly
     for (uint32_t i = t; i <= span; i += 64)
-        if (s_run[wv][i] != s_cnt[wv][i])
+        if (s_pos[wv][i] != s_end[wv][i])
             atomicOr((unsigned long long *)&status[1],
                      (unsigned long long)(Status::kOverflow | Status::kListMismatch));
 }
@@ -1152,8 +1155,9 @@ hipError_t bin_finish_fused(const float *rec, const BinBufs &u, int64_t n, const
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_segments, dim3(1), dim3(kBlk), 0, s, (const uint32_t *)u.bucket, nbk,
                        L.n_eblk, (const int64_t *)b.status, u.seg);
-    hipLaunchKernelGGL(k_emit_bucketed, dim3(8 * cdiv(L.n_eblk, 8 * kEmitWaves)),
-                       dim3(64 * kEmitWaves), 0, s,
+    // a smaller bucket table in LDS when it fits: more waves per CU
+    hipLaunchKernelGGL(nbk <= 64 ? k_emit_bucketed<64> : k_emit_bucketed<256>,
+                       dim3(8 * cdiv(L.n_eblk, 8 * kEmitWaves)), dim3(64 * kEmitWaves), 0, s,
                        (const float4 *)rec, (const ushort4 *)u.rects, n, o.width, o.height,
                        (int)tiles_x(o), 1.0f / o.tile_w, o.tile_h, support_two_p(o), cv, ncv,
                        (const uint32_t *)u.bucket, nbk, L.n_eblk, u.packed, b.status);

@@ -63,6 +63,13 @@ def test_bucketed_lists_equal_radix_lists(torch_cuda, tile):
     assert _same(torch_cuda, _odd_canvas(), tile) > 1000
 
 
+def test_bucketed_lists_equal_radix_lists_at_the_bucket_limit(torch_cuda):
+    # 256 x 256 tiles of 8 x 8: 65,536 tile keys, the builder's 256 buckets
+    _note("bucketed vs radix lists, 2048x2048, tile (8, 8), 256 buckets")
+    sc = scenes.mixed(8, 2048, 2048, 150, 300, K=24, R=8, S_open=3, extent=(4.0, 600.0))
+    assert _same(torch_cuda, sc, (8, 8)) > 10 ** 5
+
+
 def test_bucketed_lists_equal_radix_lists_at_paper_scale(torch_cuda):
     _note("bucketed vs radix lists, 2048x2048 20k curves")
     assert _same(torch_cuda, scenes.paper_2048(0)) > 10 ** 7

@@ -610,6 +610,35 @@ constexpr int kEmitWaves = 1;
 constexpr int kStartBits = 2048;   // pairs of a chunk whose rows a bitmap marks
 constexpr int kBkChunk = 128;   // row items per chunk
 
+// A support as the bucketed emission keeps it in LDS: the float row geometry
+// and the pixel box in 16 bits (a canvas side is at most 32768 pixels); r2
+// depends on the options alone and is recomputed as the support computes it.
+struct SupportLds {
+    float mx, my, a, D, isyy, dys;
+    uint16_t px0, px1, py0, py1;
+};
+
+__device__ inline SupportLds pack_support(const Support &s) {
+    return SupportLds{s.mx, s.my, s.a, s.D, s.isyy, s.dys, (uint16_t)s.px0, (uint16_t)s.px1,
+                      (uint16_t)s.py0, (uint16_t)s.py1};
+}
+
+__device__ inline Support unpack_support(const SupportLds &p, float r2) {
+    Support s;
+    s.mx = p.mx;
+    s.my = p.my;
+    s.a = p.a;
+    s.D = p.D;
+    s.isyy = p.isyy;
+    s.dys = p.dys;
+    s.r2 = r2;
+    s.px0 = p.px0;
+    s.px1 = p.px1;
+    s.py0 = p.py0;
+    s.py1 = p.py1;
+    return s;
+}
+
 // kMaxBk: at least the number of buckets (the LDS of a wave's bucket parts)
 template <int kMaxBk>
 __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
@@ -619,7 +648,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     uint32_t *__restrict__ packed, int64_t *status) {
     static_assert(kEmitBlock == kEmitG, "one emission block per wave");
     __shared__ uint32_t s_rows[kEmitWaves][kEmitG + 1];   // exclusive prefix of tile rows
-    __shared__ Support s_sup[kEmitWaves][kEmitG];
+    __shared__ SupportLds s_sup[kEmitWaves][kEmitG];
     __shared__ uint32_t s_key0[kEmitWaves][kEmitG];      // key of tile (first row, column 0)
     __shared__ uint16_t s_ty0[kEmitWaves][kEmitG];
     __shared__ uint16_t s_tx[kEmitWaves][kEmitG];
@@ -652,7 +681,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         if (rc.x <= rc.z && rc.y <= rc.w &&
             support_of(rec[3 * g], rec[3 * g + 1], Wc, Hc, two_p, sp, finite)) {
             my_rows = (uint32_t)(rc.w - rc.y + 1);
-            s_sup[wv][t] = sp;
+            s_sup[wv][t] = pack_support(sp);
             s_key0[wv][t] = tbase + (uint32_t)rc.y * (uint32_t)txc;
             s_ty0[wv][t] = rc.y;
             s_tx[wv][t] = (uint16_t)txc;
@@ -690,6 +719,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     };
     const uint64_t lt = (t == 0) ? 0ull : (~0ull >> (64 - t));
     const int th_ = th;
+    const float r2 = two_p * (kCullSlackBox * kCullSlackBox);   // as support_of sets it
     for (uint32_t c0 = 0; c0 < nrows; c0 += kBkChunk) {
         const uint32_t ci = nrows - c0 < (uint32_t)kBkChunk ? nrows - c0 : (uint32_t)kBkChunk;
         // A row item's Gaussian: mark the first items of the Gaussians with
@@ -728,7 +758,8 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
                 const int lo = s_nzg[wv][mbase + (uint32_t)__popc(mword & upto)];
                 const int dr = (int)(r - s_rows[wv][lo]);
                 int cl, ch;
-                support_row(s_sup[wv][lo], (int)s_ty0[wv][lo] + dr, th_, inv_tw, cl, ch);
+                support_row(unpack_support(s_sup[wv][lo], r2), (int)s_ty0[wv][lo] + dr, th_,
+                            inv_tw, cl, ch);
                 wid[j] = ch >= cl ? (uint32_t)(ch - cl + 1) : 0u;
                 ikey[j] = s_key0[wv][lo] + (uint32_t)dr * (uint32_t)s_tx[wv][lo] + (uint32_t)cl;
                 ig[j] = (uint32_t)lo;

@@ -578,9 +578,13 @@ __global__ void k_set_count(int64_t *status, int64_t n) {
 
 // --- bucketed path ----------------------------------------------------------
 
-__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+// Start of a bucketed binning with Gaussians: the status words and the
+// (bucket, emission block) counts cleared, in one launch (the in-bucket pass
+// writes every tile's range itself).
+__global__ void k_bucket_clear(int64_t *status, uint32_t *bucket, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (i < n) bucket[i] = 0u;
+    if (i < 2) status[i] = 0;
 }
 
 
@@ -1163,14 +1167,16 @@ float support_two_p(const bz_opts &o) { return 2.0f * (-logf(o.g_min)); }
 
 // Status and ranges cleared: before anything of the call writes a flag.  The
 // bucketed path's counts start at zero (they are added to).
-void bin_prepare(const BinBufs &u, const bz_bins &b, hipStream_t s) {
+void bin_prepare(const BinBufs &u, const bz_bins &b, int64_t n, hipStream_t s) {
+    if (u.L.fused && n > 0) {
+        const int64_t nf = u.L.n_buckets * u.L.n_eblk;
+        hipLaunchKernelGGL(k_bucket_clear, dim3(cdiv(nf > 2 ? nf : 2, 256)), dim3(256), 0, s,
+                           b.status, u.bucket, nf);
+        return;
+    }
     const int64_t nr = 2 * u.L.n_tiles;
     hipLaunchKernelGGL(k_bin_clear, dim3(cdiv(nr > 2 ? nr : 2, 256)), dim3(256), 0, s, b.status,
                        b.ranges, nr);
-    if (u.L.fused) {
-        const int64_t nf = u.L.n_buckets * u.L.n_eblk;
-        hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(nf, 256)), dim3(256), 0, s, u.bucket, nf, 0u);
-    }
 }
 
 // Bucketed path, after the counts per (bucket, emission block): positions,
@@ -1248,7 +1254,7 @@ hipError_t bin_finish(const float *rec, const BinBufs &u, int64_t n, const bz_op
 hipError_t launch_bin(const float *rec_f, int64_t n, const bz_opts &o, const bz_bins &b,
                       hipStream_t s) {
     const BinBufs u = bin_bufs(o, n, b);
-    bin_prepare(u, b, s);
+    bin_prepare(u, b, n, s);
     if (n == 0) return hipGetLastError();
     const bz_canvas *cv = o.batch ? o.batch->canvas : nullptr;
     const int ncv = o.batch ? o.batch->n_canvas : 0;
@@ -1263,7 +1269,7 @@ hipError_t launch_sample_bin(const bz_curves &c, const bz_opts &o, float *rec, c
                              hipStream_t s) {
     const int64_t n = c.n_gauss;
     const BinBufs u = bin_bufs(o, n, b);
-    bin_prepare(u, b, s);
+    bin_prepare(u, b, n, s);
     if (n == 0) return hipGetLastError();
     const BinCount bc = {u.counts, u.rects, b.status, 1.0f / o.tile_w, 1.0f / o.tile_h, o.tile_h,
                          support_two_p(o), u.bucket, u.L.n_eblk, (int)u.L.n_buckets,

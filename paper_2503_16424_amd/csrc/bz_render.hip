@@ -992,8 +992,8 @@ __global__ void k_zero(float *p, int64_t n) {
 // LDS sized for them, the others with kCurveThreads threads; each launch
 // skips the other's curves.  lk and lg are the K and Gaussian capacities the
 // dynamic LDS is laid out for.
-// Eight waves per SIMD (64 VGPRs, a few spills outside the per-Gaussian
-// loop): the stage waits on latency, and at seven it ran 5% slower.
+// Eight waves per SIMD (at most 64 VGPRs; 49 used): the stage waits on
+// latency, and at seven it ran 5% slower.
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_bwd_curves(bz_curves c, int lk, int lg, double inv_rho2,
                                                    double s0, const float *__restrict__ d_gauss,
@@ -1026,23 +1026,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     float2 *Tv = Th + lg;                                              // tangent term
     float2 *Xbar = Tm;                                                 // [rows*K]
     const bool closed = v.kind == BZ_CLOSED;
-    for (int k = lane; k < v.K; k += NT) {
-        int s;
-        double t, B[4];
-        column_param(k, v.K, v.S, s, t);
-        bernstein3(t, B);
-        Bw[k] = make_float4((float)B[0], (float)B[1], (float)B[2], (float)B[3]);
-        Bs[k] = s;
-        // samples k and k + 1 of each boundary in double precision; their
-        // differences rounded once
-        const double2 a0 = boundary_point(v, false, k);
-        const double2 a1 = k + 1 < v.K ? boundary_point(v, false, k + 1) : a0;
-        DA[k] = make_float2((float)(a1.x - a0.x), (float)(a1.y - a0.y));
-        if (closed) {
-            const double2 b0 = boundary_point(v, true, k);
-            const double2 b1 = k + 1 < v.K ? boundary_point(v, true, k + 1) : b0;
-            DB[k] = make_float2((float)(b1.x - b0.x), (float)(b1.y - b0.y));
-            Wd[k] = make_float2((float)(b0.x - a0.x), (float)(b0.y - a0.y));
+    // The boundary samples in double precision, one per thread, in the space
+    // of the terms (written only after the next barrier; 32 K <= 32 lg
+    // bytes), and each column's segment and Bernstein weights beside them;
+    // then the differences, rounded once.
+    {
+        double2 *P = reinterpret_cast<double2 *>(Tm);    // [A's K][B's K]
+        const int nb = closed ? 2 : 1;
+        for (int i = lane; i < (nb + 1) * v.K; i += NT) {
+            if (i < nb * v.K) {
+                const bool bb = i >= v.K;
+                P[i] = boundary_point(v, bb, bb ? i - v.K : i);
+            } else {
+                const int k = i - nb * v.K;
+                int s;
+                double t, B[4];
+                column_param(k, v.K, v.S, s, t);
+                bernstein3(t, B);
+                Bw[k] = make_float4((float)B[0], (float)B[1], (float)B[2], (float)B[3]);
+                Bs[k] = s;
+            }
+        }
+        __syncthreads();
+        for (int k = lane; k < v.K; k += NT) {
+            const double2 a0 = P[k], a1 = k + 1 < v.K ? P[k + 1] : a0;
+            DA[k] = make_float2((float)(a1.x - a0.x), (float)(a1.y - a0.y));
+            if (closed) {
+                const double2 b0 = P[v.K + k], b1 = k + 1 < v.K ? P[v.K + k + 1] : b0;
+                DB[k] = make_float2((float)(b1.x - b0.x), (float)(b1.y - b0.y));
+                Wd[k] = make_float2((float)(b0.x - a0.x), (float)(b0.y - a0.y));
+            }
         }
     }
     const int n = v.rows * v.K;

@@ -46,7 +46,10 @@ def curve_area(sc, opts=None) -> np.ndarray:
 
 
 def area_order(sc, opts=None):
-    a = curve_area(sc, opts).astype(np.float32)     # the key the library sorts by
+    # The order is an integer decision taken from the areas, so it is taken in
+    # the precision the kernels sort in: the FP64 areas rounded to float32,
+    # then a stable sort (equal keys keep curve index order).
+    a = curve_area(sc, opts).astype(np.float32)
     order = np.argsort(a, kind="stable")
     per = np.where(sc.kind == 1, sc.r_interior + 2, 1) * sc.k_samples
     goff = np.concatenate([[0], np.cumsum(per[order])]).astype(np.int64)

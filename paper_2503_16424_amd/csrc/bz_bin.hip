@@ -942,8 +942,7 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const uint32_t *__restrict_
                                                      const int64_t *status,
                                                      uint32_t *__restrict__ ids) {
     __shared__ uint32_t s_keys[kTile];
-    __shared__ uint32_t s_prefix[kRadix];
-    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_goff[kRadix];          // output position of a digit's slot 0
     __shared__ uint32_t s_wrun[kBlk / 64][kRadix];
     __shared__ uint64_t s_wave[kBlk / 64];
     __shared__ uint32_t s_S[kRadix + 1], s_P[kRadix + 1];
@@ -976,31 +975,34 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const uint32_t *__restrict_
     }
     __syncthreads();
     {
-        uint32_t tt = 0;
+        // digit tid: the block's count before it (prefix), then each wave's
+        // first slot in the block's order and the output position of slot 0
+        uint32_t c[kBlk / 64], tt = 0;
 #pragma unroll
         for (int q = 0; q < kBlk / 64; ++q) {
-            const uint32_t c = s_wrun[q][tid];
-            s_wrun[q][tid] = tt;
-            tt += c;
+            c[q] = s_wrun[q][tid];
+            tt += c[q];
         }
         uint64_t tot;
-        s_prefix[tid] = (uint32_t)block_excl_scan(tt, s_wave, tot);
-        s_gbase[tid] = hseg[sb.h0 + (int64_t)tid * sb.nbs];
+        const uint32_t prefix = (uint32_t)block_excl_scan(tt, s_wave, tot);
+        uint32_t r = prefix;
+#pragma unroll
+        for (int q = 0; q < kBlk / 64; ++q) {
+            s_wrun[q][tid] = r;
+            r += c[q];
+        }
+        s_goff[tid] = hseg[sb.h0 + (int64_t)tid * sb.nbs] - prefix;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int li = w * kWaveItems + j * 64 + lane;
-        if (li < cnt) {
-            const uint32_t d = key[j] >> 24;
-            s_keys[s_prefix[d] + run[d] + rank[j]] = key[j];
-        }
+        if (li < cnt) s_keys[run[key[j] >> 24] + rank[j]] = key[j];
     }
     __syncthreads();
     for (int i = tid; i < cnt; i += kBlk) {
         const uint32_t k = s_keys[i];
-        const uint32_t d = k >> 24;
-        ids[s_gbase[d] + (uint32_t)i - s_prefix[d]] = k & 0xffffffu;
+        ids[s_goff[k >> 24] + (uint32_t)i] = k & 0xffffffu;
     }
 }
 

@@ -181,16 +181,37 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, uint32_t
     __shared__ uint32_t s_v[kTile + kTile / 32];
     __shared__ uint64_t s_wave[kBlk / 64];
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    // the block's values and the partials before it are loaded kU at a time
+    // with no wait between the loads: one memory latency instead of one per
+    // partial a thread adds
+    uint32_t x[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t e = base + j * kBlk + threadIdx.x;
+        x[j] = e < n ? in[e] : 0u;
+    }
+    constexpr int kU = 8;
+    const int64_t nprev = blockIdx.x;
     uint64_t c = 0;
-    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kBlk) c += part[i];
+    int64_t i = threadIdx.x;
+    for (; i + (kU - 1) * kBlk < nprev; i += kU * kBlk) {
+        uint64_t p[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) p[u] = part[i + u * kBlk];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) c += p[u];
+    }
+    {
+        uint64_t p[kU - 1];
+#pragma unroll
+        for (int u = 0; u < kU - 1; ++u) p[u] = i + u * kBlk < nprev ? part[i + u * kBlk] : 0ull;
+#pragma unroll
+        for (int u = 0; u < kU - 1; ++u) c += p[u];
+    }
     uint64_t carry;
     block_excl_scan(c, s_wave, carry);
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        int li = j * kBlk + threadIdx.x;
-        int64_t e = base + li;
-        s_v[lds_pad(li)] = e < n ? in[e] : 0u;
-    }
+    for (int j = 0; j < kItems; ++j) s_v[lds_pad(j * kBlk + threadIdx.x)] = x[j];
     __syncthreads();
     uint32_t v[kItems];
     uint64_t s = 0;

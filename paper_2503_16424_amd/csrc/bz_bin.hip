@@ -601,10 +601,13 @@ __global__ void k_set_count(int64_t *status, int64_t n) {
 
 // Start of a bucketed binning with Gaussians: the status words and the
 // (bucket, emission block) counts cleared, in one launch (the in-bucket pass
-// writes every tile's range itself).
+// writes every tile's range itself).  16 bytes per thread (the table starts
+// on a 256-byte boundary), then the last n % 4 words.
 __global__ void k_bucket_clear(int64_t *status, uint32_t *bucket, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) bucket[i] = 0u;
+    const int64_t n4 = n >> 2;
+    if (i < n4) reinterpret_cast<uint4 *>(bucket)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < (n & 3)) bucket[4 * n4 + i] = 0u;
     if (i < 2) status[i] = 0;
 }
 
@@ -1192,9 +1195,9 @@ float support_two_p(const bz_opts &o) { return 2.0f * (-logf(o.g_min)); }
 // bucketed path's counts start at zero (they are added to).
 void bin_prepare(const BinBufs &u, const bz_bins &b, int64_t n, hipStream_t s) {
     if (u.L.fused && n > 0) {
-        const int64_t nf = u.L.n_buckets * u.L.n_eblk;
-        hipLaunchKernelGGL(k_bucket_clear, dim3(cdiv(nf > 2 ? nf : 2, 256)), dim3(256), 0, s,
-                           b.status, u.bucket, nf);
+        const int64_t nf = u.L.n_buckets * u.L.n_eblk, nt = (nf >> 2) > 3 ? (nf >> 2) : 3;
+        hipLaunchKernelGGL(k_bucket_clear, dim3(cdiv(nt, 256)), dim3(256), 0, s, b.status,
+                           u.bucket, nf);
         return;
     }
     const int64_t nr = 2 * u.L.n_tiles;

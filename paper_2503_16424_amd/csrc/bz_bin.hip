@@ -667,13 +667,47 @@ __device__ inline Support unpack_support(const SupportLds &p, float r2) {
     return s;
 }
 
+// Segment table of the in-bucket pass, written by one wave (the first of the
+// emission, which runs after the counts' scan and before the pass):
+// seg[s] = first position of bucket s, seg[nbk + 1 + s] = its first radix
+// block (ceil(len / kTile) blocks per bucket), entry nbk of each = the end.
+// Lane l takes buckets 4 l .. 4 l + 3 (nbk <= 256).
+__device__ inline void segment_table(const uint32_t *__restrict__ bucket, int nbk,
+                                     int64_t n_eblk, uint32_t total, int lane,
+                                     uint32_t *__restrict__ seg) {
+    uint32_t S[4], nb[4], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = 4 * lane + i;
+        S[i] = t < nbk ? bucket[(int64_t)t * n_eblk] : total;
+        const uint32_t S1 = t + 1 < nbk ? bucket[(int64_t)(t + 1) * n_eblk] : total;
+        nb[i] = t < nbk ? (S1 - S[i] + kTile - 1) / kTile : 0u;
+        sum += nb[i];
+    }
+    uint32_t tot;
+    uint32_t P = wave_excl_scan(sum, tot);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = 4 * lane + i;
+        if (t <= nbk) {
+            seg[t] = S[i];
+            seg[nbk + 1 + t] = P;
+        }
+        P += nb[i];
+    }
+    if (nbk == 4 * 64 && lane == 63) {
+        seg[nbk] = total;
+        seg[2 * nbk + 1] = P;
+    }
+}
+
 // kMaxBk: at least the number of buckets (the LDS of a wave's bucket parts)
 template <int kMaxBk>
 __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     const float4 *__restrict__ rec, const ushort4 *__restrict__ rects, int64_t n, int W, int H,
     int tiles_x, float inv_tw, int th, float two_p, const bz_canvas *__restrict__ cv,
     int n_canvas, const uint32_t *__restrict__ bucket, int nbk, int64_t n_eblk,
-    uint32_t *__restrict__ packed, int64_t *status) {
+    uint32_t *__restrict__ packed, uint32_t *__restrict__ seg, int64_t *status) {
     static_assert(kEmitBlock == kEmitG, "one emission block per wave");
     __shared__ uint32_t s_rows[kEmitWaves][kEmitG + 1];   // exclusive prefix of tile rows
     __shared__ SupportLds s_sup[kEmitWaves][kEmitG];
@@ -690,6 +724,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     __shared__ uint32_t s_pos[kEmitWaves][kMaxBk], s_end[kEmitWaves][kMaxBk];
     if (status[1] & Status::kOverflow) return;
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && wv == 0) segment_table(bucket, nbk, n_eblk, (uint32_t)status[0], t, seg);
     const int64_t per = (n_eblk + 8 * kEmitWaves - 1) / (8 * kEmitWaves);   // workgroups per XCD
     const int64_t eb = ((int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3)) * kEmitWaves + wv;
     if (eb >= n_eblk) return;                        // whole wave
@@ -867,31 +902,6 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         if (s_pos[wv][i] != s_end[wv][i])
             atomicOr((unsigned long long *)&status[1],
                      (unsigned long long)(Status::kOverflow | Status::kListMismatch));
-}
-
-// Segment table of the in-bucket pass: seg[s] = first position of bucket s,
-// seg[nbk + 1 + s] = its first radix block (ceil(len / kTile) blocks per
-// bucket), entry nbk of each = the end.  One workgroup of kBlk threads.
-__global__ __launch_bounds__(256) void k_segments(const uint32_t *__restrict__ bucket, int nbk,
-                                                  int64_t n_eblk, const int64_t *status,
-                                                  uint32_t *__restrict__ seg) {
-    __shared__ uint64_t s_wave[kBlk / 64];
-    if (status[1] & Status::kOverflow) return;
-    const int t = threadIdx.x;
-    const uint32_t total = (uint32_t)status[0];
-    const uint32_t S = t < nbk ? bucket[(int64_t)t * n_eblk] : total;
-    const uint32_t S1 = t + 1 < nbk ? bucket[(int64_t)(t + 1) * n_eblk] : total;
-    const uint32_t nb = t < nbk ? (S1 - S + kTile - 1) / kTile : 0u;
-    uint64_t tot;
-    const uint32_t P = (uint32_t)block_excl_scan(nb, s_wave, tot);
-    if (t <= nbk) {
-        seg[t] = S;
-        seg[nbk + 1 + t] = P;
-    }
-    if (nbk == kBlk && t == kBlk - 1) {
-        seg[nbk] = total;
-        seg[2 * nbk + 1] = P + nb;
-    }
 }
 
 // Segment of radix block b (b < P[nbk]): the last s with P[s] <= b (buckets
@@ -1216,14 +1226,12 @@ hipError_t bin_finish_fused(const float *rec, const BinBufs &u, int64_t n, const
     hipError_t e = scan_u32(u.bucket, u.bucket, L.n_buckets * L.n_eblk, u.part, b.status,
                             b.cap_pairs, b.status, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_segments, dim3(1), dim3(kBlk), 0, s, (const uint32_t *)u.bucket, nbk,
-                       L.n_eblk, (const int64_t *)b.status, u.seg);
     // a smaller bucket table in LDS when it fits: more waves per CU
     hipLaunchKernelGGL(nbk <= 64 ? k_emit_bucketed<64> : k_emit_bucketed<256>,
                        dim3(8 * cdiv(L.n_eblk, 8 * kEmitWaves)), dim3(64 * kEmitWaves), 0, s,
                        (const float4 *)rec, (const ushort4 *)u.rects, n, o.width, o.height,
                        (int)tiles_x(o), 1.0f / o.tile_w, o.tile_h, support_two_p(o), cv, ncv,
-                       (const uint32_t *)u.bucket, nbk, L.n_eblk, u.packed, b.status);
+                       (const uint32_t *)u.bucket, nbk, L.n_eblk, u.packed, u.seg, b.status);
     hipLaunchKernelGGL(k_seg_hist, dim3(L.seg_blocks), dim3(kBlk), 0, s,
                        (const uint32_t *)u.packed, (const uint32_t *)u.seg, nbk,
                        (const int64_t *)b.status, u.hseg);

@@ -623,12 +623,13 @@ __global__ void k_bucket_clear(int64_t *status, uint32_t *bucket, int64_t n) {
 // the marked first pairs of the rows at or before it (a bitmap per chunk; a
 // binary search in chunks of more than kStartBits pairs); a row item finds
 // its Gaussian the same way from the Gaussians' first items.  A pair's place
-// inside its bucket is the wave's running count of
-// that bucket (LDS) plus the lanes of the round before it with the same
-// bucket, found with one ballot per bit of the bucket's index relative to the
-// block's first bucket (as the radix scatter ranks digits); so each bucket
-// keeps draw order, and a row whose keys straddle two buckets needs nothing
-// special.  A pair is packed as (key & 255) << 24 | Gaussian.  Every bucket's
+// is its bucket's running position in the block's part (LDS) plus the lanes
+// of the round before it with the same bucket, found with one ballot per bit
+// of the bucket's index relative to the block's first bucket (as the radix
+// scatter ranks digits); so each bucket keeps draw order, and a row whose
+// keys straddle two buckets needs nothing special.  LDS per wave is what
+// limits the waves a CU holds, so the supports are kept as 32 bytes and the
+// bucket arrays are sized for the buckets there are (64 or 256).  A pair is packed as (key & 255) << 24 | Gaussian.  Every bucket's
 // total must equal the count's; otherwise the lists are marked invalid (never
 // expected), and no lane writes outside the block's part of a bucket.
 // Neighbouring blocks' parts of a bucket are neighbours in memory, so blocks

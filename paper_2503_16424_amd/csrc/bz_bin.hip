@@ -715,14 +715,14 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
     __shared__ uint32_t s_key0[kEmitWaves][kEmitG];      // key of tile (first row, column 0)
     __shared__ uint16_t s_ty0[kEmitWaves][kEmitG];
     __shared__ uint16_t s_tx[kEmitWaves][kEmitG];
-    __shared__ uint32_t s_item_off[kEmitWaves][kBkChunk + 1];
-    __shared__ uint32_t s_item_key[kEmitWaves][kBkChunk];
-    __shared__ uint8_t s_item_g[kEmitWaves][kBkChunk];
+    // rows with pairs: (first pair in the chunk, first key | Gaussian << 16),
+    // one 8-byte read for a pair's row (keys are below 2^16 on this path)
+    __shared__ uint2 s_item[kEmitWaves][kBkChunk + 1];
     __shared__ __align__(8) uint32_t s_start[kEmitWaves][kStartBits / 32];
     __shared__ uint8_t s_nzg[kEmitWaves][kEmitG];        // Gaussians with rows, in order
     __shared__ uint32_t s_gstart[kEmitWaves][kBkChunk / 32], s_gpref[kEmitWaves][kBkChunk / 32];
     // a bucket's next position in this block's part, and the part's end
-    __shared__ uint32_t s_pos[kEmitWaves][kMaxBk], s_end[kEmitWaves][kMaxBk];
+    __shared__ uint2 s_pe[kEmitWaves][kMaxBk];   // (pos, end), one 8-byte read
     if (status[1] & Status::kOverflow) return;
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (blockIdx.x == 0 && wv == 0) segment_table(bucket, nbk, n_eblk, (uint32_t)status[0], t, seg);
@@ -777,8 +777,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         for (uint32_t i = t; i <= span; i += 64) {
             const int64_t fi = (int64_t)(hl + i) * n_eblk + eb;
             const uint32_t a = bucket[fi];
-            s_pos[wv][i] = a;
-            s_end[wv][i] = fi + 1 < nflat ? bucket[fi + 1] : total;
+            s_pe[wv][i] = make_uint2(a, fi + 1 < nflat ? bucket[fi + 1] : total);
         }
     };
     const uint64_t lt = (t == 0) ? 0ull : (~0ull >> (64 - t));
@@ -850,9 +849,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
 #pragma unroll
         for (int j = 0; j < kBkChunk / 64; ++j) {
             if (wid[j] != 0u) {
-                s_item_key[wv][rk] = ikey[j];
-                s_item_g[wv][rk] = (uint8_t)ig[j];
-                s_item_off[wv][rk] = ex;
+                s_item[wv][rk] = make_uint2(ex, ikey[j] | (ig[j] << 16));
                 if (use_bits) atomicOr(&s_start[wv][ex >> 5], 1u << (ex & 31));
                 ++rk;
             }
@@ -860,7 +857,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
         }
         // the slots past the chunk's last row hold cnt (> every pair index),
         // so the pair search below needs no bound
-        for (uint32_t it = nnz + t; it <= (uint32_t)kBkChunk; it += 64) s_item_off[wv][it] = cnt;
+        for (uint32_t it = nnz + t; it <= (uint32_t)kBkChunk; it += 64) s_item[wv][it].x = cnt;
         if (c0 == 0) fetch_parts();
         wave_lds_fence();
         // rounds of 64 consecutive pairs of the chunk, one per lane
@@ -879,28 +876,30 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit_bucketed(
             } else {
 #pragma unroll
                 for (int step = kBkChunk / 2; step >= 1; step >>= 1)
-                    if (s_item_off[wv][lo + step] <= i) lo += step;
+                    if (s_item[wv][lo + step].x <= i) lo += step;
             }
             // lo is a row of the chunk for every lane (lanes past the last
             // pair too), so the reads need no guard; those lanes' values are
             // not used
-            const uint32_t key = s_item_key[wv][lo] + (i - s_item_off[wv][lo]);
-            const uint32_t gl = s_item_g[wv][lo];
+            const uint2 item = s_item[wv][lo];
+            const uint32_t key = (item.y & 0xffffu) + (i - item.x);
+            const uint32_t gl = item.y >> 16;
             const uint32_t hr = valid ? (key >> 8) - hl : 0u;
             const uint64_t peers = digit_peers(valid, hr, nbits);
             // the wave's LDS accesses execute in order: this round reads the
             // counts the previous round's group leaders wrote
-            const uint32_t before = s_pos[wv][hr];
+            const uint2 pe = s_pe[wv][hr];
+            const uint32_t before = pe.x;
             const uint32_t pos = before + (uint32_t)__popcll(peers & lt);
-            if (valid && (peers & lt) == 0) s_pos[wv][hr] = before + (uint32_t)__popcll(peers);
-            if (valid && pos < s_end[wv][hr])
+            if (valid && (peers & lt) == 0) s_pe[wv][hr].x = before + (uint32_t)__popcll(peers);
+            if (valid && pos < pe.y)
                 packed[pos] = ((key & 255u) << 24) | (uint32_t)(g0 + gl);
         }
         wave_lds_fence();
     }
     // every bucket of the block filled exactly
     for (uint32_t i = t; i <= span; i += 64)
-        if (s_pos[wv][i] != s_end[wv][i])
+        if (s_pe[wv][i].x != s_pe[wv][i].y)
             atomicOr((unsigned long long *)&status[1],
                      (unsigned long long)(Status::kOverflow | Status::kListMismatch));
 }

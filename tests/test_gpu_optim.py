@@ -226,8 +226,9 @@ def test_fit_checkpoint_resume_matches_uninterrupted_run(torch_cuda, tmp_path):
     """60 optimiser steps straight against 30 steps, a checkpoint (.npz of the
     parameters, the optimiser's momentum buffers and the generator states), a
     fresh rasterizer and 30 resumed steps: the same parameters, up to the
-    run-to-run spread of the backward's float atomics (measured here with a
-    second straight run).  Momentum SGD keeps that spread at the rounding
+    run-to-run spread of the backward's float atomics (measured here as the
+    largest difference among three straight runs: one pair alone can land
+    well below the spread a third run shows).  Momentum SGD keeps that spread at the rounding
     level (Adam's normalisation amplifies it chaotically; its moments' round
     trip is checked bit for bit on the host)."""
     torch = torch_cuda
@@ -246,7 +247,7 @@ def test_fit_checkpoint_resume_matches_uninterrupted_run(torch_cuda, tmp_path):
 
     start = params(bz.Rasterizer(sc))
     straight = []
-    for _ in range(2):
+    for _ in range(3):
         r = bz.Rasterizer(sc)
         fit(r, clean, cfg)
         straight.append(params(r))
@@ -258,7 +259,8 @@ def test_fit_checkpoint_resume_matches_uninterrupted_run(torch_cuda, tmp_path):
     fit(r2, clean, cfg, resume_from=path)
     resumed = params(r2)
     moved = float(np.abs(straight[0] - mid).max())
-    spread = float(np.abs(straight[1] - straight[0]).max())
+    spread = max(float(np.abs(straight[i] - straight[j]).max())
+                 for i in range(3) for j in range(i + 1, 3))
     err = float(np.abs(resumed - straight[0]).max())
     _note(f"  resumed vs straight {err:.2e}, straight vs straight {spread:.2e}, "
           f"second half moved {moved:.2e}, whole run {float(np.abs(straight[0] - start).max()):.2e}")
